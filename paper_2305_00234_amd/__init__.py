@@ -1,0 +1,11 @@
+"""MI355X-native CCPR-FDTD forward / adjoint / gradient library.
+
+The compute path lives in the HIP/C++ shared library built from csrc/ (its
+C-ABI is declared in include/ccprfdtd.h).  This package holds the thin ctypes
+binding (``lib``), the density -> objective autograd function (``autograd``),
+the serving driver (``serve``) and the seeded synthetic inputs (``inputs``).
+Importing the package does not load the GPU library; ``lib.load()`` does, and
+fails loudly when it has not been built.
+"""
+
+__all__ = ["inputs", "lib", "solver", "autograd", "serve"]
