@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark: one step = one whole forward + adjoint + gradient solve of the
+paper-shaped gap problem (320^3 cells, 12-cell CPML, 160x160x80 design of
+Table-1 gold with 3 CCPR pole pairs, TF/SF plane wave, 6000 leapfrog steps,
+DFT |E|^2 over a 4^3 gap, time-exact gradient), inputs resident in HBM.
+
+Prints one JSON line.  value = cell-updates of the forward and adjoint runs
+(cells x 2 x 6000 per solve) per second, in millions.  The roofline object is
+for the fused step kernel: algorithmic bytes per launch over
+its average launch duration, timed with HIP events on the library's stream
+inside the timed region.  The CPU baseline is the FP64 oracle on a bounded
+sample of the same workload (a few forward + adjoint steps on the full grid).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-updates/s fwd+adjoint (% HBM roofline) vs plain; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload_by_name(name, solve_steps=None):
+    from paper_2305_00234_amd import inputs as I
+    table = {
+        "gold_gap_320": lambda m: I.gold_gap_320(steps=m or 6000),
+        "drude_dipole_32": lambda m: I.drude_dipole_32(steps=m or 400),
+        "gold_gap_td_512x512x256": lambda m: I.gold_gap_timedomain_512(steps=m or 8000),
+        "aniso_two_material_384": lambda m: I.aniso_two_material_384(steps=m or 8000),
+    }
+    return table[name](solve_steps)
+
+
+def algorithmic_bytes(w):
+    """Bytes per fused step launch, averaged over the forward and adjoint
+    launches (one forward launch and one adjoint launch move these on
+    average): 48 B/cell for E,H read+write; per design voxel 16 B per pole pair
+    and component (J read+write) + 4 B density; 32 B per (cell, CPML axis)
+    for the psi memories; forward gradient record 12 B/voxel, adjoint
+    correlation 12 B read + 16 B FP64 accumulator read/write per voxel."""
+    nx, ny, nz = w.shape
+    N = nx * ny * nz
+    nd = int(np.prod(w.design_dims))
+    pairs = sum(w.mat1[a].npairs + w.mat2[a].npairs for a in range(3))
+    p = w.npml
+    pml_axis_cells = 0
+    if p:
+        pml_axis_cells = 2 * p * (ny * nz + nx * nz + nx * ny)
+    per_launch = 48 * N + (16 * pairs + 4) * nd + 32 * pml_axis_cells
+    record = (12 * nd + (12 + 16) * nd) / 2.0
+    return per_launch + record
+
+
+def traffic_from_profile(kernel_src_hash):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_hbm_traffic_gold_gap_320.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha256") != kernel_src_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def kernel_hash():
+    src = os.path.join(ROOT, "paper_2305_00234_amd", "csrc", "ccpr_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()
+
+
+def cpu_baseline(w, sample_steps):
+    """FP64 oracle, as it stands, on the full grid of the same workload for
+    sample_steps forward + sample_steps adjoint steps."""
+    from oracle import build as obuild
+    from oracle.oracle import OBJ_DFT, OBJ_TIME, num_threads
+    if not os.path.exists(obuild.LIB):
+        obuild.build()
+    from tests.oracle_setup import oracle_from_workload
+    o = oracle_from_workload(w)
+    kind = OBJ_DFT if w.objective == "dft" else OBJ_TIME
+    t0 = time.perf_counter()
+    o.gradient(sample_steps, kind, w.gap_lo, w.gap_dims, w.omega, w.window[0], sample_steps + 1)
+    dt = time.perf_counter() - t0
+    o.close()
+    upd = w.cells * 2 * sample_steps
+    return {"value": upd / dt / 1e6, "unit": "Mcell-updates/s", "cores": num_threads(),
+            "kind": "oracle",
+            "sample": f"{w.name}: full {w.shape[0]}x{w.shape[1]}x{w.shape[2]} grid, "
+                      f"{sample_steps} forward + {sample_steps} adjoint FP64 steps incl. "
+                      f"objective and gradient ({dt:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gold_gap_320")
+    ap.add_argument("--solve-steps", type=int, default=None,
+                    help="leapfrog steps per solve (default: the workload's)")
+    ap.add_argument("--tile-planes", type=int, default=None)
+    ap.add_argument("--cpu-sample-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "layout is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2305_00234_amd.solver import solver_for
+
+    w = workload_by_name(args.workload, args.solve_steps)
+    M = w.steps
+    s = solver_for(w)
+    if args.tile_planes:
+        s.set_tile_planes(args.tile_planes)
+    d = w.design_dims
+    grad = torch.empty((d[2], d[1], d[0]), dtype=torch.float64, device="cuda")
+
+    def one_solve():
+        F = s.forward(M)
+        s.adjoint()
+        s.gradient(out=grad)
+        return F
+
+    for _ in range(args.warmup):
+        one_solve()
+    torch.cuda.synchronize()
+
+    s.set_timing(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = None
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        F = one_solve()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    step_ms, launches = s.timing()
+    s.set_timing(False)
+    info = s.info()
+
+    ms_per_step = total / args.steps * 1e3
+    updates = w.cells * 2 * M
+    value = updates / (total / args.steps) / 1e6
+    avg_launch_s = step_ms / 1e3 / max(launches, 1)
+    alg = algorithmic_bytes(w)
+    achieved = alg / avg_launch_s / 1e9
+    traffic = traffic_from_profile(kernel_hash())
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cells": w.cells, "grid": list(w.shape),
+                   "leapfrog_steps_per_solve": M, "design": list(w.design_dims),
+                   "pole_pairs_per_axis": w.max_pairs(), "cpml": w.npml,
+                   "source": w.source, "objective": w.objective,
+                   "gradient": "time-exact",
+                   "history_segments": info["segments"], "tile_planes": info["tile_planes"]},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 2)},
+        "objective": F,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "ccpr_step_kernel",
+                     "alg_bytes_per_launch": int(alg),
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": launches},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,225 @@
+/*
+ * ccprfdtd.h -- C-ABI of the MI355X (gfx950) CCPR-FDTD forward / adjoint /
+ * gradient library.
+ *
+ * The library solves the density-based inverse-design problem of Gedeon,
+ * Hassan and Cala Lesina, "Free-form inverse design of arbitrary dispersive
+ * materials in nanophotonics":
+ *   maximise F[E] over rho in [0,1], subject to Maxwell's equations with the
+ *   complex-conjugate pole-residue (CCPR) model (Eq. CCPRModel), the density
+ *   interpolation of Eqs. eps_mixed, sigma_mixed, Poles_mixed, and a diagonal
+ *   permittivity tensor (Sec. "Time-domain adjoint formulation");
+ * by a 3-D Yee FDTD forward run, a time-reversed adjoint run that is the same
+ * solver with another source (supplement Eqs. Tranformations, AdjointSystem),
+ * and the design gradient accumulated from forward/adjoint field correlations
+ * (Eq. Gradient_FDTD, in the exact discrete index pairing).
+ *
+ * Conventions
+ *  - Units are SI at this interface (m, s, V/m, A/m, A/m^2, S/m, rad/s).
+ *    Field scaling used inside the library is private.
+ *  - Grid: cells i in [0,nx), j in [0,ny), k in [0,nz); x fastest in every
+ *    array.  Ex[k][j][i] sits at ((i+1/2)dx, j dx, k dx), Ey at
+ *    (i dx, (j+1/2)dx, k dx), Ez at (i dx, j dx, (k+1/2)dx), Hx at
+ *    (i dx, (j+1/2)dx, (k+1/2)dx), Hy at ((i+1/2)dx, j dx, (k+1/2)dx), Hz at
+ *    ((i+1/2)dx, (j+1/2)dx, k dx).  Perfect electric walls bound the domain
+ *    (behind the CPML when one is requested).
+ *  - Design voxel (i,j,k) carries one density that drives the three E edges
+ *    stored at [k][j][i]; the gradient is one value per voxel.
+ *  - Ownership: every pointer argument is caller-owned.  Host buffers are
+ *    consumed before the call returns.  Device buffers (mem == CCPR_MEM_DEVICE)
+ *    are read or written by work enqueued on the bound stream and must stay
+ *    valid until that work completes.  The workspace is borrowed, never freed.
+ *  - Errors: every call returns a ccpr_status; no exception crosses the ABI.
+ *    ccpr_last_error() describes the last failure of that solver.
+ *  - Threading: one host thread per solver at a time.  Solvers are
+ *    independent; several may share a device and a stream.
+ */
+#ifndef CCPRFDTD_H
+#define CCPRFDTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CCPR_OK = 0,
+    CCPR_EINVAL = -1,    /* bad shape, enum, NaN or out-of-range density      */
+    CCPR_ECFL = -2,      /* Courant number above 1/sqrt(3)                     */
+    CCPR_ENOMEM = -3,    /* workspace too small                                */
+    CCPR_EDEVICE = -4,   /* HIP runtime error                                  */
+    CCPR_ESTATE = -5,    /* call out of order (e.g. adjoint before forward)    */
+    CCPR_EDIVERGED = -6, /* non-finite or exploding fields                     */
+    CCPR_ENOTSUP = -7    /* valid request outside what this build supports     */
+} ccpr_status;
+
+enum { CCPR_MEM_HOST = 0, CCPR_MEM_DEVICE = 1 };
+enum { CCPR_OBJ_TIME_E2 = 0, CCPR_OBJ_DFT_E2 = 1 };
+enum { CCPR_EX = 0, CCPR_EY, CCPR_EZ, CCPR_HX, CCPR_HY, CCPR_HZ };
+
+#define CCPR_MAX_PAIRS_PER_AXIS 8 /* pole pairs over both materials, per axis */
+#define CCPR_MAX_NX 1024          /* x extent handled by one workgroup row    */
+
+typedef struct ccpr_solver ccpr_solver;
+
+/* Grid and absorbing boundary.  dt = courant * dx / c0; courant must be in
+ * (0, 1/sqrt(3)].  npml cells of CFS-CPML line every wall (0 = bare PEC).
+ * Grading (Methods, "Technical details": only the thickness is given; these
+ * are the standard polynomial CFS-CPML parameters):
+ *   xi = depth/npml, sigma = sigma_scale*0.8*(m+1)/(eta0*dx) * xi^m,
+ *   kappa = 1 + (kappa_max-1) xi^m, alpha = alpha_max (1-xi). */
+typedef struct {
+    int nx, ny, nz;
+    double dx;
+    double courant;
+    int npml;
+    double pml_order;       /* m, typically 3                    */
+    double pml_kappa_max;   /* typically 1                       */
+    double pml_alpha_max;   /* S/m, typically 0.05               */
+    double pml_sigma_scale; /* typically 1                       */
+} ccpr_grid;
+
+/* Create a solver (host state only; no device work until a workspace is
+ * bound).  Validates the grid: CCPR_EINVAL for non-positive sizes or a CPML
+ * thicker than half the grid, CCPR_ECFL for courant > 1/sqrt(3), CCPR_ENOTSUP
+ * for nx > CCPR_MAX_NX.  *out receives the handle (NULL on error). */
+ccpr_status ccpr_create(const ccpr_grid* g, ccpr_solver** out);
+
+/* Destroy a solver.  Does not free the bound workspace (caller-owned).
+ * Waits for the solver's outstanding stream work. */
+void ccpr_destroy(ccpr_solver* s);
+
+/* Text of the last error of this solver ("" if none).  Valid until the next
+ * call on the same solver.  s may be NULL (returns the last creation error). */
+const char* ccpr_last_error(const ccpr_solver* s);
+
+/* CCPR coefficients of one material for one field axis (Eq. CCPRModel;
+ * diagonal anisotropy by per-axis calls, Sec. "Time-domain adjoint
+ * formulation").  slot 1 is the material at rho = 0, slot 2 at rho = 1
+ * (Eqs. eps_mixed, sigma_mixed, Poles_mixed).  a, c: npairs complex numbers as
+ * (re, im) doubles [1/s].  Unset slots are vacuum (eps_inf 1, no poles).
+ * CCPR_EINVAL for axis/slot out of range, npairs < 0, or non-finite values;
+ * CCPR_ENOTSUP if the two slots together exceed CCPR_MAX_PAIRS_PER_AXIS on an
+ * axis. */
+ccpr_status ccpr_set_material(ccpr_solver* s, int slot, int axis, double eps_inf,
+                              double sigma, int npairs, const double* a, const double* c);
+
+/* Design box [lo, lo+dims) with one density per voxel (float, x fastest,
+ * dims[0]*dims[1]*dims[2] values) and the conductivity damping gamma [S/m] of
+ * Eq. sigma_mixed.  The box must lie inside the grid and outside the CPML.
+ * Densities must be finite and within [0,1] (checked for host input; for
+ * device input the check runs on the device and is reported by the next
+ * ccpr_forward / ccpr_step).  mem = CCPR_MEM_DEVICE requires a bound
+ * workspace: the copy is enqueued on the bound stream.  Outside the box the
+ * medium is vacuum. */
+ccpr_status ccpr_set_design(ccpr_solver* s, const int lo[3], const int dims[3], double gamma,
+                            const float* rho, int mem);
+
+/* Point current source (host data): J_src [A/m^2] on the 'axis' edge of
+ * 'cell', wave[n] being its value at t = (n+1/2) dt for n in [0,nsteps); zero
+ * afterwards.  Replaces any previous source. */
+ccpr_status ccpr_set_source_dipole(ccpr_solver* s, const int cell[3], int axis,
+                                   const double* wave, int nsteps);
+
+/* Axis-aligned plane wave by total-field/scattered-field (host data),
+ * travelling along sign * prop_axis with E along pol_axis (Sec. "Topology
+ * Optimization Setup": the excitation is a polarised plane wave).  The total
+ * field box spans cell corners [lo, hi] (inclusive), strictly inside the grid
+ * and outside the CPML.  wave[n] is the incident E [V/m] at the launch point of
+ * an exact 1-D auxiliary line at t = n dt, n in [0,nsteps).  Replaces any
+ * previous source. */
+ccpr_status ccpr_set_source_planewave(ccpr_solver* s, int prop_axis, int sign, int pol_axis,
+                                      const int lo[3], const int hi[3], const double* wave,
+                                      int nsteps);
+
+/* Objective over the gap box [lo, lo+dims) using all three E edges of each gap
+ * cell:
+ *   CCPR_OBJ_TIME_E2: F = eps0/2 dx^3 dt sum_{n in [n_begin,n_end)} sum E^2
+ *                     (Eq. 2, rectangle rule, air in the gap);
+ *   CCPR_OBJ_DFT_E2:  F = sum |dt sum_{n=0..M} E^n exp(-j omega n dt)|^2.
+ * n_end < 0 means "through the last step". */
+ccpr_status ccpr_set_objective(ccpr_solver* s, int kind, const int lo[3], const int dims[3],
+                               double omega, int n_begin, int n_end);
+
+/* Forward-history checkpointing for the time-exact gradient.  The forward run
+ * stores one gradient factor (3 floats) per design voxel and step; when the
+ * full history does not fit, the run is split into segments of
+ * checkpoint_every steps that are recomputed from state checkpoints during the
+ * adjoint.  0 = the smallest segment count that fits the bound workspace.
+ * Results are bit-identical for every segment size. */
+ccpr_status ccpr_set_checkpointing(ccpr_solver* s, int checkpoint_every);
+
+/* Device bytes needed for a forward + adjoint + gradient solve of nsteps
+ * (nsteps = 0: field stepping only) with the current configuration and
+ * checkpoint_every (0: full history).  Drives admission in serving. */
+ccpr_status ccpr_workspace_size(const ccpr_solver* s, int nsteps, uint64_t* bytes);
+
+/* Borrow a device buffer of 'bytes' (256-byte aligned) as workspace and bind a
+ * HIP stream (hipStream_t, may be NULL for the null stream).  The library
+ * never allocates device memory itself.  Rebinding resets the solver. */
+ccpr_status ccpr_bind_workspace(ccpr_solver* s, void* dev_ptr, uint64_t bytes, void* hip_stream);
+
+/* Forward run of nsteps from zero fields, recording the gap monitor and the
+ * gradient history, then the objective (synchronises the stream to return
+ * *objective_out, which may be NULL). */
+ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out);
+
+/* Adjoint run (same update, zero initial fields, time-reversed source
+ * (1/dt) dF/dE at the gap edges, no incident wave) with the gradient
+ * correlation; recomputes checkpointed segments as needed.  Stream-ordered.
+ * CCPR_ESTATE before a successful ccpr_forward. */
+ccpr_status ccpr_adjoint(ccpr_solver* s);
+
+/* dF/drho per design voxel (FP64: in SI units the objective of a weak source
+ * is far below the FP32 range), dims of the design box, x fastest, written to
+ * host memory (synchronises) or device memory (stream-ordered).  Eq.
+ * Gradient_FDTD in the exact discrete pairing:
+ *   dF/drho_v = sum_k sum_{n=0}^{M-1} Et_k^{M-n}(v) T_k^{n+1/2}(v),
+ *   T = eps0 deps_k (E^{n+1}-E^n) + dsig_k,eff dt (E^{n+1}+E^n)/2
+ *       + dt sum_p dkappa_p Re{J_p^{n+1}+J_p^n},
+ * Et^m the adjoint E after m adjoint steps, dsig_eff = sig2-sig1+(1-2 rho) gamma.
+ * CCPR_ESTATE before ccpr_adjoint. */
+ccpr_status ccpr_gradient(ccpr_solver* s, double* grad, int mem);
+
+/* Zero the fields and the step counter (forward source active). */
+ccpr_status ccpr_reset(ccpr_solver* s);
+
+/* Advance n leapfrog steps with the configured forward source and no
+ * recording. */
+ccpr_status ccpr_step(ccpr_solver* s, int n);
+
+/* Copy one field component (comp = CCPR_EX..CCPR_HZ, SI units) of the current
+ * state -- the forward state after ccpr_step/ccpr_forward, the adjoint state
+ * after ccpr_adjoint -- into nz*ny*nx floats (host: synchronises; device:
+ * stream-ordered). */
+ccpr_status ccpr_get_field(ccpr_solver* s, int comp, float* out, int mem);
+
+/* Number of leapfrog steps taken since the last reset (forward state). */
+int ccpr_step_count(const ccpr_solver* s);
+
+/* ---- diagnostics ------------------------------------------------------- */
+
+/* Enable (1) or disable (0) stream-event timing of the fused step-kernel
+ * loops of ccpr_forward and ccpr_adjoint, and clear the counters.  Timing
+ * synchronises the stream at the end of each loop. */
+ccpr_status ccpr_set_timing(ccpr_solver* s, int enable);
+
+/* Accumulated event time [ms] of the timed step-kernel loops and the number of
+ * step-kernel launches they contain (their ratio is the average launch
+ * duration, loop gaps included). */
+ccpr_status ccpr_get_timing(const ccpr_solver* s, double* step_ms_total, long long* step_launches);
+
+/* Segment count and length of the last ccpr_forward layout, and the number of
+ * z-planes one workgroup of the step kernel marches over.  Any pointer may be
+ * NULL. */
+ccpr_status ccpr_get_info(const ccpr_solver* s, int* segments, int* segment_steps, int* tile_planes);
+
+/* Launch shape: z-planes per workgroup of the step kernel (default 16).
+ * Results do not depend on it. */
+ccpr_status ccpr_set_tile_planes(ccpr_solver* s, int planes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

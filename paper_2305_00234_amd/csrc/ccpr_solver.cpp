@@ -1,0 +1,1000 @@
+// Host runtime of the CCPR-FDTD library: the C-ABI of include/ccprfdtd.h.
+//
+// Responsibilities: argument validation, FP64 precompute of the scaled
+// material / CPML constants, carving the caller's workspace, ordering the
+// kernel launches of the forward run, the adjoint run with segment
+// checkpoint/recompute, and the gradient read-out.  Every arithmetic step of
+// the path itself runs in the gfx950 kernels of ccpr_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ccprfdtd.h"
+#include "ccpr_internal.h"
+
+namespace {
+
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kMu0 = 1.25663706212e-6;
+constexpr double kC0 = 299792458.0;
+
+typedef std::complex<double> cd;
+
+struct MatHost {
+    double eps = 1.0, sig = 0.0;
+    std::vector<cd> a, c;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    // fixed part
+    size_t Eb[2][2], Hb[2][2];   // [state][parity] -> 3*ncell floats
+    size_t Jb[2];                // [state]
+    size_t psiE[2];              // [state] all three slabs
+    size_t psiH[2][2];           // [state][parity]
+    size_t ssh[2];               // [state] FP64 shadow of E on source edges
+    size_t rho, pmlE, pmlH, scal, gradacc, work;
+    size_t fixed_end;
+    // variable part
+    size_t src_fwd, src_adj, wave, lineE, lineH, incE, incH, gap, T, ckpt, stage;
+    size_t total;
+    int K = 0, S = 1;            // segment length / count
+    size_t ckpt_bytes = 0;
+    int inc_steps = 0, line_L = 0;
+};
+
+}  // namespace
+
+struct ccpr_solver {
+    ccpr_grid g{};
+    double dt = 0;
+    long long ncell = 0;
+    std::string err;
+    MatHost mat[2][3];
+    // design
+    bool has_design = false;
+    int dlo[3]{}, ddim[3]{};
+    long long nd = 0;
+    double gamma = 0;
+    std::vector<float> rho_host;
+    bool rho_on_host = false, rho_uploaded = false;
+    // source
+    int src_kind = 0;  // 0 none, 1 dipole, 2 plane wave
+    int dip_cell[3]{}, dip_axis = 0;
+    int pw_d = 2, pw_sgn = 1, pw_p = 0, pw_lo[3]{}, pw_hi[3]{};
+    std::vector<double> wave;
+    double alpha = 1.0;  // forward source scale
+    // objective
+    bool has_obj = false;
+    int obj_kind = 1, glo[3]{}, gdim[3]{}, gncell = 0, nb = 0, ne = -1;
+    double omega = 0;
+    int ckpt_every = 0;
+    // workspace
+    char* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    int maxpairs = 0, npairs_total = 0;
+    int tz = 16;
+    // run state
+    int parity[2] = {0, 0};
+    int step_count = 0;
+    int src_table_steps = -1;   // steps covered by the uploaded forward source table
+    Layout lay{};
+    bool have_forward = false, have_adjoint = false;
+    int M = 0;
+    double F = 0, adj_alpha = 1.0, grad_scale = 0;
+    int current_state = 0;  // 0 forward, 1 adjoint (for get_field)
+    AxisMat mats[3]{};
+    long long fixed_key[4] = {-1, -1, -1, -1};
+    // diagnostics
+    double stat_ms = 0;
+    long long stat_launches = 0;
+    bool timing = false;
+};
+
+namespace {
+
+std::string g_create_err;
+
+ccpr_status fail(ccpr_solver* s, ccpr_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (s) s->err = buf;
+    else g_create_err = buf;
+    return st;
+}
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (hipError_t)(x);                                                   \
+        if (e_ != hipSuccess) return fail(s, CCPR_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+long long psi_total(const ccpr_solver* s)
+{
+    if (s->g.npml <= 0) return 0;
+    long long t = 0;
+    for (int a = 0; a < 3; ++a) t += slab_size(a, s->g.nx, s->g.ny, s->g.nz, s->g.npml);
+    return t;
+}
+
+int pairs_on_axis(const ccpr_solver* s, int ax)
+{
+    return (int)(s->mat[0][ax].a.size() + s->mat[1][ax].a.size());
+}
+
+void recount_pairs(ccpr_solver* s)
+{
+    s->maxpairs = 0;
+    s->npairs_total = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        s->maxpairs = std::max(s->maxpairs, pairs_on_axis(s, ax));
+        s->npairs_total += pairs_on_axis(s, ax);
+    }
+}
+
+int plane_span(const ccpr_solver* s) { return s->pw_hi[s->pw_d] - s->pw_lo[s->pw_d] + 1; }
+
+// Workspace layout for a solve of M steps (M = 0: stepping only).
+Layout make_layout(const ccpr_solver* s, int M, int K_req)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    const size_t nc = (size_t)s->ncell;
+    const size_t nd = (size_t)std::max<long long>(s->nd, 1);
+    const size_t psi = (size_t)psi_total(s);
+    for (int st = 0; st < 2; ++st) {
+        for (int p = 0; p < 2; ++p) L.Eb[st][p] = take(3 * nc * 4);
+        for (int p = 0; p < 2; ++p) L.Hb[st][p] = take(3 * nc * 4);
+        L.Jb[st] = take(2 * (size_t)std::max(s->npairs_total, 1) * nd * 4);
+        L.psiE[st] = take(std::max<size_t>(psi, 1) * 4);
+        for (int p = 0; p < 2; ++p) L.psiH[st][p] = take(std::max<size_t>(psi, 1) * 4);
+        L.ssh[st] = take((size_t)std::max(s->gncell, 1) * 3 * 8);
+    }
+    L.rho = take(nd * 4);
+    L.pmlE = take((size_t)(s->g.nx + s->g.ny + s->g.nz) * 16);
+    L.pmlH = take((size_t)(s->g.nx + s->g.ny + s->g.nz) * 16);
+    L.scal = take(16 * 8);
+    L.gradacc = take(nd * 8);
+    L.work = take((size_t)std::max(s->gncell * 3, 1) * 16);
+    L.fixed_end = o;
+    // forward source tables cover the solve (or the waveform when stepping)
+    const int nw = (int)s->wave.size();
+    const int steps = M > 0 ? M : std::max(nw, 1);
+    L.inc_steps = steps;
+    L.src_fwd = take((size_t)steps * 3 * 4);
+    if (s->src_kind == 2) {
+        const int span = plane_span(s);
+        L.line_L = span + 16 + steps / 2 + 16;
+        L.wave = take((size_t)std::max(nw, 1) * 8);
+        L.lineE = take((size_t)(L.line_L + 1) * 8);
+        L.lineH = take((size_t)(L.line_L + 1) * 8);
+        L.incE = take((size_t)(steps + 1) * span * 4);
+        L.incH = take((size_t)(steps + 1) * (span + 1) * 4);
+    }
+    if (M > 0) {
+        L.src_adj = take((size_t)M * std::max(s->gncell, 1) * 3 * 4);
+        L.gap = take((size_t)(M + 1) * std::max(s->gncell, 1) * 3 * 4);
+        int K = K_req > 0 ? std::min(K_req, M) : M;
+        L.K = K;
+        L.S = (M + K - 1) / K;
+        L.T = take((size_t)K * 3 * nd * 4);
+        L.ckpt_bytes = (6 * nc + 2 * (size_t)std::max(s->npairs_total, 1) * nd + 2 * psi) * 4 + 8 * 3 * 8;
+        L.ckpt = take((size_t)(L.S - 1) * align256(L.ckpt_bytes));
+    }
+    L.stage = take(std::max(nc * 4, nd * 8));
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+T* wsp(ccpr_solver* s, size_t off) { return reinterpret_cast<T*>(s->ws + off); }
+
+ccpr_status need_bound(ccpr_solver* s)
+{
+    if (!s->ws) return fail(s, CCPR_ESTATE, "no workspace bound");
+    return CCPR_OK;
+}
+
+// Scaled material constants of one axis (FP64 -> FP32 kernel constants).
+void axis_mat(const ccpr_solver* s, int ax, int jofs, AxisMat& m)
+{
+    const MatHost& m1 = s->mat[0][ax];
+    const MatHost& m2 = s->mat[1][ax];
+    const double dt = s->dt, h = dt / (2 * kEps0);
+    m.eps1 = (float)m1.eps;
+    m.deps = (float)(m2.eps - m1.eps);
+    m.sig1 = (float)(m1.sig * h);
+    m.dsig = (float)((m2.sig - m1.sig) * h);
+    m.gam = (float)(s->gamma * h);
+    m.np1 = (int)m1.a.size();
+    m.np = (int)(m1.a.size() + m2.a.size());
+    m.jofs = jofs;
+    int q = 0;
+    for (int slot = 0; slot < 2; ++slot) {
+        const MatHost& mm = slot == 0 ? m1 : m2;
+        for (size_t p = 0; p < mm.a.size(); ++p, ++q) {
+            const cd a = mm.a[p], c = mm.c[p];
+            const cd den = 1.0 - a * dt / 2.0;
+            const cd km1 = a * dt / den;  // k_p - 1, free of cancellation
+            const cd b = c * dt / den;
+            m.kr[q] = (float)km1.real();
+            m.ki[q] = (float)km1.imag();
+            m.br[q] = (float)b.real();
+            m.bi[q] = (float)b.imag();
+        }
+    }
+    for (; q < CCPR_PMAX; ++q) m.kr[q] = m.ki[q] = m.br[q] = m.bi[q] = 0.f;
+}
+
+// CPML coefficient (b, a, 1/kappa) at position pos (cell units) along an axis
+// of N cells.
+void pml_point(const ccpr_solver* s, int N, double pos, float* out)
+{
+    const int np = s->g.npml;
+    double xi = 0;
+    if (np > 0) {
+        double d = std::max(std::max(np - pos, pos - (N - np)), 0.0);
+        xi = std::min(d, (double)np) / np;
+    }
+    const double eta0 = std::sqrt(kMu0 / kEps0);
+    const double m = s->g.pml_order;
+    const double smax = s->g.pml_sigma_scale * 0.8 * (m + 1) / (eta0 * s->g.dx);
+    const double sig = smax * std::pow(xi, m);
+    const double kap = 1 + (s->g.pml_kappa_max - 1) * std::pow(xi, m);
+    const double al = s->g.pml_alpha_max * (1 - xi);
+    const double b = std::exp(-(sig / kap + al) * s->dt / kEps0);
+    const double a = sig > 0 ? sig * (b - 1) / (sig * kap + kap * kap * al) : 0.0;
+    out[0] = (float)b;
+    out[1] = (float)a;
+    out[2] = (float)(1.0 / kap);
+    out[3] = 0.f;
+}
+
+ccpr_status upload_static(ccpr_solver* s)
+{
+    const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
+    std::vector<float> e, h;
+    for (int ax = 0; ax < 3; ++ax)
+        for (int q = 0; q < n3[ax]; ++q) {
+            float v[4];
+            pml_point(s, n3[ax], q, v);
+            e.insert(e.end(), v, v + 4);
+            pml_point(s, n3[ax], q + 0.5, v);
+            h.insert(h.end(), v, v + 4);
+        }
+    HIPCHK(hipMemcpyAsync(s->ws + s->lay.pmlE, e.data(), e.size() * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->ws + s->lay.pmlH, h.data(), h.size() * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CCPR_OK;
+}
+
+ccpr_status upload_rho(ccpr_solver* s)
+{
+    if (!s->ws || !s->has_design || !s->rho_on_host || s->rho_uploaded) return CCPR_OK;
+    HIPCHK(hipMemcpyAsync(s->ws + s->lay.rho, s->rho_host.data(), s->rho_host.size() * 4,
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->rho_uploaded = true;
+    return CCPR_OK;
+}
+
+ccpr_status zero_state(ccpr_solver* s, int st)
+{
+    const Layout& L = s->lay;
+    const long long psi = psi_total(s);
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Eb[st][0]), 3 * s->ncell, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Eb[st][1]), 3 * s->ncell, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Hb[st][0]), 3 * s->ncell, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Hb[st][1]), 3 * s->ncell, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Jb[st]), 2LL * s->npairs_total * std::max(s->nd, 1LL), 0.f,
+                            s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.psiE[st]), psi, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.psiH[st][0]), psi, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.psiH[st][1]), psi, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.ssh[st]), (long long)std::max(s->gncell, 1) * 3, 0.0, s->stream));
+    s->parity[st] = 0;
+    return CCPR_OK;
+}
+
+// Forward source tables (scaled by alpha) for 'steps' steps.
+ccpr_status prepare_source(ccpr_solver* s, int steps)
+{
+    const Layout& L = s->lay;
+    const int nw = (int)s->wave.size();
+    double mx = 0;
+    for (double v : s->wave) mx = std::max(mx, std::fabs(v));
+    if (!(mx > 0)) mx = 1.0;
+    if (s->src_kind == 1) {
+        s->alpha = kEps0 / (s->dt * mx);
+        std::vector<float> t((size_t)steps * 3, 0.f);
+        for (int n = 0; n < steps && n < nw; ++n) t[(size_t)n * 3 + s->dip_axis] = (float)(s->wave[n] / mx);
+        HIPCHK(hipMemcpyAsync(s->ws + L.src_fwd, t.data(), t.size() * 4, hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    } else if (s->src_kind == 2) {
+        s->alpha = 1.0 / mx;
+        std::vector<double> w(nw);
+        for (int n = 0; n < nw; ++n) w[n] = s->wave[n] / mx;
+        HIPCHK(hipMemcpyAsync(s->ws + L.wave, w.data(), w.size() * 8, hipMemcpyHostToDevice, s->stream));
+        const int d = s->pw_d, p = s->pw_p, t = 3 - d - p;
+        auto levi = [](int a, int b, int c) {
+            return ((a == 0 && b == 1 && c == 2) || (a == 1 && b == 2 && c == 0) || (a == 2 && b == 0 && c == 1)) ? 1 : -1;
+        };
+        const double coef = levi(p, d, t) * s->pw_sgn * s->g.courant;
+        const int ref = s->pw_sgn > 0 ? s->pw_lo[d] - 2 : s->pw_hi[d] + 2;
+        HIPCHK(ccpr_launch_incident_line(wsp<double>(s, L.wave), nw, steps, L.line_L, coef, s->pw_lo[d],
+                                         s->pw_hi[d], s->pw_sgn, ref, wsp<double>(s, L.lineE),
+                                         wsp<double>(s, L.lineH), wsp<float>(s, L.incE),
+                                         wsp<float>(s, L.incH), s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    s->src_table_steps = steps;
+    return CCPR_OK;
+}
+
+int sigma_ca(int c, int a) { return a == (c + 1) % 3 ? 1 : -1; }
+
+StepArgs base_args(ccpr_solver* s, int st)
+{
+    const Layout& L = s->lay;
+    StepArgs A{};
+    A.nx = s->g.nx; A.ny = s->g.ny; A.nz = s->g.nz;
+    A.plane = (long long)s->g.nx * s->g.ny;
+    A.S = (float)s->g.courant;
+    const int par = s->parity[st];
+    for (int c = 0; c < 3; ++c) {
+        A.Ei[c] = wsp<float>(s, L.Eb[st][par]) + c * s->ncell;
+        A.Eo[c] = wsp<float>(s, L.Eb[st][par ^ 1]) + c * s->ncell;
+        A.Hi[c] = wsp<float>(s, L.Hb[st][par]) + c * s->ncell;
+        A.Ho[c] = wsp<float>(s, L.Hb[st][par ^ 1]) + c * s->ncell;
+    }
+    if (s->has_design) {
+        for (int a = 0; a < 3; ++a) { A.dlo[a] = s->dlo[a]; A.ddim[a] = s->ddim[a]; }
+        A.nd = s->nd;
+        A.rho = wsp<float>(s, L.rho);
+        A.J = wsp<float>(s, L.Jb[st]);
+        for (int ax = 0; ax < 3; ++ax) A.mat[ax] = s->mats[ax];
+    }
+    A.npml = s->g.npml;
+    if (s->g.npml > 0) {
+        const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
+        size_t offc = 0, offs = 0;
+        for (int a = 0; a < 3; ++a) {
+            A.pmlE[a] = wsp<float4>(s, L.pmlE) + offc;
+            A.pmlH[a] = wsp<float4>(s, L.pmlH) + offc;
+            A.psiE[a] = wsp<float>(s, L.psiE[st]) + offs;
+            A.psiHi[a] = wsp<float>(s, L.psiH[st][par]) + offs;
+            A.psiHo[a] = wsp<float>(s, L.psiH[st][par ^ 1]) + offs;
+            offc += n3[a];
+            offs += slab_size(a, s->g.nx, s->g.ny, s->g.nz, s->g.npml);
+        }
+    }
+    A.tz = s->tz;
+    A.nys = (s->g.ny + CCPR_ROWS - 1) / CCPR_ROWS;
+    A.nblk = A.nys * ((s->g.nz + s->tz - 1) / s->tz);
+    return A;
+}
+
+void set_forward_source(ccpr_solver* s, StepArgs& A)
+{
+    const Layout& L = s->lay;
+    if (s->src_kind == 1) {
+        A.src_on = 1;
+        for (int a = 0; a < 3; ++a) { A.slo[a] = s->dip_cell[a]; A.sdim[a] = 1; }
+        A.sncell = 1;
+        A.snsteps = s->src_table_steps;
+        A.src = wsp<float>(s, L.src_fwd);
+        A.ssh = wsp<double>(s, L.ssh[0]);
+    } else if (s->src_kind == 2) {
+        A.pw_on = 1;
+        A.pw_d = s->pw_d; A.pw_p = s->pw_p; A.pw_t = 3 - s->pw_d - s->pw_p;
+        for (int a = 0; a < 3; ++a) { A.pwlo[a] = s->pw_lo[a]; A.pwhi[a] = s->pw_hi[a]; }
+        A.pw_spanE = plane_span(s);
+        A.pw_spanH = plane_span(s) + 1;
+        A.sg_Ep_d = (float)sigma_ca(A.pw_p, A.pw_d);
+        A.sg_Ed_p = (float)sigma_ca(A.pw_d, A.pw_p);
+        A.sg_Ht_d = (float)sigma_ca(A.pw_t, A.pw_d);
+        A.sg_Hd_t = (float)sigma_ca(A.pw_d, A.pw_t);
+        A.incE = wsp<float>(s, L.incE);
+        A.incH = wsp<float>(s, L.incH);
+    }
+}
+
+ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st)
+{
+    int e = ccpr_launch_step(A, s->maxpairs, s->stream);
+    if (e != 0) return fail(s, CCPR_EDEVICE, "step kernel launch: %s", hipGetErrorString((hipError_t)e));
+    s->parity[st] ^= 1;
+    return CCPR_OK;
+}
+
+// One forward step n of the forward state with optional recording.
+ccpr_status forward_step(ccpr_solver* s, int n, float* Tout, bool gap)
+{
+    StepArgs A = base_args(s, 0);
+    set_forward_source(s, A);
+    A.n = n;
+    A.Tout = Tout;
+    if (gap && s->has_obj) {
+        A.gap_on = 1;
+        for (int a = 0; a < 3; ++a) { A.glo[a] = s->glo[a]; A.gdim[a] = s->gdim[a]; }
+        A.gncell = s->gncell;
+        A.gap = wsp<float>(s, s->lay.gap);
+    }
+    return launch_step(s, A, 0);
+}
+
+// copy the forward state (current parity) to / from checkpoint slot c
+ccpr_status checkpoint(ccpr_solver* s, int slot, bool save)
+{
+    const Layout& L = s->lay;
+    float* ck = wsp<float>(s, L.ckpt + (size_t)slot * align256(L.ckpt_bytes));
+    const int par = save ? s->parity[0] : 0;
+    const long long nc3 = 3 * s->ncell, nj = 2LL * s->npairs_total * std::max(s->nd, 1LL);
+    const long long psi = psi_total(s);
+    struct { float* dev; long long n; } parts[5] = {
+        {wsp<float>(s, L.Eb[0][par]), nc3},
+        {wsp<float>(s, L.Hb[0][par]), nc3},
+        {wsp<float>(s, L.Jb[0]), nj},
+        {wsp<float>(s, L.psiE[0]), psi},
+        {wsp<float>(s, L.psiH[0][par]), psi},
+    };
+    long long off = 0;
+    for (auto& p : parts) {
+        if (save) HIPCHK(ccpr_launch_copy(ck + off, p.dev, p.n, s->stream));
+        else HIPCHK(ccpr_launch_copy(p.dev, ck + off, p.n, s->stream));
+        off += p.n;
+    }
+    // FP64 shadow of the dipole edge (the forward source box is one cell)
+    double* cks = reinterpret_cast<double*>(ck + ((off + 1) & ~1LL));
+    if (save) HIPCHK(ccpr_launch_copy_d(cks, wsp<double>(s, L.ssh[0]), 3, s->stream));
+    else HIPCHK(ccpr_launch_copy_d(wsp<double>(s, L.ssh[0]), cks, 3, s->stream));
+    if (!save) s->parity[0] = 0;
+    return CCPR_OK;
+}
+
+ccpr_status check_ready(ccpr_solver* s, bool need_obj)
+{
+    ccpr_status st = need_bound(s);
+    if (st) return st;
+    if (s->src_kind == 0) return fail(s, CCPR_ESTATE, "no source set");
+    if (need_obj && !s->has_obj) return fail(s, CCPR_ESTATE, "no objective set");
+    if (need_obj && !s->has_design) return fail(s, CCPR_ESTATE, "no design set");
+    return CCPR_OK;
+}
+
+void build_mats(ccpr_solver* s)
+{
+    int jofs = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        axis_mat(s, ax, jofs, s->mats[ax]);
+        jofs += pairs_on_axis(s, ax);
+    }
+}
+
+// Re-carve the fixed part of the workspace when the configuration that sizes
+// it (design voxels, pole pairs, gap cells) changed; re-upload what lives
+// there and zero both states.
+ccpr_status refresh_fixed(ccpr_solver* s, bool force)
+{
+    if (!s->ws) return CCPR_OK;
+    Layout L = make_layout(s, 0, 0);
+    if (L.fixed_end > s->ws_bytes)
+        return fail(s, CCPR_ENOMEM, "workspace of %llu bytes, need at least %llu", (unsigned long long)s->ws_bytes,
+                    (unsigned long long)L.fixed_end);
+    const long long key[4] = {s->nd, s->npairs_total, s->gncell, (long long)L.fixed_end};
+    const bool changed = force || std::memcmp(key, s->fixed_key, sizeof key) != 0;
+    s->lay = L;
+    if (!changed) return CCPR_OK;
+    std::memcpy(s->fixed_key, key, sizeof key);
+    ccpr_status st = upload_static(s);
+    if (st) return st;
+    s->rho_uploaded = false;
+    if (!s->rho_on_host && s->has_design) s->has_design = false;  // device densities must be set again
+    HIPCHK(ccpr_launch_fill_d(wsp<double>(s, s->lay.scal), 16, 0.0, s->stream));
+    st = zero_state(s, 0);
+    if (st) return st;
+    st = zero_state(s, 1);
+    if (st) return st;
+    s->src_table_steps = -1;
+    s->step_count = 0;
+    s->have_forward = s->have_adjoint = false;
+    return upload_rho(s);
+}
+
+ccpr_status adopt_layout(ccpr_solver* s, int M)
+{
+    ccpr_status st0 = refresh_fixed(s, false);
+    if (st0) return st0;
+    build_mats(s);
+    int K = s->ckpt_every;
+    Layout L = make_layout(s, M, K);
+    if (M > 0 && K == 0 && L.total > s->ws_bytes) {
+        // smallest segment count that fits the workspace
+        for (int S = 2; S <= M; ++S) {
+            int Kt = (M + S - 1) / S;
+            L = make_layout(s, M, Kt);
+            if (L.total <= s->ws_bytes) break;
+        }
+    }
+    if (L.total > s->ws_bytes)
+        return fail(s, CCPR_ENOMEM, "workspace of %llu bytes, need %llu", (unsigned long long)s->ws_bytes,
+                    (unsigned long long)L.total);
+    s->lay = L;
+    return CCPR_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+ccpr_status ccpr_create(const ccpr_grid* g, ccpr_solver** out)
+{
+    if (!out) return fail(nullptr, CCPR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g) return fail(nullptr, CCPR_EINVAL, "grid is NULL");
+    if (g->nx < 2 || g->ny < 2 || g->nz < 2) return fail(nullptr, CCPR_EINVAL, "grid must be at least 2 cells per axis");
+    if (!(g->dx > 0) || !std::isfinite(g->dx)) return fail(nullptr, CCPR_EINVAL, "dx must be positive");
+    if (!(g->courant > 0) || !std::isfinite(g->courant)) return fail(nullptr, CCPR_EINVAL, "courant must be positive");
+    if (g->courant > 1.0 / std::sqrt(3.0) + 1e-12)
+        return fail(nullptr, CCPR_ECFL, "courant %g exceeds the 3-D Yee limit 1/sqrt(3)", g->courant);
+    if (g->npml < 0 || 2 * g->npml + 2 > std::min(g->nx, std::min(g->ny, g->nz)))
+        return fail(nullptr, CCPR_EINVAL, "CPML thickness %d too large for the grid", g->npml);
+    if (g->npml > 0 && (!(g->pml_order >= 0) || !(g->pml_kappa_max >= 1) || !(g->pml_alpha_max >= 0) ||
+                        !(g->pml_sigma_scale >= 0)))
+        return fail(nullptr, CCPR_EINVAL, "bad CPML grading parameters");
+    if (g->nx > CCPR_MAX_NX) return fail(nullptr, CCPR_ENOTSUP, "nx %d exceeds %d", g->nx, CCPR_MAX_NX);
+    ccpr_solver* s = new ccpr_solver();
+    s->g = *g;
+    s->dt = g->courant * g->dx / kC0;
+    s->ncell = (long long)g->nx * g->ny * g->nz;
+    *out = s;
+    return CCPR_OK;
+}
+
+void ccpr_destroy(ccpr_solver* s)
+{
+    if (!s) return;
+    if (s->ws) (void)hipStreamSynchronize(s->stream);
+    delete s;
+}
+
+const char* ccpr_last_error(const ccpr_solver* s) { return s ? s->err.c_str() : g_create_err.c_str(); }
+
+ccpr_status ccpr_set_material(ccpr_solver* s, int slot, int axis, double eps_inf, double sigma, int npairs,
+                              const double* a, const double* c)
+{
+    if (!s) return CCPR_EINVAL;
+    if (slot < 1 || slot > 2 || axis < 0 || axis > 2 || npairs < 0 || (npairs > 0 && (!a || !c)))
+        return fail(s, CCPR_EINVAL, "bad material arguments");
+    if (!std::isfinite(eps_inf) || !std::isfinite(sigma) || eps_inf <= 0 || sigma < 0)
+        return fail(s, CCPR_EINVAL, "eps_inf must be positive and sigma non-negative");
+    MatHost m;
+    m.eps = eps_inf;
+    m.sig = sigma;
+    for (int p = 0; p < npairs; ++p) {
+        for (int q = 0; q < 2; ++q)
+            if (!std::isfinite(a[2 * p + q]) || !std::isfinite(c[2 * p + q]))
+                return fail(s, CCPR_EINVAL, "non-finite pole or residue");
+        m.a.push_back(cd(a[2 * p], a[2 * p + 1]));
+        m.c.push_back(cd(c[2 * p], c[2 * p + 1]));
+    }
+    const int other = (int)s->mat[2 - slot][axis].a.size();
+    if (npairs + other > CCPR_MAX_PAIRS_PER_AXIS)
+        return fail(s, CCPR_ENOTSUP, "%d pole pairs on axis %d exceed %d", npairs + other, axis,
+                    CCPR_MAX_PAIRS_PER_AXIS);
+    s->mat[slot - 1][axis] = m;
+    recount_pairs(s);
+    s->have_forward = s->have_adjoint = false;
+    return refresh_fixed(s, false);
+}
+
+ccpr_status ccpr_set_design(ccpr_solver* s, const int lo[3], const int dims[3], double gamma, const float* rho,
+                            int mem)
+{
+    if (!s) return CCPR_EINVAL;
+    if (!lo || !dims || !rho || (mem != CCPR_MEM_HOST && mem != CCPR_MEM_DEVICE))
+        return fail(s, CCPR_EINVAL, "bad design arguments");
+    const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
+    const int m = std::max(s->g.npml, 1);
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || lo[a] < m || lo[a] + dims[a] > n3[a] - s->g.npml)
+            return fail(s, CCPR_EINVAL, "design box must lie inside the grid, off the walls and outside the CPML");
+    if (!std::isfinite(gamma) || gamma < 0) return fail(s, CCPR_EINVAL, "gamma must be finite and >= 0");
+    const long long nd = (long long)dims[0] * dims[1] * dims[2];
+    if (mem == CCPR_MEM_HOST) {
+        for (long long v = 0; v < nd; ++v)
+            if (!(rho[v] >= 0.f && rho[v] <= 1.f))
+                return fail(s, CCPR_EINVAL, "density %lld is %g: must be finite and in [0,1]", v, (double)rho[v]);
+    } else if (!s->ws) {
+        return fail(s, CCPR_ESTATE, "device densities need a bound workspace");
+    }
+    for (int a = 0; a < 3; ++a) { s->dlo[a] = lo[a]; s->ddim[a] = dims[a]; }
+    s->nd = nd;
+    s->gamma = gamma;
+    s->have_forward = s->have_adjoint = false;
+    if (mem == CCPR_MEM_HOST) {
+        s->rho_host.assign(rho, rho + nd);
+        s->rho_on_host = true;
+        s->rho_uploaded = false;
+        s->has_design = true;
+        ccpr_status st = refresh_fixed(s, false);
+        if (st) return st;
+        return upload_rho(s);
+    } else {
+        s->rho_on_host = false;
+        s->rho_host.clear();
+        s->has_design = true;
+        ccpr_status st = refresh_fixed(s, false);
+        if (st) return st;
+        s->has_design = true;
+        HIPCHK(hipMemcpyAsync(s->ws + s->lay.rho, rho, nd * 4, hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(ccpr_launch_fill_d(wsp<double>(s, s->lay.scal) + 2, 1, 0.0, s->stream));
+        HIPCHK(ccpr_launch_check_rho(wsp<float>(s, s->lay.rho), nd, wsp<double>(s, s->lay.scal) + 2, s->stream));
+    }
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_set_source_dipole(ccpr_solver* s, const int cell[3], int axis, const double* wave, int nsteps)
+{
+    if (!s) return CCPR_EINVAL;
+    if (!cell || axis < 0 || axis > 2 || nsteps < 1 || !wave) return fail(s, CCPR_EINVAL, "bad dipole arguments");
+    const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
+    for (int a = 0; a < 3; ++a)
+        if (cell[a] < 0 || cell[a] >= n3[a]) return fail(s, CCPR_EINVAL, "dipole cell outside the grid");
+    for (int n = 0; n < nsteps; ++n)
+        if (!std::isfinite(wave[n])) return fail(s, CCPR_EINVAL, "non-finite waveform sample");
+    s->src_kind = 1;
+    for (int a = 0; a < 3; ++a) s->dip_cell[a] = cell[a];
+    s->dip_axis = axis;
+    s->wave.assign(wave, wave + nsteps);
+    s->src_table_steps = -1;
+    s->have_forward = s->have_adjoint = false;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_set_source_planewave(ccpr_solver* s, int prop_axis, int sign, int pol_axis, const int lo[3],
+                                      const int hi[3], const double* wave, int nsteps)
+{
+    if (!s) return CCPR_EINVAL;
+    if (prop_axis < 0 || prop_axis > 2 || pol_axis < 0 || pol_axis > 2 || prop_axis == pol_axis ||
+        (sign != 1 && sign != -1) || !lo || !hi || !wave || nsteps < 1)
+        return fail(s, CCPR_EINVAL, "bad plane-wave arguments");
+    const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
+    for (int a = 0; a < 3; ++a)
+        if (lo[a] < s->g.npml + 1 || hi[a] <= lo[a] || hi[a] > n3[a] - s->g.npml - 2)
+            return fail(s, CCPR_EINVAL, "TF/SF box must lie strictly inside the grid and outside the CPML");
+    for (int n = 0; n < nsteps; ++n)
+        if (!std::isfinite(wave[n])) return fail(s, CCPR_EINVAL, "non-finite waveform sample");
+    s->src_kind = 2;
+    s->pw_d = prop_axis;
+    s->pw_sgn = sign;
+    s->pw_p = pol_axis;
+    for (int a = 0; a < 3; ++a) { s->pw_lo[a] = lo[a]; s->pw_hi[a] = hi[a]; }
+    s->wave.assign(wave, wave + nsteps);
+    s->src_table_steps = -1;
+    s->have_forward = s->have_adjoint = false;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_set_objective(ccpr_solver* s, int kind, const int lo[3], const int dims[3], double omega,
+                               int n_begin, int n_end)
+{
+    if (!s) return CCPR_EINVAL;
+    if ((kind != CCPR_OBJ_TIME_E2 && kind != CCPR_OBJ_DFT_E2) || !lo || !dims || !std::isfinite(omega))
+        return fail(s, CCPR_EINVAL, "bad objective arguments");
+    const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || lo[a] < 1 || lo[a] + dims[a] > n3[a])
+            return fail(s, CCPR_EINVAL, "gap box outside the grid");
+    if ((long long)dims[0] * dims[1] * dims[2] > 65536) return fail(s, CCPR_ENOTSUP, "gap box above 65536 cells");
+    s->obj_kind = kind;
+    for (int a = 0; a < 3; ++a) { s->glo[a] = lo[a]; s->gdim[a] = dims[a]; }
+    s->gncell = dims[0] * dims[1] * dims[2];
+    s->omega = omega;
+    s->nb = n_begin;
+    s->ne = n_end;
+    s->has_obj = true;
+    s->have_forward = s->have_adjoint = false;
+    return refresh_fixed(s, false);
+}
+
+ccpr_status ccpr_set_checkpointing(ccpr_solver* s, int every)
+{
+    if (!s) return CCPR_EINVAL;
+    if (every < 0) return fail(s, CCPR_EINVAL, "checkpoint_every must be >= 0");
+    s->ckpt_every = every;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_workspace_size(const ccpr_solver* s, int nsteps, uint64_t* bytes)
+{
+    if (!s || !bytes || nsteps < 0) return CCPR_EINVAL;
+    *bytes = make_layout(s, nsteps, s->ckpt_every).total;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_bind_workspace(ccpr_solver* s, void* dev_ptr, uint64_t bytes, void* hip_stream)
+{
+    if (!s) return CCPR_EINVAL;
+    if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(s, CCPR_EINVAL, "workspace must be 256-byte aligned");
+    Layout L = make_layout(s, 0, 0);
+    if (L.fixed_end > bytes) return fail(s, CCPR_ENOMEM, "workspace of %llu bytes, need at least %llu",
+                                         (unsigned long long)bytes, (unsigned long long)L.total);
+    if (s->ws) (void)hipStreamSynchronize(s->stream);
+    s->ws = (char*)dev_ptr;
+    s->ws_bytes = bytes;
+    s->stream = (hipStream_t)hip_stream;
+    s->lay = L;
+    return refresh_fixed(s, true);
+}
+
+ccpr_status ccpr_reset(ccpr_solver* s)
+{
+    if (!s) return CCPR_EINVAL;
+    ccpr_status st = need_bound(s);
+    if (st) return st;
+    s->step_count = 0;
+    s->current_state = 0;
+    return zero_state(s, 0);
+}
+
+ccpr_status ccpr_step(ccpr_solver* s, int n)
+{
+    if (!s) return CCPR_EINVAL;
+    if (n < 0) return fail(s, CCPR_EINVAL, "negative step count");
+    ccpr_status st = check_ready(s, false);
+    if (st) return st;
+    if (s->src_table_steps < 0 || s->src_table_steps != s->lay.inc_steps || s->have_forward) {
+        st = adopt_layout(s, 0);
+        if (st) return st;
+        st = upload_rho(s);
+        if (st) return st;
+        st = prepare_source(s, s->lay.inc_steps);
+        if (st) return st;
+        s->have_forward = s->have_adjoint = false;
+    }
+    if (s->src_kind == 2 && s->step_count + n > s->lay.inc_steps)
+        return fail(s, CCPR_ENOTSUP, "plane-wave stepping is limited to the waveform length (%d steps)",
+                    s->lay.inc_steps);
+    build_mats(s);
+    s->current_state = 0;
+    for (int q = 0; q < n; ++q) {
+        st = forward_step(s, s->step_count, nullptr, false);
+        if (st) return st;
+        s->step_count++;
+    }
+    return CCPR_OK;
+}
+
+int ccpr_step_count(const ccpr_solver* s) { return s ? s->step_count : -1; }
+
+ccpr_status ccpr_get_field(ccpr_solver* s, int comp, float* out, int mem)
+{
+    if (!s) return CCPR_EINVAL;
+    if (comp < 0 || comp > 5 || !out || (mem != CCPR_MEM_HOST && mem != CCPR_MEM_DEVICE))
+        return fail(s, CCPR_EINVAL, "bad get_field arguments");
+    ccpr_status st = need_bound(s);
+    if (st) return st;
+    const int state = s->current_state;
+    const double a = state == 0 ? s->alpha : s->adj_alpha;
+    const double eta0 = std::sqrt(kMu0 / kEps0);
+    const float f = (float)(comp < 3 ? 1.0 / a : 1.0 / (a * eta0));
+    const int par = s->parity[state];
+    const float* src = comp < 3 ? wsp<float>(s, s->lay.Eb[state][par]) + comp * s->ncell
+                                : wsp<float>(s, s->lay.Hb[state][par]) + (comp - 3) * s->ncell;
+    if (mem == CCPR_MEM_DEVICE) {
+        HIPCHK(ccpr_launch_scale(out, src, s->ncell, f, s->stream));
+    } else {
+        float* stage = wsp<float>(s, s->lay.stage);
+        HIPCHK(ccpr_launch_scale(stage, src, s->ncell, f, s->stream));
+        HIPCHK(hipMemcpyAsync(out, stage, s->ncell * 4, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
+{
+    if (!s) return CCPR_EINVAL;
+    if (nsteps < 1) return fail(s, CCPR_EINVAL, "nsteps must be >= 1");
+    ccpr_status st = check_ready(s, true);
+    if (st) return st;
+    st = adopt_layout(s, nsteps);
+    if (st) return st;
+    st = upload_rho(s);
+    if (st) return st;
+    st = prepare_source(s, nsteps);
+    if (st) return st;
+    const Layout& L = s->lay;
+    const int M = nsteps, K = L.K, S = L.S;
+    s->M = M;
+    st = zero_state(s, 0);
+    if (st) return st;
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.gap), (long long)s->gncell * 3, 0.f, s->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s->timing) {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, s->stream));
+    }
+    for (int n = 0; n < M; ++n) {
+        const int seg = n / K;
+        if (n % K == 0 && seg >= 1 && seg < S) {
+            st = checkpoint(s, seg - 1, true);
+            if (st) return st;
+        }
+        float* T = seg == S - 1 ? wsp<float>(s, L.T) + (size_t)(n - seg * K) * 3 * std::max(s->nd, 1LL) : nullptr;
+        st = forward_step(s, n, T, true);
+        if (st) return st;
+    }
+    if (s->timing) {
+        HIPCHK(hipEventRecord(e1, s->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        s->stat_ms += ms;
+        s->stat_launches += M;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    s->step_count = M;
+    s->current_state = 0;
+    const int ne = s->gncell * 3;
+    const int nend = s->ne < 0 ? M + 1 : s->ne;
+    HIPCHK(ccpr_launch_objective(wsp<float>(s, L.gap), M, ne, s->obj_kind == CCPR_OBJ_DFT_E2 ? 1 : 0,
+                                 s->omega * s->dt, s->nb, nend, wsp<double>(s, L.scal), wsp<double>(s, L.work),
+                                 wsp<float>(s, L.src_adj), s->stream));
+    double scal[4];
+    HIPCHK(hipMemcpyAsync(scal, wsp<double>(s, L.scal), sizeof scal, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (!s->rho_on_host && scal[2] != 0.0)
+        return fail(s, CCPR_EINVAL, "device densities must be finite and within [0,1]");
+    const double a = s->alpha, dt = s->dt, dx = s->g.dx;
+    if (s->obj_kind == CCPR_OBJ_DFT_E2) {
+        s->F = (dt / a) * (dt / a) * scal[0];
+        s->adj_alpha = kEps0 * a / (2 * dt * dt * scal[1]);
+        s->grad_scale = 2 * dt * dt * scal[1] / (a * a);
+    } else {
+        s->F = 0.5 * kEps0 * dx * dx * dx * dt * scal[0] / (a * a);
+        s->adj_alpha = a / (dt * dx * dx * dx * scal[1]);
+        s->grad_scale = kEps0 * dt * dx * dx * dx * scal[1] / (a * a);
+    }
+    if (!std::isfinite(s->F) || !std::isfinite(scal[1]))
+        return fail(s, CCPR_EDIVERGED, "objective is not finite: the fields diverged");
+    s->have_forward = true;
+    s->have_adjoint = false;
+    if (objective_out) *objective_out = s->F;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_adjoint(ccpr_solver* s)
+{
+    if (!s) return CCPR_EINVAL;
+    if (!s->have_forward) return fail(s, CCPR_ESTATE, "adjoint needs a completed forward run");
+    const Layout& L = s->lay;
+    const int M = s->M, K = L.K, S = L.S;
+    const long long ndm = std::max(s->nd, 1LL);
+    ccpr_status st = zero_state(s, 1);
+    if (st) return st;
+    HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), ndm, 0.0, s->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms_total = 0;
+    for (int seg = S - 1; seg >= 0; --seg) {
+        const int n0 = seg * K, n1 = std::min(M, n0 + K);
+        if (seg < S - 1) {
+            // recompute the forward segment from its checkpoint, writing the history
+            if (seg == 0) st = zero_state(s, 0);
+            else st = checkpoint(s, seg - 1, false);
+            if (st) return st;
+            for (int n = n0; n < n1; ++n) {
+                st = forward_step(s, n, wsp<float>(s, L.T) + (size_t)(n - n0) * 3 * ndm, false);
+                if (st) return st;
+            }
+        }
+        if (s->timing) {
+            HIPCHK(hipEventCreate(&e0));
+            HIPCHK(hipEventCreate(&e1));
+            HIPCHK(hipEventRecord(e0, s->stream));
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            const int p = M - 1 - n;  // adjoint step p pairs with forward step n
+            StepArgs A = base_args(s, 1);
+            A.n = p;
+            A.src_on = 1;
+            for (int a = 0; a < 3; ++a) { A.slo[a] = s->glo[a]; A.sdim[a] = s->gdim[a]; }
+            A.sncell = s->gncell;
+            A.snsteps = M;
+            A.src = wsp<float>(s, L.src_adj);
+            A.ssh = wsp<double>(s, L.ssh[1]);
+            A.Tin = wsp<float>(s, L.T) + (size_t)(n - n0) * 3 * ndm;
+            A.grad = wsp<double>(s, L.gradacc);
+            st = launch_step(s, A, 1);
+            if (st) return st;
+        }
+        if (s->timing) {
+            HIPCHK(hipEventRecord(e1, s->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            ms_total += ms;
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
+    }
+    if (s->timing) {
+        s->stat_ms += ms_total;
+        s->stat_launches += M;
+    }
+    s->current_state = 1;
+    s->have_adjoint = true;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_gradient(ccpr_solver* s, double* grad, int mem)
+{
+    if (!s) return CCPR_EINVAL;
+    if (!grad || (mem != CCPR_MEM_HOST && mem != CCPR_MEM_DEVICE)) return fail(s, CCPR_EINVAL, "bad gradient arguments");
+    if (!s->have_adjoint) return fail(s, CCPR_ESTATE, "gradient needs a completed adjoint run");
+    const double f = s->grad_scale;
+    if (mem == CCPR_MEM_DEVICE) {
+        HIPCHK(ccpr_launch_grad_out(grad, wsp<double>(s, s->lay.gradacc), s->nd, f, s->stream));
+    } else {
+        double* stage = wsp<double>(s, s->lay.stage);
+        HIPCHK(ccpr_launch_grad_out(stage, wsp<double>(s, s->lay.gradacc), s->nd, f, s->stream));
+        HIPCHK(hipMemcpyAsync(grad, stage, s->nd * 8, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return CCPR_OK;
+}
+
+// ---- diagnostics (declared in ccprfdtd.h)
+ccpr_status ccpr_set_timing(ccpr_solver* s, int enable)
+{
+    if (!s) return CCPR_EINVAL;
+    s->timing = enable != 0;
+    s->stat_ms = 0;
+    s->stat_launches = 0;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_get_timing(const ccpr_solver* s, double* step_ms_total, long long* step_launches)
+{
+    if (!s || !step_ms_total || !step_launches) return CCPR_EINVAL;
+    *step_ms_total = s->stat_ms;
+    *step_launches = s->stat_launches;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_get_info(const ccpr_solver* s, int* segments, int* segment_steps, int* tile_planes)
+{
+    if (!s) return CCPR_EINVAL;
+    if (segments) *segments = s->lay.S;
+    if (segment_steps) *segment_steps = s->lay.K;
+    if (tile_planes) *tile_planes = s->tz;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_set_tile_planes(ccpr_solver* s, int planes)
+{
+    if (!s) return CCPR_EINVAL;
+    if (planes < 1 || planes > 4096) return fail(s, CCPR_EINVAL, "tile planes must be in [1,4096]");
+    s->tz = planes;
+    return CCPR_OK;
+}
+
+}  // extern "C"

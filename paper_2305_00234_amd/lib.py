@@ -1,0 +1,269 @@
+"""ctypes binding of libccprfdtd.so (the C-ABI of include/ccprfdtd.h).
+
+Argument marshalling only: every step of the path runs in the library's gfx950
+kernels.  PyTorch supplies device memory (the workspace, device densities and
+gradients) and the HIP stream; there is no fallback of any kind -- if the
+library has not been built, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccprfdtd.so")
+
+OK, EINVAL, ECFL, ENOMEM, EDEVICE, ESTATE, EDIVERGED, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "CCPR_OK", -1: "CCPR_EINVAL", -2: "CCPR_ECFL", -3: "CCPR_ENOMEM",
+                -4: "CCPR_EDEVICE", -5: "CCPR_ESTATE", -6: "CCPR_EDIVERGED", -7: "CCPR_ENOTSUP"}
+MEM_HOST, MEM_DEVICE = 0, 1
+OBJ_TIME_E2, OBJ_DFT_E2 = 0, 1
+EX, EY, EZ, HX, HY, HZ = range(6)
+
+# every entry point declared in include/ccprfdtd.h
+EXPORTS = [
+    "ccpr_create", "ccpr_destroy", "ccpr_last_error", "ccpr_set_material", "ccpr_set_design",
+    "ccpr_set_source_dipole", "ccpr_set_source_planewave", "ccpr_set_objective",
+    "ccpr_set_checkpointing", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
+    "ccpr_adjoint", "ccpr_gradient", "ccpr_reset", "ccpr_step", "ccpr_get_field",
+    "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_info",
+    "ccpr_set_tile_planes",
+]
+
+
+class CcprGrid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double),
+                ("courant", C.c_double), ("npml", C.c_int), ("pml_order", C.c_double),
+                ("pml_kappa_max", C.c_double), ("pml_alpha_max", C.c_double),
+                ("pml_sigma_scale", C.c_double)]
+
+
+class CcprError(RuntimeError):
+    def __init__(self, status: int, what: str, msg: str):
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_LIB = None
+_p = C.c_void_p
+_i = C.c_int
+_d = C.c_double
+_ip = C.POINTER(C.c_int)
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+
+
+def load():
+    """Load the built library (raises FileNotFoundError if it was not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2305_00234_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    sig = {
+        "ccpr_create": (_i, [C.POINTER(CcprGrid), C.POINTER(_p)]),
+        "ccpr_destroy": (None, [_p]),
+        "ccpr_last_error": (C.c_char_p, [_p]),
+        "ccpr_set_material": (_i, [_p, _i, _i, _d, _d, _i, _dp, _dp]),
+        "ccpr_set_design": (_i, [_p, _ip, _ip, _d, _p, _i]),
+        "ccpr_set_source_dipole": (_i, [_p, _ip, _i, _dp, _i]),
+        "ccpr_set_source_planewave": (_i, [_p, _i, _i, _i, _ip, _ip, _dp, _i]),
+        "ccpr_set_objective": (_i, [_p, _i, _ip, _ip, _d, _i, _i]),
+        "ccpr_set_checkpointing": (_i, [_p, _i]),
+        "ccpr_workspace_size": (_i, [_p, _i, C.POINTER(C.c_uint64)]),
+        "ccpr_bind_workspace": (_i, [_p, _p, C.c_uint64, _p]),
+        "ccpr_forward": (_i, [_p, _i, _dp]),
+        "ccpr_adjoint": (_i, [_p]),
+        "ccpr_gradient": (_i, [_p, _p, _i]),
+        "ccpr_reset": (_i, [_p]),
+        "ccpr_step": (_i, [_p, _i]),
+        "ccpr_get_field": (_i, [_p, _i, _p, _i]),
+        "ccpr_step_count": (_i, [_p]),
+        "ccpr_set_timing": (_i, [_p, _i]),
+        "ccpr_get_timing": (_i, [_p, _dp, C.POINTER(C.c_longlong)]),
+        "ccpr_get_info": (_i, [_p, _ip, _ip, _ip]),
+        "ccpr_set_tile_planes": (_i, [_p, _i]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _i3(v: Sequence[int]):
+    return (C.c_int * 3)(*[int(x) for x in v])
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+class Solver:
+    """One solver handle.  Methods mirror the C-ABI one to one."""
+
+    def __init__(self, nx, ny, nz, dx, courant=0.5, npml=0, pml_order=3.0, pml_kappa_max=1.0,
+                 pml_alpha_max=0.05, pml_sigma_scale=1.0):
+        self._lib = load()
+        g = CcprGrid(nx, ny, nz, dx, courant, npml, pml_order, pml_kappa_max, pml_alpha_max,
+                     pml_sigma_scale)
+        h = _p()
+        st = self._lib.ccpr_create(C.byref(g), C.byref(h))
+        if st != OK:
+            raise CcprError(st, "ccpr_create", self._lib.ccpr_last_error(None).decode())
+        self._h = h
+        self.shape = (nz, ny, nx)
+        self._keep = []
+
+    # -- plumbing
+    def _chk(self, st, what):
+        if st != OK:
+            raise CcprError(st, what, self._lib.ccpr_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ccpr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- configuration
+    def set_material(self, slot, axis, eps_inf, sigma=0.0, a=(), c=()):
+        a = np.asarray(a, dtype=np.complex128).ravel()
+        c = np.asarray(c, dtype=np.complex128).ravel()
+        aa, ap = _f64(np.stack([a.real, a.imag], -1).ravel() if a.size else np.zeros(2))
+        cc, cp = _f64(np.stack([c.real, c.imag], -1).ravel() if c.size else np.zeros(2))
+        self._chk(self._lib.ccpr_set_material(self._h, slot, axis, eps_inf, sigma, a.size, ap, cp),
+                  "ccpr_set_material")
+
+    def set_design(self, lo, rho, gamma=0.0):
+        """rho: numpy float32 (dz, dy, dx) on the host, or a torch float32 CUDA tensor."""
+        if hasattr(rho, "data_ptr") and getattr(rho, "is_cuda", False):
+            import torch
+            assert rho.dtype == torch.float32 and rho.is_contiguous() and rho.dim() == 3
+            dims = (rho.shape[2], rho.shape[1], rho.shape[0])
+            self._chk(self._lib.ccpr_set_design(self._h, _i3(lo), _i3(dims), gamma,
+                                                C.c_void_p(rho.data_ptr()), MEM_DEVICE),
+                      "ccpr_set_design")
+        else:
+            r = np.ascontiguousarray(rho, dtype=np.float32)
+            dims = (r.shape[2], r.shape[1], r.shape[0])
+            self._chk(self._lib.ccpr_set_design(self._h, _i3(lo), _i3(dims), gamma,
+                                                r.ctypes.data_as(C.c_void_p), MEM_HOST),
+                      "ccpr_set_design")
+        self.design_dims = dims
+
+    def set_source_dipole(self, cell, axis, wave):
+        w, wp = _f64(wave)
+        self._chk(self._lib.ccpr_set_source_dipole(self._h, _i3(cell), axis, wp, w.size),
+                  "ccpr_set_source_dipole")
+
+    def set_source_planewave(self, prop_axis, sign, pol_axis, lo, hi, wave):
+        w, wp = _f64(wave)
+        self._chk(self._lib.ccpr_set_source_planewave(self._h, prop_axis, sign, pol_axis, _i3(lo),
+                                                      _i3(hi), wp, w.size),
+                  "ccpr_set_source_planewave")
+
+    def set_objective(self, kind, lo, dims, omega=0.0, n_begin=0, n_end=-1):
+        self._chk(self._lib.ccpr_set_objective(self._h, kind, _i3(lo), _i3(dims), omega, n_begin,
+                                               n_end), "ccpr_set_objective")
+
+    def set_checkpointing(self, every):
+        self._chk(self._lib.ccpr_set_checkpointing(self._h, every), "ccpr_set_checkpointing")
+
+    def workspace_size(self, nsteps):
+        b = C.c_uint64(0)
+        self._chk(self._lib.ccpr_workspace_size(self._h, nsteps, C.byref(b)), "ccpr_workspace_size")
+        return int(b.value)
+
+    def bind_workspace(self, ptr: int, nbytes: int, stream: int = 0):
+        self._chk(self._lib.ccpr_bind_workspace(self._h, C.c_void_p(ptr), nbytes, C.c_void_p(stream)),
+                  "ccpr_bind_workspace")
+
+    def bind_torch(self, nsteps: int, device=None, extra: int = 0):
+        """Allocate the workspace as a torch uint8 CUDA tensor and bind it with
+        torch's current stream on that device."""
+        import torch
+        dev = torch.device(device or "cuda")
+        nbytes = self.workspace_size(nsteps) + extra
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        self.bind_workspace(ws.data_ptr(), nbytes, stream)
+        self._ws = ws
+        return ws
+
+    # -- running
+    def forward(self, nsteps) -> float:
+        F = C.c_double(0.0)
+        self._chk(self._lib.ccpr_forward(self._h, nsteps, C.byref(F)), "ccpr_forward")
+        return F.value
+
+    def adjoint(self):
+        self._chk(self._lib.ccpr_adjoint(self._h), "ccpr_adjoint")
+
+    def gradient(self, out=None):
+        """Host numpy (dz,dy,dx) float64 by default; pass a torch float64 CUDA
+        tensor to receive it on the device (stream-ordered)."""
+        d = self.design_dims
+        if out is not None and getattr(out, "is_cuda", False):
+            self._chk(self._lib.ccpr_gradient(self._h, C.c_void_p(out.data_ptr()), MEM_DEVICE),
+                      "ccpr_gradient")
+            return out
+        g = np.empty((d[2], d[1], d[0]), dtype=np.float64)
+        self._chk(self._lib.ccpr_gradient(self._h, g.ctypes.data_as(C.c_void_p), MEM_HOST),
+                  "ccpr_gradient")
+        return g
+
+    def reset(self):
+        self._chk(self._lib.ccpr_reset(self._h), "ccpr_reset")
+
+    def step(self, n=1):
+        self._chk(self._lib.ccpr_step(self._h, int(n)), "ccpr_step")
+
+    def field(self, comp, out=None):
+        if out is not None and getattr(out, "is_cuda", False):
+            self._chk(self._lib.ccpr_get_field(self._h, comp, C.c_void_p(out.data_ptr()), MEM_DEVICE),
+                      "ccpr_get_field")
+            return out
+        f = np.empty(self.shape, dtype=np.float32)
+        self._chk(self._lib.ccpr_get_field(self._h, comp, f.ctypes.data_as(C.c_void_p), MEM_HOST),
+                  "ccpr_get_field")
+        return f
+
+    @property
+    def step_count(self):
+        return self._lib.ccpr_step_count(self._h)
+
+    # -- diagnostics
+    def set_timing(self, on=True):
+        self._chk(self._lib.ccpr_set_timing(self._h, 1 if on else 0), "ccpr_set_timing")
+
+    def timing(self):
+        ms = C.c_double(0.0)
+        n = C.c_longlong(0)
+        self._chk(self._lib.ccpr_get_timing(self._h, C.byref(ms), C.byref(n)), "ccpr_get_timing")
+        return ms.value, n.value
+
+    def info(self):
+        a, b, c = C.c_int(0), C.c_int(0), C.c_int(0)
+        self._chk(self._lib.ccpr_get_info(self._h, C.byref(a), C.byref(b), C.byref(c)),
+                  "ccpr_get_info")
+        return {"segments": a.value, "segment_steps": b.value, "tile_planes": c.value}
+
+    def set_tile_planes(self, planes):
+        self._chk(self._lib.ccpr_set_tile_planes(self._h, planes), "ccpr_set_tile_planes")

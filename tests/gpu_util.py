@@ -1,0 +1,98 @@
+"""Helpers for the GPU parity tests: run the same seeded workload through the
+library (FP32, gfx950) and through the FP64 oracle, and compare."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from oracle.oracle import OBJ_DFT, OBJ_TIME
+from paper_2305_00234_amd.inputs import Workload
+from tests.oracle_setup import oracle_from_workload
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def require_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2305_00234_amd import lib
+    lib.load()  # raises if the HIP library was not built: no fallback exists
+    return torch
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+ETA0 = 376.730313668
+
+
+def field_errors(gpu_fields, or_fields):
+    """Relative L2 errors of the field state: (E, eta0 H) together in the
+    energy norm (the parity bar), E alone and H alone (diagnostics)."""
+    g = np.stack([np.asarray(f, np.float64) for f in gpu_fields])
+    o = np.stack([np.asarray(f, np.float64) for f in or_fields])
+    w = np.array([1, 1, 1, ETA0, ETA0, ETA0]).reshape(6, 1, 1, 1)
+    state = rel_l2(g * w, o * w)
+    return state, rel_l2(g[:3], o[:3]), rel_l2(g[3:], o[3:])
+
+
+def gpu_fields_after_steps(w: Workload, steps: int, tile_planes=None):
+    from paper_2305_00234_amd.solver import configure
+    torch = require_gpu()
+    s = configure(w)
+    if tile_planes:
+        s.set_tile_planes(tile_planes)
+    s.bind_torch(0)
+    s.reset()
+    s.step(steps)
+    out = [s.field(c) for c in range(6)]
+    torch.cuda.synchronize()
+    s.close()
+    return out
+
+
+def oracle_fields_after_steps(w: Workload, steps: int):
+    o = oracle_from_workload(w)
+    o.reset()
+    o.run(steps)
+    return o.fields()
+
+
+def gpu_gradient(w: Workload, tile_planes=None, checkpoint_every=None, want_adjoint_fields=False):
+    from paper_2305_00234_amd.solver import configure
+    torch = require_gpu()
+    s = configure(w)
+    if tile_planes:
+        s.set_tile_planes(tile_planes)
+    if checkpoint_every is not None:
+        s.set_checkpointing(checkpoint_every)
+    s.bind_torch(w.steps)
+    F = s.forward(w.steps)
+    fwd = [s.field(c) for c in range(6)]
+    s.adjoint()
+    g = s.gradient()
+    adj = [s.field(c) for c in range(6)] if want_adjoint_fields else None
+    info = s.info()
+    torch.cuda.synchronize()
+    s.close()
+    return F, g, fwd, adj, info
+
+
+def oracle_gradient(w: Workload):
+    o = oracle_from_workload(w)
+    kind = OBJ_DFT if w.objective == "dft" else OBJ_TIME
+    # forward fields at the end of the run (the gradient call leaves the adjoint)
+    o.reset()
+    o.run(w.steps)
+    fwd = o.fields()
+    F, g = o.gradient(w.steps, kind, w.gap_lo, w.gap_dims, w.omega, w.window[0], w.window_end)
+    adj = o.fields()
+    return F, g, fwd, adj

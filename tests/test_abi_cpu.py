@@ -1,0 +1,130 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and validates arguments / call order on the host."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2305_00234_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2305_00234_amd import build
+        build.build()
+    return L.load()
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ccprfdtd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccpr_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declarations_match_binding():
+    assert _declared() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(built):
+    for name in _declared():
+        assert hasattr(built, name), name
+
+
+def test_create_validates_grid(built):
+    with pytest.raises(L.CcprError) as e:
+        L.Solver(32, 32, 32, 10e-9, courant=0.6)
+    assert e.value.status == L.ECFL
+    with pytest.raises(L.CcprError) as e:
+        L.Solver(1, 32, 32, 10e-9)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.CcprError) as e:
+        L.Solver(32, 32, 32, 10e-9, npml=16)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.CcprError) as e:
+        L.Solver(2048, 8, 8, 10e-9)
+    assert e.value.status == L.ENOTSUP
+    s = L.Solver(32, 32, 32, 10e-9, courant=1 / np.sqrt(3))
+    s.close()
+
+
+def test_configuration_validation_and_call_order(built):
+    s = L.Solver(32, 32, 32, 10e-9, npml=8)
+    with pytest.raises(L.CcprError) as e:
+        s.set_material(3, 0, 1.0)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.CcprError) as e:
+        s.set_material(2, 0, 1.0, 0.0, [complex(np.nan, 0)], [1.0])
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.CcprError) as e:
+        s.set_material(2, 0, 1.0, 0.0, [-1e14] * 9, [1e17] * 9)
+    assert e.value.status == L.ENOTSUP
+    rho = np.full((4, 4, 4), 0.5, np.float32)
+    with pytest.raises(L.CcprError) as e:          # inside the CPML
+        s.set_design((2, 12, 12), rho)
+    assert e.value.status == L.EINVAL
+    bad = rho.copy()
+    bad[1, 2, 3] = np.nan
+    with pytest.raises(L.CcprError) as e:
+        s.set_design((12, 12, 12), bad)
+    assert e.value.status == L.EINVAL
+    bad[1, 2, 3] = 1.5
+    with pytest.raises(L.CcprError) as e:
+        s.set_design((12, 12, 12), bad)
+    assert e.value.status == L.EINVAL
+    s.set_design((12, 12, 12), rho)
+    with pytest.raises(L.CcprError) as e:          # TF/SF box inside the CPML
+        s.set_source_planewave(2, 1, 0, (4, 4, 4), (20, 20, 20), np.ones(10))
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.CcprError) as e:
+        s.set_source_planewave(2, 1, 2, (10, 10, 10), (20, 20, 20), np.ones(10))
+    assert e.value.status == L.EINVAL
+    s.set_source_dipole((10, 16, 16), 0, np.ones(10))
+    s.set_objective(L.OBJ_DFT_E2, (15, 15, 15), (2, 2, 2), 3e15)
+    # nothing bound yet: running is out of order
+    with pytest.raises(L.CcprError) as e:
+        s.forward(10)
+    assert e.value.status == L.ESTATE
+    with pytest.raises(L.CcprError) as e:
+        s.adjoint()
+    assert e.value.status == L.ESTATE
+    with pytest.raises(L.CcprError) as e:
+        s.step(1)
+    assert e.value.status == L.ESTATE
+    with pytest.raises(L.CcprError) as e:
+        s.set_checkpointing(-1)
+    assert e.value.status == L.EINVAL
+    s.close()
+
+
+def test_workspace_size_model(built):
+    """Workspace grows with the history (3 floats per design voxel and step)
+    and shrinks with checkpointing."""
+    s = L.Solver(32, 32, 32, 10e-9, npml=8)
+    s.set_design((12, 12, 12), np.full((8, 8, 8), 0.5, np.float32))
+    s.set_source_dipole((10, 16, 16), 0, np.ones(400))
+    s.set_objective(L.OBJ_DFT_E2, (15, 15, 15), (2, 2, 2), 3e15)
+    b0 = s.workspace_size(0)
+    b1 = s.workspace_size(20000)
+    assert b1 - b0 >= 20000 * 3 * 512 * 4
+    s.set_checkpointing(1000)
+    b2 = s.workspace_size(20000)
+    assert b2 < b1
+    state = 32 ** 3 * 4 * 6
+    assert b2 >= b0 + 1000 * 3 * 512 * 4 + 19 * state
+    s.close()
+
+
+def test_bind_rejects_misaligned_or_small(built):
+    s = L.Solver(16, 16, 16, 10e-9)
+    with pytest.raises(L.CcprError) as e:
+        s.bind_workspace(0x1001, 1 << 20)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.CcprError) as e:
+        s.bind_workspace(0x100000, 16)
+    assert e.value.status == L.ENOMEM
+    s.close()

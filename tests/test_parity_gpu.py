@@ -1,0 +1,164 @@
+"""GPU (FP32, gfx950, through the C-ABI) versus the FP64 oracle.
+
+Bars: field state (E, eta0 H) relative L2 <= 1e-5 in the energy norm,
+objective relative error <= 1e-5, gradient relative L2 <= 1e-3, on the same
+seeded inputs.  E-only and H-only errors are printed as diagnostics: next to a
+point dipole the quasi-static near field makes |E| >> eta0 |H|, and FP32
+rounding of E then shows up as a larger H-only error (a plain numpy FP32 Yee
+update shows the same level).  Grids are chosen so the
+kernel's tiles are exercised with ragged tails: nx not a multiple of 64 (one
+and two waves), ny not a multiple of the 4-row strip, nz not a multiple of the
+z-chunk, several z-chunks, CPML slabs cut by tile edges.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2305_00234_amd import inputs as I
+from tests.gpu_util import (field_errors, gpu_fields_after_steps, gpu_gradient,
+                            oracle_fields_after_steps, oracle_gradient, rel_l2, say)
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-5
+GRAD_TOL = 1e-3
+
+
+def _dipole_box(n=(24, 21, 27), npml=0, steps=60, mats=None, seed=3):
+    w = I.drude_dipole_32(steps=steps, n=32, npml=max(npml, 1))
+    w.shape = n
+    w.npml = npml
+    rng = np.random.default_rng(seed)
+    w.design_lo = (max(npml, 1) + 5, max(npml, 1) + 4, max(npml, 1) + 6)
+    w.rho = rng.random((6, 7, 9)).astype(np.float32)
+    w.dipole_cell = (w.design_lo[0] - 2, w.design_lo[1] + 3, w.design_lo[2] + 2)
+    w.gap_lo = (w.design_lo[0] + 3, w.design_lo[1] + 3, w.design_lo[2] + 2)
+    w.gap_dims = (2, 2, 2)
+    if mats is not None:
+        w.mat1, w.mat2 = mats
+    return w
+
+
+def _short_pulse(w, lam=300e-9, fwhm=0.6e-15, t0=1.0e-15):
+    t = np.arange(w.steps + 1) * w.dt
+    w.wave = I.gaussian_sine(t, lam, fwhm, t0)
+    w.omega = 2 * math.pi * I.C0 / lam
+    return w
+
+
+def test_vacuum_pec_dipole_fields():
+    w = _dipole_box(mats=((I.VACUUM,) * 3, (I.VACUUM,) * 3))
+    say("vacuum PEC dipole", w.shape)
+    g = gpu_fields_after_steps(w, 60)
+    o = oracle_fields_after_steps(w, 60)
+    st, eE, eH = field_errors(g, o)
+    say("rel L2 state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+
+
+def test_dispersive_design_pec_fields_two_waves():
+    """nx = 100 (two waves, ragged), gold design with gamma, no CPML."""
+    w = _dipole_box(n=(100, 23, 30), mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
+    say("gold design PEC", w.shape)
+    g = gpu_fields_after_steps(w, 120, tile_planes=7)
+    o = oracle_fields_after_steps(w, 120)
+    st, eE, eH = field_errors(g, o)
+    say("rel L2 state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+
+
+def test_cpml_dispersive_fields():
+    w = _dipole_box(n=(70, 38, 33), npml=6, steps=150,
+                    mats=((I.lorentz(2.0, 1.2, 2 * math.pi * I.C0 / 250e-9, 2e14),) * 3,
+                          (I.GOLD_TABLE1, I.ALUMINIUM_TABLE1, I.GOLD_TABLE1)))
+    say("cpml two-material anisotropic", w.shape)
+    g = gpu_fields_after_steps(w, 150, tile_planes=5)
+    o = oracle_fields_after_steps(w, 150)
+    st, eE, eH = field_errors(g, o)
+    say("rel L2 state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+
+
+@pytest.mark.parametrize("prop,sign,pol", [(2, 1, 0), (0, -1, 1), (1, 1, 2)])
+def test_tfsf_planewave_fields(prop, sign, pol):
+    w = I.gold_gap(n=(66, 41, 45), design=(20, 13, 11), gap=2, npml=6, steps=140, seed=7,
+                   name="tfsf_small")
+    w.pw_prop_axis, w.pw_sign, w.pw_pol_axis = prop, sign, pol
+    _short_pulse(w)
+    say("tfsf", prop, sign, pol, w.shape)
+    g = gpu_fields_after_steps(w, 140, tile_planes=6)
+    o = oracle_fields_after_steps(w, 140)
+    st, eE, eH = field_errors(g, o)
+    say("rel L2 state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+
+
+def test_drude_dipole_32_fields_400_steps():
+    """The CPU-sized workload: 32^3, 8-cell CPML, Drude design, 400 steps."""
+    w = I.drude_dipole_32()
+    say("drude_dipole_32 fields")
+    g = gpu_fields_after_steps(w, 400)
+    o = oracle_fields_after_steps(w, 400)
+    st, eE, eH = field_errors(g, o)
+    say("rel L2 state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+
+
+@pytest.mark.parametrize("gamma", [0.0, 5e4])
+def test_drude_dipole_32_objective_and_gradient(gamma):
+    w = I.drude_dipole_32(gamma=gamma)
+    say("drude_dipole_32 gradient gamma", gamma)
+    Fg, gg, fg, ag, info = gpu_gradient(w, want_adjoint_fields=True)
+    Fo, go, fo, ao = oracle_gradient(w)
+    say("F", Fg, Fo, "grad rel L2", rel_l2(gg, go), "info", info)
+    assert abs(Fg - Fo) <= FIELD_TOL * abs(Fo)
+    st, eE, eH = field_errors(fg, fo)
+    say("forward state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+    st, eE, eH = field_errors(ag, ao)
+    say("adjoint state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+    assert rel_l2(gg, go) <= GRAD_TOL
+
+
+def test_time_objective_gradient_and_checkpoint_bitwise():
+    """Time-domain objective (Eq. 2) with a window; the checkpointed gradient
+    is bit-identical to the full-history one."""
+    w = _dipole_box(n=(40, 30, 36), npml=5, steps=300,
+                    mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
+    w.objective = "time"
+    w.window = (40, 280)
+    say("time objective", w.shape)
+    F1, g1, _, _, i1 = gpu_gradient(w, tile_planes=8)
+    F2, g2, _, _, i2 = gpu_gradient(w, tile_planes=8, checkpoint_every=70)
+    say("segments", i1, i2)
+    assert i1["segments"] == 1 and i2["segments"] == 5
+    assert F1 == F2
+    assert np.array_equal(g1, g2)
+    Fo, go, _, _ = oracle_gradient(w)
+    say("F", F1, Fo, "grad rel L2", rel_l2(g1, go))
+    assert abs(F1 - Fo) <= FIELD_TOL * abs(Fo)
+    assert rel_l2(g1, go) <= GRAD_TOL
+
+
+def test_planewave_gold_gradient():
+    w = I.gold_gap(n=(64, 44, 48), design=(24, 20, 12), gap=2, npml=6, steps=260, seed=5,
+                   name="pw_grad")
+    _short_pulse(w)
+    say("plane-wave gold gradient", w.shape)
+    Fg, gg, _, _, _ = gpu_gradient(w)
+    Fo, go, _, _ = oracle_gradient(w)
+    say("F", Fg, Fo, "grad rel L2", rel_l2(gg, go))
+    assert abs(Fg - Fo) <= FIELD_TOL * abs(Fo)
+    assert rel_l2(gg, go) <= GRAD_TOL
+
+
+def test_tile_shape_invariance_bitwise():
+    """Results do not depend on the z-chunk height (bitwise)."""
+    w = _dipole_box(n=(70, 38, 33), npml=6, steps=80,
+                    mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
+    a = gpu_fields_after_steps(w, 80, tile_planes=3)
+    b = gpu_fields_after_steps(w, 80, tile_planes=16)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
