@@ -215,9 +215,15 @@ ccpr_status ccpr_get_timing(const ccpr_solver* s, double* step_ms_total, long lo
  * NULL. */
 ccpr_status ccpr_get_info(const ccpr_solver* s, int* segments, int* segment_steps, int* tile_planes);
 
-/* Launch shape: z-planes per workgroup of the step kernel (default 16).
- * Results do not depend on it. */
+/* Launch shape: nominal z-planes per workgroup of the step kernel (default
+ * 8; the planes are split into about nz/planes chunks of equal estimated
+ * cost, so chunks in the CPML are thinner).  Results do not depend on it. */
 ccpr_status ccpr_set_tile_planes(ccpr_solver* s, int planes);
+
+/* Launch shape: y rows per thread of the step kernel, 2 (default) or 4
+ * (4 only for nx <= 512: CCPR_ENOTSUP otherwise).  Results do not depend on
+ * it. */
+ccpr_status ccpr_set_tile_rows(ccpr_solver* s, int rows);
 
 #ifdef __cplusplus
 }

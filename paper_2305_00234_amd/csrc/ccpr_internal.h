@@ -24,7 +24,26 @@
 #include <stdint.h>
 
 #define CCPR_PMAX 8     // pole pairs per axis (both materials together)
-#define CCPR_ROWS 4     // y rows per thread in the fused step kernel
+#define CCPR_YPAD 4     // padded y extent is a multiple of this (largest strip height)
+
+// Field arrays (E, H, both buffers) are component-major (all x components,
+// then all y, then all z; component stride npad floats) and ghost-padded so the
+// step kernel never predicates a load: x is padded to nxp = nx rounded up to
+// 64, y to nyp = (ny rounded up to CCPR_YPAD) + 2 with one zero row below, z to
+// nzp = nz + 2 with one zero plane below and above.  Cell (i,j,k) of component
+// c lives at c*npad + ((k+1)*nyp + (j+1))*nxp + i; ghost cells are zero and
+// never written.  Kernels address fields with 32-bit byte offsets, so
+// 3*npad*4 must stay below 2^32.
+
+// One TF/SF face correction: field word at byte offset 'off' of E (or H),
+// incident table column m, coefficient coef (sign, side and Courant number
+// folded in); uidx = component * nx*ny*nz + (k*ny + j)*nx + i.
+struct TfEntry {
+    unsigned off;
+    int m;
+    float coef;
+    unsigned uidx;
+};
 
 struct AxisMat {
     float eps1, deps;   // eps'(rho) = eps1 + rho*deps
@@ -37,16 +56,11 @@ struct AxisMat {
     float br[CCPR_PMAX], bi[CCPR_PMAX];  // beta'_p
 };
 
-// Everything one fused leapfrog step needs.  Passed by value.
-struct StepArgs {
-    int nx, ny, nz;
-    long long plane;            // nx*ny
-    float S;                    // Courant number
-    const float* Ei[3];         // E^n
-    float* Eo[3];               // E^{n+1}
-    const float* Hi[3];         // H^{n-1/2}
-    float* Ho[3];               // H^{n+1/2}
-
+// Step data the kernel needs only inside rare branches (design voxels, CPML
+// layers, sources, TF/SF faces, the gap monitor, the gradient history).  It
+// lives in device memory (one block per state), so the hot loop keeps its
+// scalar registers for the field bases.
+struct StepCold {
     // design box
     int dlo[3], ddim[3];
     long long nd;
@@ -55,15 +69,16 @@ struct StepArgs {
     AxisMat mat[3];
 
     // CPML: per axis, (b, a, 1/kappa, 0) at integer (E) and half-integer (H)
-    // positions; psi slabs per derivative axis (see slab_index)
-    int npml;
+    // positions; psi memories per derivative axis, two components each
+    // (second component at +slab_size/2):
+    //   x: [k][j][xs], xs in [0,2 npml) (low layer then high layer)
+    //   y: [k][ys][i (nxp)], ys in [0,2 npml)
+    //   z: [zs][j][i (nxp)], zs in [0,2 npml)
     const float4* pmlE[3];
     const float4* pmlH[3];
     float* psiE[3];
-    const float* psiHi[3];
-    float* psiHo[3];
-
-    int n;                      // step index: this launch advances n -> n+1
+    float* psiH[2][3];          // [buffer][axis]; H-side psi is double-buffered
+                                // (read psi_in, write psi_in ^ 1)
 
     // current source on the E edges of a small box: src[(n*sncell + c)*3 + axis]
     int src_on, slo[3], sdim[3], sncell, snsteps;
@@ -72,59 +87,87 @@ struct StepArgs {
 
     // TF/SF plane wave (axis-aligned): incident E' at integer positions
     // [lo_d, hi_d] (row n = E^n) and H' at half-integer positions
-    // [lo_d-1, hi_d] (row n = H^{n+1/2}) along the propagation axis d.
-    int pw_on, pw_d, pw_p, pw_t, pwlo[3], pwhi[3], pw_spanE, pw_spanH;
-    float sg_Ep_d, sg_Ed_p, sg_Ht_d, sg_Hd_t;
+    // [lo_d-1, hi_d] (row n = H^{n+1/2}) along the propagation axis d, rows
+    // 0..tf_rows-1.  The face corrections are a list of field words (TfEntry):
+    // the first tf_nE add coef*incH[n][m] to E^{n+1} after step n, the next
+    // tf_nH add coef*incE[n][m] to H^{n-1/2} before step n reads it.
+    int pw_on, pw_spanE, pw_spanH, tf_rows, tf_nE, tf_nH;
     const float* incE;
     const float* incH;
+    const struct TfEntry* tf;
 
     // gap monitor: gap[((n+1)*gncell + c)*3 + axis] = E^{n+1}
     int gap_on, glo[3], gdim[3], gncell;
     float* gap;
 
-    float* Tout;                // forward record [3][nd] for this step, or null
-    const float* Tin;           // adjoint: forward factor paired with this step
+    float* T;                   // gradient history [slot][3][nd]
     double* grad;               // adjoint: per-voxel accumulator
+};
 
-    // launch geometry
-    int tz;                     // planes per block
+// Row classes (one word per (j,k), per state) and lane classes (one word per
+// x position): which rare work a row / a lane can need.
+#define CCPR_ROW_YPML 1u        // row inside a y CPML layer
+#define CCPR_ROW_ZPML 2u        // plane inside a z CPML layer
+#define CCPR_ROW_DES 4u         // row crosses the design box
+#define CCPR_ROW_SRC 8u         // row crosses the source box
+#define CCPR_LANE_PML 1u        // x inside a CPML layer
+#define CCPR_LANE_DES 2u        // x inside the design box
+#define CCPR_LANE_SRC 4u        // x inside the source box
+
+// Kernel argument of one leapfrog step (the fused grid kernel and the
+// auxiliary kernel of the design / source / gap cells share it).
+struct StepArgs {
+    const float* Ei;            // E^n (component-major, padded)
+    float* Eo;                  // E^{n+1}
+    const float* Hi;            // H^{n-1/2}
+    float* Ho;                  // H^{n+1/2}
+    const unsigned* rowf;       // row classes [k*ny + j]
+    const unsigned* lanef;      // lane classes [nxp]
+    float* drive;               // S curl H' of design voxels [3][nd], then source cells [sncell][3]
+    const int4* extra;          // non-design cells finished by the aux kernel: (i, j, k, kind)
+    long long nextra;
+    unsigned cstride;           // bytes between field components (npad*4)
+    int nx, ny, nz, nxp, nyp;
+    int rows;                   // y rows per thread (2 or 4)
+    int npml;
+    float S;                    // Courant number
+    int n;                      // step index: this launch advances n -> n+1
+    int psi_in;                 // which H-side psi buffer holds psi^{n-1/2}
+    int tslot;                  // gradient-history slot of this step (-1: none)
+    int mode;                   // CCPR_MODE_* bits
+    const StepCold* cold;
+    const int2* zr;             // plane range [k0, k1) of each logical z-chunk
     int nys;                    // y strips
-    int nblk;                   // total blocks
+    int nblk;                   // total blocks (nys * z-chunks)
 };
 
-struct SlabDims {
-    int nx, ny, nz, npml;
-};
+#define CCPR_EXTRA_SOURCE 1     // source cell outside the design box
+#define CCPR_EXTRA_GAP 2        // gap-monitor cell outside the design and source boxes
 
-// Index in the psi slab of derivative axis a for component slot ci (0: the
-// component (a+1)%3, 1: (a+2)%3), on side 0 (low) / 1 (high).
-__host__ __device__ inline long long slab_index(int a, int ci, int side, int i, int j, int k,
-                                                int nx, int ny, int nz, int npml)
-{
-    if (a == 0) {
-        int ii = side ? i - (nx - npml) : i;
-        return ((((long long)(ci * 2 + side) * nz + k) * ny + j) * npml + ii);
-    } else if (a == 1) {
-        int jj = side ? j - (ny - npml) : j;
-        return ((((long long)(ci * 2 + side) * nz + k) * npml + jj) * nx + i);
-    } else {
-        int kk = side ? k - (nz - npml) : k;
-        return ((((long long)(ci * 2 + side) * npml + kk) * ny + j) * nx + i);
-    }
-}
+#define CCPR_MODE_RECORD 1      // forward: write T of this step to slot tslot
+#define CCPR_MODE_CORREL 2      // adjoint: grad += E^{n+1} . T[tslot]
+#define CCPR_MODE_GAP 4         // forward: record the gap monitor
 
-__host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, int npml)
+// floats of the psi memory of derivative axis a (both components)
+__host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, int nxp, int npml)
 {
-    long long cross = a == 0 ? (long long)ny * nz : a == 1 ? (long long)nx * nz : (long long)nx * ny;
-    return 4LL * npml * cross;  // 2 components x 2 sides
+    const long long t = 2LL * npml;
+    return 2 * (a == 0 ? (long long)nz * ny * t : a == 1 ? (long long)nz * t * nxp : t * ny * nxp);
 }
 
 // Launchers (ccpr_kernels.hip)
-int ccpr_launch_step(const StepArgs& a, int maxpairs, void* stream);
+// fused grid step, then (naux > 0) the aux kernel over nd + nextra + tf_nE threads
+int ccpr_launch_step(const StepArgs& a, int maxpairs, long long naux, void* stream);
+// before a step: x-CPML and TF/SF corrections of H^{n-1/2} (nxs x-layer cells,
+// ntf TF/SF H words); after it: x-CPML of E^{n+1}
+int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* stream);
+int ccpr_launch_post(const StepArgs& a, long long nxs, void* stream);
 int ccpr_launch_fill(float* p, long long n, float v, void* stream);
 int ccpr_launch_fill_d(double* p, long long n, double v, void* stream);
 int ccpr_launch_copy(float* dst, const float* src, long long n, void* stream);
 int ccpr_launch_scale(float* dst, const float* src, long long n, float s, void* stream);
+int ccpr_launch_extract(float* dst, const float* src, int comp, int nx, int ny, int nz, int nxp, int nyp,
+                        float f, void* stream);
 int ccpr_launch_grad_out(double* dst, const double* acc, long long n, double s, void* stream);
 int ccpr_launch_copy_d(double* dst, const double* src, long long n, void* stream);
 int ccpr_launch_incident_line(const double* wave, int nw, int M, int L, double coef, int lo_d,

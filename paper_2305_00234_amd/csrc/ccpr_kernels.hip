@@ -1,17 +1,25 @@
 // gfx950 kernels of the CCPR-FDTD path.
 //
-// ccpr_step_kernel performs one full leapfrog step -- H^{n-1/2} -> H^{n+1/2}
-// (Faraday, supplement Eq. Maxwells2 c) and E^n -> E^{n+1} with the CCPR
-// pole-pair currents (Eqs. Maxwells2 a, b; interpolation Eqs. eps_mixed,
-// sigma_mixed, Poles_mixed) -- plus CPML, sources, TF/SF corrections, the gap
-// monitor, the forward gradient record and the adjoint gradient correlation
-// (Eq. Gradient_FDTD), in ONE pass over memory: every field word is read once
-// and written once per step (48 bytes per vacuum cell).
+// One leapfrog step -- H^{n-1/2} -> H^{n+1/2} (Faraday, supplement
+// Eq. Maxwells2 c) and E^n -> E^{n+1} with the CCPR pole-pair currents
+// (Eqs. Maxwells2 a, b; interpolation Eqs. eps_mixed, sigma_mixed,
+// Poles_mixed) -- is two launches:
+//  - ccpr_step_kernel streams the whole grid once (every E and H word read
+//    once and written once: 48 bytes per cell) and applies the vacuum update,
+//    the CPML memories and the TF/SF face corrections.  For design and source
+//    cells it also stores the E drive S curl H';
+//  - ccpr_aux_kernel, one thread per design voxel (plus the few source and gap
+//    cells outside the design), redoes those cells' E update from E^n and the
+//    drive: CCPR pole-pair currents, source current, the forward gradient
+//    record and the adjoint gradient correlation (Eq. Gradient_FDTD), and the
+//    gap monitor.
+// Keeping the dispersive work out of the grid kernel keeps the grid kernel's
+// loop at the register and instruction budget of a plain Yee update.
 //
-// Work decomposition (memory-bound stencil, no MFMA):
+// Grid kernel decomposition (memory-bound stencil, no MFMA):
 //  - a workgroup spans the whole x extent (blockDim = nx rounded up to 64),
-//    so x-neighbours come from wave shuffles plus one LDS word per wave seam;
-//  - each thread owns CCPR_ROWS consecutive y rows (register blocking) and the
+//    so x-neighbours come from DPP wave shifts plus one LDS word per wave seam;
+//  - each thread owns R consecutive y rows (register blocking) and the
 //    workgroup marches over a chunk of tz z-planes, keeping the previous
 //    plane's new H and the next plane's old E in registers;
 //  - H^{n+1/2} is recomputed on one halo row (y = j0-1) and one halo plane
@@ -27,8 +35,6 @@
 
 namespace {
 
-constexpr int R = CCPR_ROWS;
-
 __device__ __forceinline__ bool in_box(int i, int j, int k, const int* lo, const int* dim)
 {
     return (unsigned)(i - lo[0]) < (unsigned)dim[0] && (unsigned)(j - lo[1]) < (unsigned)dim[1] &&
@@ -40,89 +46,14 @@ __device__ __forceinline__ int box_index(int i, int j, int k, const int* lo, con
     return ((k - lo[2]) * dim[1] + (j - lo[1])) * dim[0] + (i - lo[0]);
 }
 
-// Stretched derivative on the H side: psi^{n+1/2} = b psi^{n-1/2} + a d,
-// returns d/kappa + psi.  Only the owner of the H point stores psi.
-template <int AX>
-__device__ __forceinline__ float pml_h(const StepArgs& a, int ci, int pos, int i, int j, int k,
-                                       float d, bool own)
-{
-    const int N = AX == 0 ? a.nx : AX == 1 ? a.ny : a.nz;
-    const int side = pos < a.npml ? 0 : 1;
-    (void)N;
-    const float4 cf = a.pmlH[AX][pos];
-    const long long s = slab_index(AX, ci, side, i, j, k, a.nx, a.ny, a.nz, a.npml);
-    const float psi = fmaf(cf.x, a.psiHi[AX][s], cf.y * d);
-    if (own) a.psiHo[AX][s] = psi;
-    return fmaf(d, cf.z, psi);
-}
-
-template <int AX>
-__device__ __forceinline__ float pml_e(const StepArgs& a, int ci, int pos, int i, int j, int k,
-                                       float d)
-{
-    const int side = pos < a.npml ? 0 : 1;
-    const float4 cf = a.pmlE[AX][pos];
-    const long long s = slab_index(AX, ci, side, i, j, k, a.nx, a.ny, a.nz, a.npml);
-    const float psi = fmaf(cf.x, a.psiE[AX][s], cf.y * d);
-    a.psiE[AX][s] = psi;
-    return fmaf(d, cf.z, psi);
-}
-
-__device__ __forceinline__ bool in_slab(int pos, int N, int npml)
-{
-    return npml > 0 && (pos < npml || pos >= N - npml);
-}
-
-// TF/SF correction to (curl E)_c at an H point (see host code for the face
-// bookkeeping): H just outside a face sees the total E on the face.
-__device__ __forceinline__ float tfsf_h(const StepArgs& a, int c, int cd, int cp, int ct)
-{
-    const int d = a.pw_d, p = a.pw_p, t = a.pw_t;
-    const float* inc = a.incE + (long long)a.n * a.pw_spanE;
-    const int lod = a.pwlo[d], hid = a.pwhi[d];
-    if (c == t) {
-        if (ct >= a.pwlo[t] && ct <= a.pwhi[t] && cp >= a.pwlo[p] && cp < a.pwhi[p]) {
-            if (cd == lod - 1) return -a.sg_Ht_d * inc[0];
-            if (cd == hid) return a.sg_Ht_d * inc[hid - lod];
-        }
-    } else if (c == d) {
-        if (cd >= lod && cd <= hid && cp >= a.pwlo[p] && cp < a.pwhi[p]) {
-            if (ct == a.pwlo[t] - 1) return -a.sg_Hd_t * inc[cd - lod];
-            if (ct == a.pwhi[t]) return a.sg_Hd_t * inc[cd - lod];
-        }
-    }
-    return 0.f;
-}
-
-// TF/SF correction to (curl H)_c at an E point on a face of the total-field
-// box: the E point is total, its outside H neighbour is scattered.
-__device__ __forceinline__ float tfsf_e(const StepArgs& a, int c, int cd, int cp, int ct)
-{
-    const int d = a.pw_d, p = a.pw_p, t = a.pw_t;
-    const float* inc = a.incH + (long long)a.n * a.pw_spanH;
-    const int lod = a.pwlo[d], hid = a.pwhi[d];
-    if (c == p) {
-        if (ct >= a.pwlo[t] && ct <= a.pwhi[t] && cp >= a.pwlo[p] && cp < a.pwhi[p]) {
-            if (cd == lod) return -a.sg_Ep_d * inc[0];
-            if (cd == hid) return a.sg_Ep_d * inc[hid - lod + 1];
-        }
-    } else if (c == d) {
-        if (ct >= a.pwlo[t] && ct <= a.pwhi[t] && cd >= lod && cd < hid) {
-            if (cp == a.pwlo[p]) return -a.sg_Ed_p * inc[cd - lod + 1];
-            if (cp == a.pwhi[p]) return a.sg_Ed_p * inc[cd - lod + 1];
-        }
-    }
-    return 0.f;
-}
-
 // Dispersive E update of component C at design voxel v (see ccpr_internal.h).
 // sh (may be null): FP64 shadow of E on a source edge; E^{n+1} is then
 // accumulated in FP64 and rounded once.
 template <int C, int PMAX>
-__device__ __forceinline__ float e_disp(const StepArgs& a, float E, float drive, float rho,
+__device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive, float rho,
                                         long long v, float* T, double* sh)
 {
-    const AxisMat& m = a.mat[C];
+    const AxisMat& m = c.mat[C];
     const float om = 1.f - rho;
     const float eps = fmaf(rho, m.deps, m.eps1);
     const float sig = fmaf(rho, m.dsig, m.sig1) + rho * om * m.gam;
@@ -133,8 +64,8 @@ __device__ __forceinline__ float e_disp(const StepArgs& a, float E, float drive,
     for (int p = 0; p < PMAX; ++p) {
         if (p < m.np) {
             const long long q = m.jofs + p;
-            jr[p] = a.J[(2 * q) * a.nd + v];
-            ji[p] = a.J[(2 * q + 1) * a.nd + v];
+            jr[p] = c.J[(2 * q) * c.nd + v];
+            ji[p] = c.J[(2 * q + 1) * c.nd + v];
             const float kap = p < m.np1 ? om : rho;
             A = fmaf(kap, m.br[p], A);
             // Re{(1 + k_p) J} with 1 + k_p = 2 + (k_p - 1)
@@ -155,8 +86,8 @@ __device__ __forceinline__ float e_disp(const StepArgs& a, float E, float drive,
             // J^{n+1} = J + (k_p - 1) J + beta'_p dE
             const float nr = jr[p] + fmaf(m.kr[p], jr[p], fmaf(-m.ki[p], ji[p], m.br[p] * dE));
             const float ni = ji[p] + fmaf(m.kr[p], ji[p], fmaf(m.ki[p], jr[p], m.bi[p] * dE));
-            a.J[(2 * q) * a.nd + v] = nr;
-            a.J[(2 * q + 1) * a.nd + v] = ni;
+            c.J[(2 * q) * c.nd + v] = nr;
+            c.J[(2 * q + 1) * c.nd + v] = ni;
             rnew += p < m.np1 ? -nr : nr;
         }
     }
@@ -164,120 +95,193 @@ __device__ __forceinline__ float e_disp(const StepArgs& a, float E, float drive,
     return En;
 }
 
-template <int PMAX>
-__global__ __launch_bounds__(1024) void ccpr_step_kernel(const StepArgs a)
+// x-neighbour exchange on the 64 lanes of a wave (DPP wave shifts, one VALU
+// op each): lane i receives lane i+1 (shl) / lane i-1 (shr); the lane at the
+// wave seam receives 'edge' instead.
+__device__ __forceinline__ float from_right(float v, float edge)
+{
+    return __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+__device__ __forceinline__ float from_left(float v, float edge)
+{
+    return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+
+
+// 32-bit byte offsets from a uniform base: lets the compiler use the
+// SGPR-base + VGPR-offset addressing form (no 64-bit address math per access).
+__device__ __forceinline__ float ldf(const float* base, unsigned boff)
+{
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
+}
+__device__ __forceinline__ void stf(float* base, unsigned boff, float v)
+{
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
+// CPML memory update on one derivative d with the old memory p:
+// p' = b p + a d (stored by the owner only); returns d/kappa + p'.
+__device__ __forceinline__ float cpml(float d, float4 cf, float p, float* pout, unsigned idx, bool store)
+{
+    const float q = fmaf(cf.x, p, cf.y * d);
+    if (store) pout[idx] = q;
+    return fmaf(d, cf.z, q);
+}
+
+// Fused leapfrog step over the whole grid: vacuum update of H and E with the
+// y and z CPML.  For design and source cells the E drive S (curl H) is also
+// stored; ccpr_aux_kernel then finishes those cells and the TF/SF E faces.
+// The x CPML and the TF/SF H faces are applied to H^{n-1/2} beforehand by
+// ccpr_pre_kernel, the x CPML of E^{n+1} afterwards by ccpr_post_kernel: the
+// x layers then cost no extra work inside the x-spanning workgroup.
+// R = 2 rows per thread for any nx (blockDim up to 1024); R = 4 keeps more
+// rows in registers and is limited to blockDim <= 512.
+template <int R>
+__global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const StepArgs a)
 {
     __shared__ float xe[2][R + 1][16];
     __shared__ float xh[2][R][16];
+    const StepCold& c = *a.cold;
 
     // XCD-aware tile order: hardware hands workgroups to the 8 XCDs round
-    // robin; give each XCD a contiguous range of logical tiles.
+    // robin; give each XCD a contiguous range of logical tiles (neighbouring
+    // y-strips share halo rows in that XCD's L2).  Logical z-chunk zl covers
+    // planes zr[zl] = [k0, k1): the host sizes chunks to equal work (CPML
+    // planes cost more) and spreads them over the XCDs.
     const int b = blockIdx.x;
     const int per = a.nblk >> 3, rem = a.nblk & 7;
     const int xcd = b & 7, q = b >> 3;
     const int L = xcd * per + (xcd < rem ? xcd : rem) + q;
-    const int ys = L % a.nys, zc = L / a.nys;
+    const int ys = L % a.nys, zl = L / a.nys;
+    const int2 kr = a.zr[zl];
     const int j0 = ys * R;
-    const int k0 = zc * a.tz;
-    const int k1 = min(k0 + a.tz, a.nz);
+    const int k0 = kr.x, k1 = kr.y;
 
     const int i = threadIdx.x;
-    const int lane = i & 63, w = i >> 6, nw = blockDim.x >> 6;
+    const int lane = i & 63;
+    const int w = __builtin_amdgcn_readfirstlane(i >> 6);
+    const int nw = blockDim.x >> 6;
     const bool xin = i < a.nx;
     const float S = a.S;
-    const bool xpml = in_slab(i, a.nx, a.npml);
+    const unsigned nxp = a.nxp, nyp = a.nyp, cs = a.cstride;
+    const int npml = a.npml;
+    const int ny = a.ny, nz = a.nz;
+    const unsigned lf = a.lanef[i];
+    const bool anypml = npml > 0;
+    const unsigned np2 = 2u * (unsigned)npml;
+    const unsigned szy = (unsigned)nz * np2 * nxp;
+    const unsigned szz = np2 * ny * nxp;
+    const float* const* psiHi = c.psiH[a.psi_in];
+    float* const* psiHo = c.psiH[a.psi_in ^ 1];
 
-    // registers: E^n on the current plane (rows j0-1 .. j0+R), next plane,
-    // H^{n+1/2} of the previous plane (x, y comps, rows j0 .. j0+R-1)
-    float ex[R + 2], ey[R + 2], ez[R + 2];
-    float nex[R + 2], ney[R + 2], nez[R + 2];
-    float hxm[R + 1], hym[R + 1];
-    float hx[R + 1], hy[R + 1], hz[R + 1];
-
-    auto row_ok = [&](int j, int k) { return xin && j >= 0 && j < a.ny && k >= 0 && k < a.nz; };
-    auto load_plane = [&](int k, float* px, float* py, float* pz) {
-#pragma unroll
-        for (int r = 0; r < R + 2; ++r) {
-            const int j = j0 - 1 + r;
-            const bool ok = row_ok(j, k);
-            const long long o = (long long)k * a.plane + (long long)j * a.nx + i;
-            px[r] = ok ? a.Ei[0][o] : 0.f;
-            py[r] = (ok && r <= R) ? a.Ei[1][o] : 0.f;
-            pz[r] = ok ? a.Ei[2][o] : 0.f;
-        }
+    auto poff = [&](int k, int r) -> unsigned {
+        return (((unsigned)(k + 1) * nyp + (unsigned)(j0 + r)) * nxp + (unsigned)i) * 4u;
+    };
+    auto yidx = [&](int k, int j) -> unsigned {
+        const int ysl = j < npml ? j : j - (ny - npml) + npml;
+        return ((unsigned)k * np2 + ysl) * nxp + i;
+    };
+    auto zidx = [&](int k, int j) -> unsigned {
+        const int zsl = k < npml ? k : k - (nz - npml) + npml;
+        return ((unsigned)zsl * ny + j) * nxp + i;
     };
 
-    load_plane(k0 - 1, ex, ey, ez);
+    float ex[R + 2], ey[R + 2], ez[R + 2];     // E^n, plane kk
+    float nex[R + 2], ney[R + 2], nez[R + 2];  // E^n, plane kk+1
+    float hxm[R + 1], hym[R + 1];              // H^{n+1/2}, plane kk-1
+    float hx[R + 1], hy[R + 1], hz[R + 1];     // H^{n+1/2}, plane kk
+
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) {
+        const unsigned o = poff(k0 - 1, r);
+        ex[r] = ldf(a.Ei, o);
+        ey[r] = ldf(a.Ei, o + cs);
+        ez[r] = ldf(a.Ei, o + 2 * cs);
+    }
 #pragma unroll
     for (int r = 0; r <= R; ++r) { hxm[r] = 0.f; hym[r] = 0.f; }
 
     for (int kk = k0 - 1; kk < k1; ++kk) {
-        load_plane(kk + 1, nex, ney, nez);
+        // ---- loads: E^n of plane kk+1, H^{n-1/2} of plane kk (unconditional;
+        // ghost rows and planes are zero)
+        float hxo[R + 1], hyo[R + 1], hzo[R + 1];
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) {
+            const unsigned o = poff(kk + 1, r);
+            nex[r] = ldf(a.Ei, o);
+            ney[r] = ldf(a.Ei, o + cs);
+            nez[r] = ldf(a.Ei, o + 2 * cs);
+        }
+#pragma unroll
+        for (int r = 0; r <= R; ++r) {
+            const unsigned o = poff(kk, r);
+            hxo[r] = ldf(a.Hi, o);
+            hyo[r] = ldf(a.Hi, o + cs);
+            hzo[r] = ldf(a.Hi, o + 2 * cs);
+        }
 
-        // ---- x+1 neighbours of E^n on this plane (Ey rows 0..R, Ez rows 0..R)
+        // ---- row classes of this plane.  Row r is H row j0-1+r; E rows are r = 1..R.
+        bool rowv[R + 1];
+        unsigned rf[R + 1];
+#pragma unroll
+        for (int r = 0; r <= R; ++r) {
+            const int j = j0 - 1 + r;
+            rowv[r] = j >= 0 && j < ny && kk >= 0;
+            rf[r] = rowv[r] ? a.rowf[(unsigned)kk * ny + j] : 0u;
+        }
+
+        // ---- E^n at x+1 (Ey, Ez on rows 0..R)
         if (lane == 0) {
 #pragma unroll
             for (int r = 0; r <= R; ++r) { xe[0][r][w] = ey[r]; xe[1][r][w] = ez[r]; }
         }
         __syncthreads();
         float eyr[R + 1], ezr[R + 1];
+        const bool has_right = w + 1 < nw;
 #pragma unroll
         for (int r = 0; r <= R; ++r) {
-            eyr[r] = __shfl_down(ey[r], 1);
-            ezr[r] = __shfl_down(ez[r], 1);
-            if (lane == 63) {
-                eyr[r] = (w + 1 < nw) ? xe[0][r][w + 1] : 0.f;
-                ezr[r] = (w + 1 < nw) ? xe[1][r][w + 1] : 0.f;
-            }
+            eyr[r] = from_right(ey[r], has_right ? xe[0][r][w + 1] : 0.f);
+            ezr[r] = from_right(ez[r], has_right ? xe[1][r][w + 1] : 0.f);
         }
 
         // ---- H^{n+1/2} on rows j0-1 .. j0+R-1 of plane kk
-        const bool kok = kk >= 0;
-        const bool zpml = in_slab(kk, a.nz, a.npml);
 #pragma unroll
         for (int r = 0; r <= R; ++r) {
             const int j = j0 - 1 + r;
-            const bool ok = kok && row_ok(j, kk);
-            const bool own = ok && r >= 1 && kk >= k0;
-            const long long o = (long long)kk * a.plane + (long long)j * a.nx + i;
-            float hxo = 0.f, hyo = 0.f, hzo = 0.f;
-            if (ok) { hxo = a.Hi[0][o]; hyo = a.Hi[1][o]; hzo = a.Hi[2][o]; }
-            // Hx: d1 = y (Ez), d2 = z (Ey);  Hy: d1 = z (Ex), d2 = x (Ez);
-            // Hz: d1 = x (Ey), d2 = y (Ex)   -- forward differences
+            const bool own = rowv[r] && r >= 1 && kk >= k0;    // uniform
+            // Hx: y-derivative of Ez minus z-derivative of Ey; Hy: z of Ex minus
+            // x of Ez; Hz: x of Ey minus y of Ex -- forward differences
             float dxA = ez[r + 1] - ez[r], dxB = ney[r] - ey[r];
             float dyA = nex[r] - ex[r], dyB = ezr[r] - ez[r];
             float dzA = eyr[r] - ey[r], dzB = ex[r + 1] - ex[r];
-            if (ok && a.npml > 0) {
-                const bool ypml = in_slab(j, a.ny, a.npml);
-                if (ypml) {
-                    dxA = pml_h<1>(a, 1, j, i, j, kk, dxA, own);
-                    dzB = pml_h<1>(a, 0, j, i, j, kk, dzB, own);
+            if (anypml) {
+                if (rf[r] & CCPR_ROW_YPML) {
+                    const float4 cf = c.pmlH[1][j];
+                    const unsigned y = yidx(kk, j);
+                    const float q0 = psiHi[1][szy + y], q1 = psiHi[1][y];
+                    dxA = cpml(dxA, cf, q0, psiHo[1], szy + y, own && xin);
+                    dzB = cpml(dzB, cf, q1, psiHo[1], y, own && xin);
                 }
-                if (zpml) {
-                    dxB = pml_h<2>(a, 0, kk, i, j, kk, dxB, own);
-                    dyA = pml_h<2>(a, 1, kk, i, j, kk, dyA, own);
-                }
-                if (xpml) {
-                    dyB = pml_h<0>(a, 0, i, i, j, kk, dyB, own);
-                    dzA = pml_h<0>(a, 1, i, i, j, kk, dzA, own);
+                if (rf[r] & CCPR_ROW_ZPML) {
+                    const float4 cf = c.pmlH[2][kk];
+                    const unsigned z = zidx(kk, j);
+                    const float q0 = psiHi[2][z], q1 = psiHi[2][szz + z];
+                    dxB = cpml(dxB, cf, q0, psiHo[2], z, own && xin);
+                    dyA = cpml(dyA, cf, q1, psiHo[2], szz + z, own && xin);
                 }
             }
-            float cx = dxA - dxB, cy = dyA - dyB, cz = dzA - dzB;
-            if (a.pw_on && ok) {
-                const int cd = a.pw_d == 0 ? i : a.pw_d == 1 ? j : kk;
-                const int cp = a.pw_p == 0 ? i : a.pw_p == 1 ? j : kk;
-                const int ct = a.pw_t == 0 ? i : a.pw_t == 1 ? j : kk;
-                cx += tfsf_h(a, 0, cd, cp, ct);
-                cy += tfsf_h(a, 1, cd, cp, ct);
-                cz += tfsf_h(a, 2, cd, cp, ct);
+            hx[r] = fmaf(-S, dxA - dxB, hxo[r]);
+            hy[r] = fmaf(-S, dyA - dyB, hyo[r]);
+            hz[r] = fmaf(-S, dzA - dzB, hzo[r]);
+            if (own && xin) {
+                const unsigned o = poff(kk, r);
+                stf(a.Ho, o, hx[r]);
+                stf(a.Ho, o + cs, hy[r]);
+                stf(a.Ho, o + 2 * cs, hz[r]);
             }
-            hx[r] = ok ? fmaf(-S, cx, hxo) : 0.f;
-            hy[r] = ok ? fmaf(-S, cy, hyo) : 0.f;
-            hz[r] = ok ? fmaf(-S, cz, hzo) : 0.f;
-            if (own) { a.Ho[0][o] = hx[r]; a.Ho[1][o] = hy[r]; a.Ho[2][o] = hz[r]; }
         }
 
-        // ---- x-1 neighbours of H^{n+1/2} (Hy, Hz rows 1..R)
+        // ---- H^{n+1/2} at x-1 (Hy, Hz on rows 1..R)
         if (lane == 63) {
 #pragma unroll
             for (int r = 1; r <= R; ++r) { xh[0][r - 1][w] = hy[r]; xh[1][r - 1][w] = hz[r]; }
@@ -286,106 +290,62 @@ __global__ __launch_bounds__(1024) void ccpr_step_kernel(const StepArgs a)
         float hyl[R + 1], hzl[R + 1];
 #pragma unroll
         for (int r = 1; r <= R; ++r) {
-            hyl[r] = __shfl_up(hy[r], 1);
-            hzl[r] = __shfl_up(hz[r], 1);
-            if (lane == 0) {
-                hyl[r] = w > 0 ? xh[0][r - 1][w - 1] : 0.f;
-                hzl[r] = w > 0 ? xh[1][r - 1][w - 1] : 0.f;
-            }
+            hyl[r] = from_left(hy[r], w > 0 ? xh[0][r - 1][w - 1] : 0.f);
+            hzl[r] = from_left(hz[r], w > 0 ? xh[1][r - 1][w - 1] : 0.f);
         }
 
         // ---- E^{n+1} on rows j0 .. j0+R-1 of plane kk
         if (kk >= k0) {
-            const bool zp = in_slab(kk, a.nz, a.npml);
 #pragma unroll
             for (int r = 1; r <= R; ++r) {
                 const int j = j0 - 1 + r;
-                if (!row_ok(j, kk)) continue;
-                const long long o = (long long)kk * a.plane + (long long)j * a.nx + i;
-                // (curl H)_x: d1 = y (Hz), d2 = z (Hy); (curl H)_y: d1 = z (Hx),
-                // d2 = x (Hz); (curl H)_z: d1 = x (Hy), d2 = y (Hx)  -- backward
+                if (j >= ny) continue;  // uniform
+                // (curl H)_x: y-derivative of Hz minus z-derivative of Hy;
+                // (curl H)_y: z of Hx minus x of Hz; (curl H)_z: x of Hy minus
+                // y of Hx -- backward differences
                 float gxA = hz[r] - hz[r - 1], gxB = hy[r] - hym[r];
                 float gyA = hx[r] - hxm[r], gyB = hz[r] - hzl[r];
                 float gzA = hy[r] - hyl[r], gzB = hx[r] - hx[r - 1];
-                if (a.npml > 0) {
-                    if (in_slab(j, a.ny, a.npml)) {
-                        gxA = pml_e<1>(a, 1, j, i, j, kk, gxA);
-                        gzB = pml_e<1>(a, 0, j, i, j, kk, gzB);
+                if (anypml) {
+                    if (rf[r] & CCPR_ROW_YPML) {
+                        const float4 cf = c.pmlE[1][j];
+                        const unsigned y = yidx(kk, j);
+                        const float q0 = c.psiE[1][szy + y], q1 = c.psiE[1][y];
+                        gxA = cpml(gxA, cf, q0, c.psiE[1], szy + y, xin);
+                        gzB = cpml(gzB, cf, q1, c.psiE[1], y, xin);
                     }
-                    if (zp) {
-                        gxB = pml_e<2>(a, 0, kk, i, j, kk, gxB);
-                        gyA = pml_e<2>(a, 1, kk, i, j, kk, gyA);
-                    }
-                    if (xpml) {
-                        gyB = pml_e<0>(a, 0, i, i, j, kk, gyB);
-                        gzA = pml_e<0>(a, 1, i, i, j, kk, gzA);
+                    if (rf[r] & CCPR_ROW_ZPML) {
+                        const float4 cf = c.pmlE[2][kk];
+                        const unsigned z = zidx(kk, j);
+                        const float q0 = c.psiE[2][z], q1 = c.psiE[2][szz + z];
+                        gxB = cpml(gxB, cf, q0, c.psiE[2], z, xin);
+                        gyA = cpml(gyA, cf, q1, c.psiE[2], szz + z, xin);
                     }
                 }
-                float cx = gxA - gxB, cy = gyA - gyB, cz = gzA - gzB;
-                if (a.pw_on) {
-                    const int cd = a.pw_d == 0 ? i : a.pw_d == 1 ? j : kk;
-                    const int cp = a.pw_p == 0 ? i : a.pw_p == 1 ? j : kk;
-                    const int ct = a.pw_t == 0 ? i : a.pw_t == 1 ? j : kk;
-                    cx += tfsf_e(a, 0, cd, cp, ct);
-                    cy += tfsf_e(a, 1, cd, cp, ct);
-                    cz += tfsf_e(a, 2, cd, cp, ct);
-                }
-                float dx_ = S * cx, dy_ = S * cy, dz_ = S * cz;
-                double* sh = nullptr;  // FP64 shadow of E on source edges
-                if (a.src_on && in_box(i, j, kk, a.slo, a.sdim)) {
-                    const int ci = box_index(i, j, kk, a.slo, a.sdim);
-                    if (a.n < a.snsteps) {
-                        const float* s = a.src + ((long long)a.n * a.sncell + ci) * 3;
-                        dx_ -= s[0];
-                        dy_ -= s[1];
-                        dz_ -= s[2];
-                    }
-                    if (a.ssh) sh = a.ssh + (long long)ci * 3;
-                }
-                const float e0x = ex[r], e0y = ey[r], e0z = ez[r];
-                float nxv, nyv, nzv;
-                if (PMAX >= 0 && a.nd > 0 && in_box(i, j, kk, a.dlo, a.ddim)) {
-                    const long long v = box_index(i, j, kk, a.dlo, a.ddim);
-                    const float rho = a.rho[v];
-                    float Tx, Ty, Tz;
-                    nxv = e_disp<0, PMAX>(a, e0x, dx_, rho, v, &Tx, sh);
-                    nyv = e_disp<1, PMAX>(a, e0y, dy_, rho, v, &Ty, sh ? sh + 1 : nullptr);
-                    nzv = e_disp<2, PMAX>(a, e0z, dz_, rho, v, &Tz, sh ? sh + 2 : nullptr);
-                    if (j == 0 || kk == 0) nxv = 0.f;  // never inside a valid design box
-                    if (a.Tout) {
-                        a.Tout[v] = Tx;
-                        a.Tout[a.nd + v] = Ty;
-                        a.Tout[2 * a.nd + v] = Tz;
-                    }
-                    if (a.Tin) {
-                        const double g = (double)nxv * a.Tin[v] + (double)nyv * a.Tin[a.nd + v] +
-                                         (double)nzv * a.Tin[2 * a.nd + v];
-                        a.grad[v] += g;
-                    }
-                } else if (sh) {
-                    sh[0] += (double)dx_;
-                    sh[1] += (double)dy_;
-                    sh[2] += (double)dz_;
-                    nxv = (float)sh[0];
-                    nyv = (float)sh[1];
-                    nzv = (float)sh[2];
-                } else {
-                    nxv = e0x + dx_;
-                    nyv = e0y + dy_;
-                    nzv = e0z + dz_;
-                }
+                const float dx_ = S * (gxA - gxB), dy_ = S * (gyA - gyB), dz_ = S * (gzA - gzB);
+                float nxv = ex[r] + dx_, nyv = ey[r] + dy_, nzv = ez[r] + dz_;
                 // tangential E on the walls stays zero
                 if (j == 0 || kk == 0) nxv = 0.f;
-                if (i == 0 || kk == 0) nyv = 0.f;
-                if (i == 0 || j == 0) nzv = 0.f;
-                a.Eo[0][o] = nxv;
-                a.Eo[1][o] = nyv;
-                a.Eo[2][o] = nzv;
-                if (a.gap_on && in_box(i, j, kk, a.glo, a.gdim)) {
-                    float* g = a.gap + ((long long)(a.n + 1) * a.gncell + box_index(i, j, kk, a.glo, a.gdim)) * 3;
-                    g[0] = nxv;
-                    g[1] = nyv;
-                    g[2] = nzv;
+                if (kk == 0) nyv = 0.f;
+                if (j == 0) nzv = 0.f;
+                if (i == 0) { nyv = 0.f; nzv = 0.f; }
+                if (xin) {
+                    const unsigned o = poff(kk, r);
+                    stf(a.Eo, o, nxv);
+                    stf(a.Eo, o + cs, nyv);
+                    stf(a.Eo, o + 2 * cs, nzv);
+                }
+                // design / source cells: hand the drive to the aux kernel
+                if ((rf[r] & CCPR_ROW_DES) && (lf & CCPR_LANE_DES)) {
+                    const long long v = box_index(i, j, kk, c.dlo, c.ddim);
+                    a.drive[v] = dx_;
+                    a.drive[c.nd + v] = dy_;
+                    a.drive[2 * c.nd + v] = dz_;
+                } else if ((rf[r] & CCPR_ROW_SRC) && (lf & CCPR_LANE_SRC)) {
+                    float* d = a.drive + 3 * c.nd + (long long)box_index(i, j, kk, c.slo, c.sdim) * 3;
+                    d[0] = dx_;
+                    d[1] = dy_;
+                    d[2] = dz_;
                 }
             }
         }
@@ -396,6 +356,193 @@ __global__ __launch_bounds__(1024) void ccpr_step_kernel(const StepArgs a)
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) { ex[r] = nex[r]; ey[r] = ney[r]; ez[r] = nez[r]; }
     }
+}
+
+// Finish the cells the fused step left to it, one thread per cell or word:
+//  - design voxels (threads [0, nd)): CCPR pole-pair update of the three E
+//    edges from E^n and the stored drive (minus a source current if the voxel
+//    is also a source cell), the gradient record (forward) or correlation
+//    (adjoint), and the gap monitor;
+//  - extra cells (threads [nd, nd+nextra)): source cells outside the design
+//    (vacuum update with FP64 accumulation) and gap cells outside both;
+//  - TF/SF E face words (the next tf_nE threads).  Their cells lie outside
+//    the design, source and gap boxes, so no two threads touch one word.
+// E^{n+1} of these cells is written over the fused kernel's vacuum value.
+template <int PMAX>
+__global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
+{
+    const StepCold& c = *a.cold;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned cs = a.cstride;
+    const int n = a.n;
+    if (t < c.nd) {
+        const long long v = t;
+        const int i = c.dlo[0] + (int)(v % c.ddim[0]);
+        const long long u = v / c.ddim[0];
+        const int j = c.dlo[1] + (int)(u % c.ddim[1]);
+        const int kk = c.dlo[2] + (int)(u / c.ddim[1]);
+        const unsigned o = (((unsigned)(kk + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
+        const float e0x = ldf(a.Ei, o), e0y = ldf(a.Ei, o + cs), e0z = ldf(a.Ei, o + 2 * cs);
+        float dx_ = a.drive[v], dy_ = a.drive[c.nd + v], dz_ = a.drive[2 * c.nd + v];
+        double* sh = nullptr;
+        if (c.src_on && in_box(i, j, kk, c.slo, c.sdim)) {
+            const int ci = box_index(i, j, kk, c.slo, c.sdim);
+            if (n < c.snsteps) {
+                const float* s = c.src + ((long long)n * c.sncell + ci) * 3;
+                dx_ -= s[0];
+                dy_ -= s[1];
+                dz_ -= s[2];
+            }
+            if (c.ssh) sh = c.ssh + (long long)ci * 3;
+        }
+        const float rho = c.rho[v];
+        float Tx, Ty, Tz;
+        const float nxv = e_disp<0, PMAX>(c, e0x, dx_, rho, v, &Tx, sh);
+        const float nyv = e_disp<1, PMAX>(c, e0y, dy_, rho, v, &Ty, sh ? sh + 1 : nullptr);
+        const float nzv = e_disp<2, PMAX>(c, e0z, dz_, rho, v, &Tz, sh ? sh + 2 : nullptr);
+        stf(a.Eo, o, nxv);
+        stf(a.Eo, o + cs, nyv);
+        stf(a.Eo, o + 2 * cs, nzv);
+        if (a.mode & CCPR_MODE_RECORD) {
+            float* T = c.T + (long long)a.tslot * 3 * c.nd;
+            T[v] = Tx;
+            T[c.nd + v] = Ty;
+            T[2 * c.nd + v] = Tz;
+        }
+        if (a.mode & CCPR_MODE_CORREL) {
+            const float* T = c.T + (long long)a.tslot * 3 * c.nd;
+            c.grad[v] += (double)nxv * T[v] + (double)nyv * T[c.nd + v] + (double)nzv * T[2 * c.nd + v];
+        }
+        if ((a.mode & CCPR_MODE_GAP) && in_box(i, j, kk, c.glo, c.gdim)) {
+            float* g = c.gap + ((long long)(n + 1) * c.gncell + box_index(i, j, kk, c.glo, c.gdim)) * 3;
+            g[0] = nxv;
+            g[1] = nyv;
+            g[2] = nzv;
+        }
+        return;
+    }
+    const long long e = t - c.nd;
+    if (e >= a.nextra) {
+        // TF/SF E faces: E^{n+1} += coef*incH[n][m]
+        const long long f = e - a.nextra;
+        if (f < c.tf_nE) {
+            const TfEntry q = c.tf[f];
+            if (n < c.tf_rows) stf(a.Eo, q.off, ldf(a.Eo, q.off) + q.coef * c.incH[(long long)n * c.pw_spanH + q.m]);
+        }
+        return;
+    }
+    const int4 cell = a.extra[e];  // (i, j, k, CCPR_EXTRA_*)
+    const int i = cell.x, j = cell.y, kk = cell.z;
+    const unsigned o = (((unsigned)(kk + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
+    float nxv, nyv, nzv;
+    if (cell.w == CCPR_EXTRA_SOURCE) {
+        const int ci = box_index(i, j, kk, c.slo, c.sdim);
+        const float* d = a.drive + 3 * c.nd + (long long)ci * 3;
+        float dx_ = d[0], dy_ = d[1], dz_ = d[2];
+        if (n < c.snsteps) {
+            const float* s = c.src + ((long long)n * c.sncell + ci) * 3;
+            dx_ -= s[0];
+            dy_ -= s[1];
+            dz_ -= s[2];
+        }
+        double* sh = c.ssh + (long long)ci * 3;
+        sh[0] += (double)dx_;
+        sh[1] += (double)dy_;
+        sh[2] += (double)dz_;
+        nxv = (float)sh[0];
+        nyv = (float)sh[1];
+        nzv = (float)sh[2];
+        // tangential E on the walls stays zero
+        if (j == 0 || kk == 0) nxv = 0.f;
+        if (i == 0 || kk == 0) nyv = 0.f;
+        if (i == 0 || j == 0) nzv = 0.f;
+        stf(a.Eo, o, nxv);
+        stf(a.Eo, o + cs, nyv);
+        stf(a.Eo, o + 2 * cs, nzv);
+    } else {
+        nxv = ldf(a.Eo, o);
+        nyv = ldf(a.Eo, o + cs);
+        nzv = ldf(a.Eo, o + 2 * cs);
+    }
+    if ((a.mode & CCPR_MODE_GAP) && in_box(i, j, kk, c.glo, c.gdim)) {
+        float* g = c.gap + ((long long)(n + 1) * c.gncell + box_index(i, j, kk, c.glo, c.gdim)) * 3;
+        g[0] = nxv;
+        g[1] = nyv;
+        g[2] = nzv;
+    }
+}
+
+// Before step n: corrections to H^{n-1/2} (a.Hi) that turn the grid
+// kernel's vacuum Faraday update into the full one.
+//  - x CPML (threads [0, 2 npml ny nz)): with d the forward x-difference of
+//    E^n, psi' = b psi + a d and d -> d/kappa + psi', so
+//    Hy += S((1/kappa - 1) d(Ez) + psi'),  Hz -= S((1/kappa - 1) d(Ey) + psi');
+//  - TF/SF H faces (the next tf_nH threads): H += coef*incE[n][m].
+__global__ __launch_bounds__(256) void ccpr_pre_kernel(const StepArgs a, long long nxs)
+{
+    const StepCold& c = *a.cold;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    float* H = const_cast<float*>(a.Hi);
+    const unsigned cs = a.cstride;
+    if (t < nxs) {
+        const int np2 = 2 * a.npml;
+        const int xs = (int)(t % np2);
+        const long long u = t / np2;
+        const int j = (int)(u % a.ny), k = (int)(u / a.ny);
+        const int i = xs < a.npml ? xs : a.nx - np2 + xs;
+        const unsigned o = (((unsigned)(k + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
+        const bool right = i + 1 < a.nx;
+        const float dEz = (right ? ldf(a.Ei, o + 4 + 2 * cs) : 0.f) - ldf(a.Ei, o + 2 * cs);
+        const float dEy = (right ? ldf(a.Ei, o + 4 + cs) : 0.f) - ldf(a.Ei, o + cs);
+        const float4 cf = c.pmlH[0][i];
+        const unsigned x = (unsigned)u * np2 + xs;
+        const unsigned sz = (unsigned)a.nz * a.ny * np2;
+        const float* pin = c.psiH[a.psi_in][0];
+        float* pout = c.psiH[a.psi_in ^ 1][0];
+        const float p0 = fmaf(cf.x, pin[x], cf.y * dEz);
+        const float p1 = fmaf(cf.x, pin[sz + x], cf.y * dEy);
+        pout[x] = p0;
+        pout[sz + x] = p1;
+        stf(H, o + cs, ldf(H, o + cs) + a.S * fmaf(cf.z - 1.f, dEz, p0));
+        stf(H, o + 2 * cs, ldf(H, o + 2 * cs) - a.S * fmaf(cf.z - 1.f, dEy, p1));
+        return;
+    }
+    const long long f = t - nxs;
+    if (c.pw_on && f < c.tf_nH && a.n < c.tf_rows) {
+        const TfEntry q = c.tf[c.tf_nE + f];
+        stf(H, q.off, ldf(H, q.off) + q.coef * c.incE[(long long)a.n * c.pw_spanE + q.m]);
+    }
+}
+
+// After step n (grid and aux kernels): the x CPML of E^{n+1} (a.Eo) from
+// H^{n+1/2} (a.Ho), with d the backward x-difference of H:
+//   Ey -= S((1/kappa - 1) d(Hz) + psi'),  Ez += S((1/kappa - 1) d(Hy) + psi').
+// Tangential E on the walls stays zero.
+__global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long long nxs)
+{
+    const StepCold& c = *a.cold;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nxs) return;
+    const unsigned cs = a.cstride;
+    const int np2 = 2 * a.npml;
+    const int xs = (int)(t % np2);
+    const long long u = t / np2;
+    const int j = (int)(u % a.ny), k = (int)(u / a.ny);
+    const int i = xs < a.npml ? xs : a.nx - np2 + xs;
+    if (i == 0) return;
+    const unsigned o = (((unsigned)(k + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
+    const float dHz = ldf(a.Ho, o + 2 * cs) - ldf(a.Ho, o - 4 + 2 * cs);
+    const float dHy = ldf(a.Ho, o + cs) - ldf(a.Ho, o - 4 + cs);
+    const float4 cf = c.pmlE[0][i];
+    const unsigned x = (unsigned)u * np2 + xs;
+    const unsigned sz = (unsigned)a.nz * a.ny * np2;
+    float* ps = c.psiE[0];
+    const float p0 = fmaf(cf.x, ps[x], cf.y * dHz);
+    const float p1 = fmaf(cf.x, ps[sz + x], cf.y * dHy);
+    ps[x] = p0;
+    ps[sz + x] = p1;
+    if (k != 0) stf(a.Eo, o + cs, ldf(a.Eo, o + cs) - a.S * fmaf(cf.z - 1.f, dHz, p0));
+    if (j != 0) stf(a.Eo, o + 2 * cs, ldf(a.Eo, o + 2 * cs) + a.S * fmaf(cf.z - 1.f, dHy, p1));
 }
 
 __global__ void fill_kernel(float* p, long long n, float v)
@@ -424,6 +571,21 @@ __global__ void scale_kernel(float* __restrict__ d, const float* __restrict__ s,
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (long long)gridDim.x * blockDim.x)
         d[t] = s[t] * f;
+}
+
+// one component of the interior of a ghost-padded field, scaled:
+// out[(k*ny+j)*nx+i]
+__global__ void extract_kernel(float* __restrict__ d, const float* __restrict__ s, int comp, int nx,
+                               int ny, int nz, int nxp, int nyp, float f)
+{
+    const long long n = (long long)nx * ny * nz;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(t % nx);
+        const long long u = t / nx;
+        const int j = (int)(u % ny), k = (int)(u / ny);
+        d[t] = s[(long long)comp * nxp * nyp * (nz + 2) + ((long long)(k + 1) * nyp + (j + 1)) * nxp + i] * f;
+    }
 }
 
 __global__ void grad_out_kernel(double* __restrict__ d, const double* __restrict__ acc, long long n,
@@ -554,18 +716,39 @@ int grid_for(long long n) { long long g = (n + 255) / 256; return (int)(g < 4096
 
 }  // namespace
 
-int ccpr_launch_step(const StepArgs& a, int maxpairs, void* stream)
+int ccpr_launch_step(const StepArgs& a, int maxpairs, long long naux, void* stream)
 {
-    const int threads = ((a.nx + 63) / 64) * 64;
-    dim3 grid(a.nblk), block(threads);
+    dim3 grid(a.nblk), block(a.nxp);
     hipStream_t s = (hipStream_t)stream;
-    if (maxpairs <= 0) hipLaunchKernelGGL(ccpr_step_kernel<0>, grid, block, 0, s, a);
-    else if (maxpairs <= 1) hipLaunchKernelGGL(ccpr_step_kernel<1>, grid, block, 0, s, a);
-    else if (maxpairs <= 2) hipLaunchKernelGGL(ccpr_step_kernel<2>, grid, block, 0, s, a);
-    else if (maxpairs <= 3) hipLaunchKernelGGL(ccpr_step_kernel<3>, grid, block, 0, s, a);
-    else if (maxpairs <= 4) hipLaunchKernelGGL(ccpr_step_kernel<4>, grid, block, 0, s, a);
-    else if (maxpairs <= 6) hipLaunchKernelGGL(ccpr_step_kernel<6>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(ccpr_step_kernel<8>, grid, block, 0, s, a);
+    if (a.rows == 2) hipLaunchKernelGGL(ccpr_step_kernel<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(ccpr_step_kernel<4>, grid, block, 0, s, a);
+    if (naux > 0) {
+        dim3 ag((unsigned)((naux + 255) / 256)), ab(256);
+        if (maxpairs <= 0) hipLaunchKernelGGL(ccpr_aux_kernel<0>, ag, ab, 0, s, a);
+        else if (maxpairs <= 1) hipLaunchKernelGGL(ccpr_aux_kernel<1>, ag, ab, 0, s, a);
+        else if (maxpairs <= 2) hipLaunchKernelGGL(ccpr_aux_kernel<2>, ag, ab, 0, s, a);
+        else if (maxpairs <= 3) hipLaunchKernelGGL(ccpr_aux_kernel<3>, ag, ab, 0, s, a);
+        else if (maxpairs <= 4) hipLaunchKernelGGL(ccpr_aux_kernel<4>, ag, ab, 0, s, a);
+        else if (maxpairs <= 6) hipLaunchKernelGGL(ccpr_aux_kernel<6>, ag, ab, 0, s, a);
+        else hipLaunchKernelGGL(ccpr_aux_kernel<8>, ag, ab, 0, s, a);
+    }
+    return (int)hipGetLastError();
+}
+
+int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* stream)
+{
+    const long long n = nxs + ntf;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(ccpr_pre_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a,
+                       nxs);
+    return (int)hipGetLastError();
+}
+
+int ccpr_launch_post(const StepArgs& a, long long nxs, void* stream)
+{
+    if (nxs <= 0) return 0;
+    hipLaunchKernelGGL(ccpr_post_kernel, dim3((unsigned)((nxs + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       a, nxs);
     return (int)hipGetLastError();
 }
 
@@ -601,6 +784,15 @@ int ccpr_launch_copy_d(double* d, const double* s, long long n, void* stream)
 {
     if (n <= 0) return 0;
     hipLaunchKernelGGL(copy_d_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, d, s, n);
+    return (int)hipGetLastError();
+}
+
+int ccpr_launch_extract(float* d, const float* src, int comp, int nx, int ny, int nz, int nxp, int nyp,
+                        float f, void* stream)
+{
+    const long long n = (long long)nx * ny * nz;
+    hipLaunchKernelGGL(extract_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, d, src, comp,
+                       nx, ny, nz, nxp, nyp, f);
     return (int)hipGetLastError();
 }
 

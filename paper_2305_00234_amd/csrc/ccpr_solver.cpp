@@ -41,10 +41,15 @@ struct Layout {
     size_t psiE[2];              // [state] all three slabs
     size_t psiH[2][2];           // [state][parity]
     size_t ssh[2];               // [state] FP64 shadow of E on source edges
+    size_t cold[2];              // [state] StepCold block
+    size_t rowf[2], lanef[2];    // [state] row / lane class words
+    size_t extra[2];             // [state] aux-kernel cell list
+    size_t zr;                   // z-chunk plane ranges of the step kernel
+    size_t drive;                // S curl H' of the aux kernel's cells (scratch of one step)
     size_t rho, pmlE, pmlH, scal, gradacc, work;
     size_t fixed_end;
     // variable part
-    size_t src_fwd, src_adj, wave, lineE, lineH, incE, incH, gap, T, ckpt, stage;
+    size_t src_fwd, src_adj, wave, lineE, lineH, incE, incH, tf, gap, T, ckpt, stage;
     size_t total;
     int K = 0, S = 1;            // segment length / count
     size_t ckpt_bytes = 0;
@@ -56,7 +61,10 @@ struct Layout {
 struct ccpr_solver {
     ccpr_grid g{};
     double dt = 0;
-    long long ncell = 0;
+    long long ncell = 0;        // nx*ny*nz
+    int nxp = 0, nyp = 0, nzp = 0;
+    long long npad = 0;         // nxp*nyp*nzp: floats per padded field component
+    int rows = 2;               // y rows per thread of the step kernel
     std::string err;
     MatHost mat[2][3];
     // design
@@ -82,7 +90,7 @@ struct ccpr_solver {
     uint64_t ws_bytes = 0;
     hipStream_t stream = nullptr;
     int maxpairs = 0, npairs_total = 0;
-    int tz = 16;
+    int tz = 8;                 // nominal planes per z-chunk of the step kernel
     // run state
     int parity[2] = {0, 0};
     int step_count = 0;
@@ -93,6 +101,12 @@ struct ccpr_solver {
     double F = 0, adj_alpha = 1.0, grad_scale = 0;
     int current_state = 0;  // 0 forward, 1 adjoint (for get_field)
     AxisMat mats[3]{};
+    StepCold cold_host[2]{};
+    std::vector<unsigned> rowf_host[2], lanef_host[2];
+    std::vector<int4> extra_host[2];
+    std::vector<TfEntry> tf_host;
+    std::vector<int2> zr_host;  // plane range of each logical z-chunk
+    int tf_nE = 0, tf_nH = 0;
     long long fixed_key[4] = {-1, -1, -1, -1};
     // diagnostics
     double stat_ms = 0;
@@ -126,7 +140,7 @@ long long psi_total(const ccpr_solver* s)
 {
     if (s->g.npml <= 0) return 0;
     long long t = 0;
-    for (int a = 0; a < 3; ++a) t += slab_size(a, s->g.nx, s->g.ny, s->g.nz, s->g.npml);
+    for (int a = 0; a < 3; ++a) t += slab_size(a, s->g.nx, s->g.ny, s->g.nz, s->nxp, s->g.npml);
     return t;
 }
 
@@ -147,13 +161,22 @@ void recount_pairs(ccpr_solver* s)
 
 int plane_span(const ccpr_solver* s) { return s->pw_hi[s->pw_d] - s->pw_lo[s->pw_d] + 1; }
 
+// Number of TF/SF face words (E and H) of the plane-wave box.
+long long tf_count(const ccpr_solver* s)
+{
+    const int d = s->pw_d, p = s->pw_p, t = 3 - d - p;
+    const long long Ld = s->pw_hi[d] - s->pw_lo[d], Lp = s->pw_hi[p] - s->pw_lo[p],
+                    Lt = s->pw_hi[t] - s->pw_lo[t];
+    return 2 * (Lt + 1) * Lp + 2 * (Lt + 1) * Ld + 2 * (Lt + 1) * Lp + 2 * (Ld + 1) * Lp;
+}
+
 // Workspace layout for a solve of M steps (M = 0: stepping only).
 Layout make_layout(const ccpr_solver* s, int M, int K_req)
 {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-    const size_t nc = (size_t)s->ncell;
+    const size_t nc = (size_t)s->npad;
     const size_t nd = (size_t)std::max<long long>(s->nd, 1);
     const size_t psi = (size_t)psi_total(s);
     for (int st = 0; st < 2; ++st) {
@@ -164,6 +187,16 @@ Layout make_layout(const ccpr_solver* s, int M, int K_req)
         for (int p = 0; p < 2; ++p) L.psiH[st][p] = take(std::max<size_t>(psi, 1) * 4);
         L.ssh[st] = take((size_t)std::max(s->gncell, 1) * 3 * 8);
     }
+    L.cold[0] = take(sizeof(StepCold));
+    L.cold[1] = take(sizeof(StepCold));
+    const size_t nsrc = (size_t)std::max(s->gncell, 1);  // dipole: 1 cell; adjoint: the gap box
+    for (int st = 0; st < 2; ++st) {
+        L.rowf[st] = take((size_t)s->g.ny * s->g.nz * 4);
+        L.lanef[st] = take((size_t)s->nxp * 4);
+        L.extra[st] = take((2 * nsrc + 1) * sizeof(int4));
+    }
+    L.drive = take((3 * nd + 3 * nsrc) * 4);
+    L.zr = take((size_t)(s->g.nz + 1) * sizeof(int2));
     L.rho = take(nd * 4);
     L.pmlE = take((size_t)(s->g.nx + s->g.ny + s->g.nz) * 16);
     L.pmlH = take((size_t)(s->g.nx + s->g.ny + s->g.nz) * 16);
@@ -184,6 +217,7 @@ Layout make_layout(const ccpr_solver* s, int M, int K_req)
         L.lineH = take((size_t)(L.line_L + 1) * 8);
         L.incE = take((size_t)(steps + 1) * span * 4);
         L.incH = take((size_t)(steps + 1) * (span + 1) * 4);
+        L.tf = take((size_t)tf_count(s) * sizeof(TfEntry));
     }
     if (M > 0) {
         L.src_adj = take((size_t)M * std::max(s->gncell, 1) * 3 * 4);
@@ -195,7 +229,7 @@ Layout make_layout(const ccpr_solver* s, int M, int K_req)
         L.ckpt_bytes = (6 * nc + 2 * (size_t)std::max(s->npairs_total, 1) * nd + 2 * psi) * 4 + 8 * 3 * 8;
         L.ckpt = take((size_t)(L.S - 1) * align256(L.ckpt_bytes));
     }
-    L.stage = take(std::max(nc * 4, nd * 8));
+    L.stage = take(std::max((size_t)s->ncell * 4, nd * 8));
     L.total = o;
     return L;
 }
@@ -296,10 +330,10 @@ ccpr_status zero_state(ccpr_solver* s, int st)
 {
     const Layout& L = s->lay;
     const long long psi = psi_total(s);
-    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Eb[st][0]), 3 * s->ncell, 0.f, s->stream));
-    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Eb[st][1]), 3 * s->ncell, 0.f, s->stream));
-    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Hb[st][0]), 3 * s->ncell, 0.f, s->stream));
-    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Hb[st][1]), 3 * s->ncell, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Eb[st][0]), 3 * s->npad, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Eb[st][1]), 3 * s->npad, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Hb[st][0]), 3 * s->npad, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Hb[st][1]), 3 * s->npad, 0.f, s->stream));
     HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Jb[st]), 2LL * s->npairs_total * std::max(s->nd, 1LL), 0.f,
                             s->stream));
     HIPCHK(ccpr_launch_fill(wsp<float>(s, L.psiE[st]), psi, 0.f, s->stream));
@@ -347,93 +381,318 @@ ccpr_status prepare_source(ccpr_solver* s, int steps)
 
 int sigma_ca(int c, int a) { return a == (c + 1) % 3 ? 1 : -1; }
 
-StepArgs base_args(ccpr_solver* s, int st)
+// TF/SF face words of the plane-wave box (total field inside [lo, hi]).  In
+// the coordinates (d, p, t) = (propagation, polarisation, third axis):
+//  E_p on the d-faces and E_d on the p-faces are total-field points whose
+//  outside H neighbour is scattered-field: the incident H is added to their
+//  curl;  H_t on the d-planes and H_d on the t-planes just outside are
+//  scattered-field points whose inside E neighbour is total-field: the
+//  incident E is removed from their curl.  sigma_ca gives the sign with which
+//  a derivative along axis a enters (curl)_c.  The scaled update is
+//  E += S(curl H + corr),  H -= S(curl E + corr),  so coef = +-S*sigma for E
+//  words and -+S*sigma for H words.  E words come first in 'out'.
+ccpr_status build_tf(ccpr_solver* s, const StepCold& C)
+{
+    auto& out = s->tf_host;
+    out.clear();
+    const int d = s->pw_d, p = s->pw_p, t = 3 - d - p;
+    const int* lo = s->pw_lo;
+    const int* hi = s->pw_hi;
+    const double S = s->g.courant;
+    const int nx = s->g.nx, ny = s->g.ny;
+    auto push = [&](int comp, int cd, int cp, int ct, int m, double coef) {
+        int x[3];
+        x[d] = cd;
+        x[p] = cp;
+        x[t] = ct;
+        TfEntry e;
+        const long long cell = ((long long)(x[2] + 1) * s->nyp + (x[1] + 1)) * s->nxp + x[0];
+        e.off = (unsigned)((comp * s->npad + cell) * 4);
+        e.m = m;
+        e.coef = (float)coef;
+        e.uidx = (unsigned)(comp * s->ncell + ((long long)x[2] * ny + x[1]) * nx + x[0]);
+        out.push_back(e);
+    };
+    auto inside = [](const int* x, const int* blo, const int* bdim) {
+        return x[0] >= blo[0] && x[0] < blo[0] + bdim[0] && x[1] >= blo[1] && x[1] < blo[1] + bdim[1] &&
+               x[2] >= blo[2] && x[2] < blo[2] + bdim[2];
+    };
+    bool clash = false;
+    auto e_word = [&](int comp, int cd, int cp, int ct, int m, double coef) {
+        int x[3];
+        x[d] = cd;
+        x[p] = cp;
+        x[t] = ct;
+        if (C.nd > 0 && inside(x, C.dlo, C.ddim)) clash = true;
+        if (C.gap_on && inside(x, C.glo, C.gdim)) clash = true;
+        push(comp, cd, cp, ct, m, coef);
+    };
+    const double sEp = sigma_ca(p, d), sEd = sigma_ca(d, p), sHt = sigma_ca(t, d), sHd = sigma_ca(d, t);
+    // E_p on the d-faces
+    for (int ct = lo[t]; ct <= hi[t]; ++ct)
+        for (int cp = lo[p]; cp < hi[p]; ++cp) {
+            e_word(p, lo[d], cp, ct, 0, -S * sEp);
+            e_word(p, hi[d], cp, ct, hi[d] - lo[d] + 1, S * sEp);
+        }
+    // E_d on the p-faces
+    for (int ct = lo[t]; ct <= hi[t]; ++ct)
+        for (int cd = lo[d]; cd < hi[d]; ++cd) {
+            e_word(d, cd, lo[p], ct, cd - lo[d] + 1, -S * sEd);
+            e_word(d, cd, hi[p], ct, cd - lo[d] + 1, S * sEd);
+        }
+    s->tf_nE = (int)out.size();
+    // H_t on the d-planes just outside
+    for (int ct = lo[t]; ct <= hi[t]; ++ct)
+        for (int cp = lo[p]; cp < hi[p]; ++cp) {
+            push(t, lo[d] - 1, cp, ct, 0, S * sHt);
+            push(t, hi[d], cp, ct, hi[d] - lo[d], -S * sHt);
+        }
+    // H_d on the t-planes just outside
+    for (int cd = lo[d]; cd <= hi[d]; ++cd)
+        for (int cp = lo[p]; cp < hi[p]; ++cp) {
+            push(d, cd, cp, lo[t] - 1, cd - lo[d], S * sHd);
+            push(d, cd, cp, hi[t], cd - lo[d], -S * sHd);
+        }
+    s->tf_nH = (int)out.size() - s->tf_nE;
+    if ((long long)out.size() > tf_count(s))
+        return fail(s, CCPR_EINVAL, "internal: TF/SF word count %zu above %lld", out.size(), tf_count(s));
+    if (clash)
+        return fail(s, CCPR_ENOTSUP, "the TF/SF boundary must lie in the background: it crosses the design or gap box");
+    return CCPR_OK;
+}
+
+// Cold step data of state st (0 forward, 1 adjoint): everything the kernel
+// reads only in its rare branches.  Written to the workspace once per pass.
+void fill_cold(ccpr_solver* s, int st, StepCold& C)
 {
     const Layout& L = s->lay;
-    StepArgs A{};
-    A.nx = s->g.nx; A.ny = s->g.ny; A.nz = s->g.nz;
-    A.plane = (long long)s->g.nx * s->g.ny;
-    A.S = (float)s->g.courant;
-    const int par = s->parity[st];
-    for (int c = 0; c < 3; ++c) {
-        A.Ei[c] = wsp<float>(s, L.Eb[st][par]) + c * s->ncell;
-        A.Eo[c] = wsp<float>(s, L.Eb[st][par ^ 1]) + c * s->ncell;
-        A.Hi[c] = wsp<float>(s, L.Hb[st][par]) + c * s->ncell;
-        A.Ho[c] = wsp<float>(s, L.Hb[st][par ^ 1]) + c * s->ncell;
-    }
+    C = StepCold{};
     if (s->has_design) {
-        for (int a = 0; a < 3; ++a) { A.dlo[a] = s->dlo[a]; A.ddim[a] = s->ddim[a]; }
-        A.nd = s->nd;
-        A.rho = wsp<float>(s, L.rho);
-        A.J = wsp<float>(s, L.Jb[st]);
-        for (int ax = 0; ax < 3; ++ax) A.mat[ax] = s->mats[ax];
+        for (int a = 0; a < 3; ++a) { C.dlo[a] = s->dlo[a]; C.ddim[a] = s->ddim[a]; }
+        C.nd = s->nd;
+        C.rho = wsp<float>(s, L.rho);
+        C.J = wsp<float>(s, L.Jb[st]);
+        for (int ax = 0; ax < 3; ++ax) C.mat[ax] = s->mats[ax];
     }
-    A.npml = s->g.npml;
     if (s->g.npml > 0) {
         const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
         size_t offc = 0, offs = 0;
         for (int a = 0; a < 3; ++a) {
-            A.pmlE[a] = wsp<float4>(s, L.pmlE) + offc;
-            A.pmlH[a] = wsp<float4>(s, L.pmlH) + offc;
-            A.psiE[a] = wsp<float>(s, L.psiE[st]) + offs;
-            A.psiHi[a] = wsp<float>(s, L.psiH[st][par]) + offs;
-            A.psiHo[a] = wsp<float>(s, L.psiH[st][par ^ 1]) + offs;
+            C.pmlE[a] = wsp<float4>(s, L.pmlE) + offc;
+            C.pmlH[a] = wsp<float4>(s, L.pmlH) + offc;
+            C.psiE[a] = wsp<float>(s, L.psiE[st]) + offs;
+            C.psiH[0][a] = wsp<float>(s, L.psiH[st][0]) + offs;
+            C.psiH[1][a] = wsp<float>(s, L.psiH[st][1]) + offs;
             offc += n3[a];
-            offs += slab_size(a, s->g.nx, s->g.ny, s->g.nz, s->g.npml);
+            offs += slab_size(a, s->g.nx, s->g.ny, s->g.nz, s->nxp, s->g.npml);
         }
     }
-    A.tz = s->tz;
-    A.nys = (s->g.ny + CCPR_ROWS - 1) / CCPR_ROWS;
-    A.nblk = A.nys * ((s->g.nz + s->tz - 1) / s->tz);
-    return A;
+    if (st == 0 && s->src_kind == 1) {
+        C.src_on = 1;
+        for (int a = 0; a < 3; ++a) { C.slo[a] = s->dip_cell[a]; C.sdim[a] = 1; }
+        C.sncell = 1;
+        C.snsteps = s->src_table_steps;
+        C.src = wsp<float>(s, L.src_fwd);
+        C.ssh = wsp<double>(s, L.ssh[0]);
+    } else if (st == 0 && s->src_kind == 2) {
+        C.pw_on = 1;
+        C.pw_spanE = plane_span(s);
+        C.pw_spanH = plane_span(s) + 1;
+        C.tf_rows = L.inc_steps + 1;
+        C.tf_nE = s->tf_nE;
+        C.tf_nH = s->tf_nH;
+        C.incE = wsp<float>(s, L.incE);
+        C.incH = wsp<float>(s, L.incH);
+        C.tf = wsp<TfEntry>(s, L.tf);
+    } else if (st == 1) {
+        C.src_on = 1;
+        for (int a = 0; a < 3; ++a) { C.slo[a] = s->glo[a]; C.sdim[a] = s->gdim[a]; }
+        C.sncell = s->gncell;
+        C.snsteps = s->M;
+        C.src = wsp<float>(s, L.src_adj);
+        C.ssh = wsp<double>(s, L.ssh[1]);
+    }
+    if (st == 0 && s->has_obj && L.gap) {
+        C.gap_on = 1;
+        for (int a = 0; a < 3; ++a) { C.glo[a] = s->glo[a]; C.gdim[a] = s->gdim[a]; }
+        C.gncell = s->gncell;
+        C.gap = wsp<float>(s, L.gap);
+    }
+    if (L.T) C.T = wsp<float>(s, L.T);
+    C.grad = wsp<double>(s, L.gradacc);
 }
 
-void set_forward_source(ccpr_solver* s, StepArgs& A)
+// Row classes [k*ny + j] and lane classes [i] of state st (see CCPR_ROW_*,
+// CCPR_LANE_*): which rare branches a row / a lane can need.
+void fill_classes(const ccpr_solver* s, const StepCold& C, std::vector<unsigned>& rowf,
+                  std::vector<unsigned>& lanef)
+{
+    const int nx = s->g.nx, ny = s->g.ny, nz = s->g.nz, np = s->g.npml;
+    auto in = [](int v, int lo, int hi_excl) { return v >= lo && v < hi_excl; };
+    rowf.assign((size_t)ny * nz, 0u);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            unsigned f = 0;
+            if (np > 0 && (j < np || j >= ny - np)) f |= CCPR_ROW_YPML;
+            if (np > 0 && (k < np || k >= nz - np)) f |= CCPR_ROW_ZPML;
+            if (C.nd > 0 && in(j, C.dlo[1], C.dlo[1] + C.ddim[1]) && in(k, C.dlo[2], C.dlo[2] + C.ddim[2]))
+                f |= CCPR_ROW_DES;
+            if (C.src_on && in(j, C.slo[1], C.slo[1] + C.sdim[1]) && in(k, C.slo[2], C.slo[2] + C.sdim[2]))
+                f |= CCPR_ROW_SRC;
+            rowf[(size_t)k * ny + j] = f;
+        }
+    lanef.assign((size_t)s->nxp, 0u);
+    for (int i = 0; i < nx; ++i) {
+        unsigned f = 0;
+        if (np > 0 && (i < np || i >= nx - np)) f |= CCPR_LANE_PML;
+        if (C.nd > 0 && in(i, C.dlo[0], C.dlo[0] + C.ddim[0])) f |= CCPR_LANE_DES;
+        if (C.src_on && in(i, C.slo[0], C.slo[0] + C.sdim[0])) f |= CCPR_LANE_SRC;
+        lanef[i] = f;
+    }
+}
+
+// Cells outside the design box that the aux kernel finishes: source cells
+// (E update from the stored drive minus the source current) and gap-monitor
+// cells outside both boxes (monitor only).
+void fill_extra(const StepCold& C, std::vector<int4>& ex)
+{
+    ex.clear();
+    auto in_box = [](int i, int j, int k, const int* lo, const int* dim) {
+        return i >= lo[0] && i < lo[0] + dim[0] && j >= lo[1] && j < lo[1] + dim[1] && k >= lo[2] &&
+               k < lo[2] + dim[2];
+    };
+    const bool des = C.nd > 0;
+    if (C.src_on)
+        for (int k = C.slo[2]; k < C.slo[2] + C.sdim[2]; ++k)
+            for (int j = C.slo[1]; j < C.slo[1] + C.sdim[1]; ++j)
+                for (int i = C.slo[0]; i < C.slo[0] + C.sdim[0]; ++i)
+                    if (!(des && in_box(i, j, k, C.dlo, C.ddim))) ex.push_back(make_int4(i, j, k, CCPR_EXTRA_SOURCE));
+    if (C.gap_on)
+        for (int k = C.glo[2]; k < C.glo[2] + C.gdim[2]; ++k)
+            for (int j = C.glo[1]; j < C.glo[1] + C.gdim[1]; ++j)
+                for (int i = C.glo[0]; i < C.glo[0] + C.gdim[0]; ++i)
+                    if (!(des && in_box(i, j, k, C.dlo, C.ddim)) && !(C.src_on && in_box(i, j, k, C.slo, C.sdim)))
+                        ex.push_back(make_int4(i, j, k, CCPR_EXTRA_GAP));
+}
+
+// z-chunks of the step kernel: about nz/tz chunks of equal estimated cost
+// (a plane in a z CPML layer also streams its psi memories: weight 1.6), so
+// that the XCDs, which each take an equal share of the chunks, finish
+// together.  Logical chunk q of XCD-contiguous order gets physical chunk
+// (q % 8) * (n/8) + q / 8 when n is a multiple of 8, which spreads the
+// expensive chunks over the XCDs.
+void plan_chunks(ccpr_solver* s)
+{
+    const int nz = s->g.nz, np = s->g.npml;
+    int n = std::max(1, std::min(nz, (nz + s->tz - 1) / s->tz));
+    if (n >= 8 && nz >= 8 * ((n + 7) / 8)) n = (n + 7) / 8 * 8;
+    std::vector<double> cum(nz + 1, 0.0);
+    for (int k = 0; k < nz; ++k) cum[k + 1] = cum[k] + ((np > 0 && (k < np || k >= nz - np)) ? 1.6 : 1.0);
+    std::vector<int> b(n + 1);
+    b[0] = 0;
+    b[n] = nz;
+    int k = 0;
+    for (int m = 1; m < n; ++m) {
+        const double target = cum[nz] * m / n;
+        while (k < nz && cum[k + 1] <= target) ++k;
+        if (k + 1 <= nz && target - cum[k] > cum[k + 1] - target) ++k;
+        b[m] = std::max(b[m - 1] + 1, std::min(k, nz - (n - m)));
+    }
+    std::vector<int2> phys(n);
+    for (int m = 0; m < n; ++m) phys[m] = make_int2(b[m], b[m + 1]);
+    s->zr_host.resize(n);
+    for (int q = 0; q < n; ++q) s->zr_host[q] = phys[n % 8 == 0 ? (q % 8) * (n / 8) + q / 8 : q];
+}
+
+ccpr_status upload_cold(ccpr_solver* s, int st)
+{
+    plan_chunks(s);
+    HIPCHK(hipMemcpyAsync(s->ws + s->lay.zr, s->zr_host.data(), s->zr_host.size() * sizeof(int2),
+                          hipMemcpyHostToDevice, s->stream));
+    // source and gap cells are finished by the aux kernel before the x-CPML
+    // pass of E: they must lie outside the x layers
+    if (s->g.npml > 0) {
+        auto off_x_layers = [&](const int* lo, const int* dim) {
+            return lo[0] >= s->g.npml && lo[0] + dim[0] <= s->g.nx - s->g.npml;
+        };
+        const int one[3] = {1, 1, 1};
+        if (s->src_kind == 1 && !off_x_layers(s->dip_cell, one))
+            return fail(s, CCPR_ENOTSUP, "the dipole cell must lie outside the x CPML layers");
+        if (s->has_obj && !off_x_layers(s->glo, s->gdim))
+            return fail(s, CCPR_ENOTSUP, "the gap box must lie outside the x CPML layers");
+    }
+    if (st == 0 && s->src_kind == 2) {
+        fill_cold(s, st, s->cold_host[st]);
+        ccpr_status e = build_tf(s, s->cold_host[st]);
+        if (e) return e;
+        HIPCHK(hipMemcpyAsync(s->ws + s->lay.tf, s->tf_host.data(), s->tf_host.size() * sizeof(TfEntry),
+                              hipMemcpyHostToDevice, s->stream));
+    }
+    fill_cold(s, st, s->cold_host[st]);
+    fill_classes(s, s->cold_host[st], s->rowf_host[st], s->lanef_host[st]);
+    fill_extra(s->cold_host[st], s->extra_host[st]);
+    if (!s->extra_host[st].empty())
+        HIPCHK(hipMemcpyAsync(s->ws + s->lay.extra[st], s->extra_host[st].data(),
+                              s->extra_host[st].size() * sizeof(int4), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->ws + s->lay.cold[st], &s->cold_host[st], sizeof(StepCold),
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->ws + s->lay.rowf[st], s->rowf_host[st].data(), s->rowf_host[st].size() * 4,
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->ws + s->lay.lanef[st], s->lanef_host[st].data(), s->lanef_host[st].size() * 4,
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CCPR_OK;
+}
+
+StepArgs hot_args(ccpr_solver* s, int st)
 {
     const Layout& L = s->lay;
-    if (s->src_kind == 1) {
-        A.src_on = 1;
-        for (int a = 0; a < 3; ++a) { A.slo[a] = s->dip_cell[a]; A.sdim[a] = 1; }
-        A.sncell = 1;
-        A.snsteps = s->src_table_steps;
-        A.src = wsp<float>(s, L.src_fwd);
-        A.ssh = wsp<double>(s, L.ssh[0]);
-    } else if (s->src_kind == 2) {
-        A.pw_on = 1;
-        A.pw_d = s->pw_d; A.pw_p = s->pw_p; A.pw_t = 3 - s->pw_d - s->pw_p;
-        for (int a = 0; a < 3; ++a) { A.pwlo[a] = s->pw_lo[a]; A.pwhi[a] = s->pw_hi[a]; }
-        A.pw_spanE = plane_span(s);
-        A.pw_spanH = plane_span(s) + 1;
-        A.sg_Ep_d = (float)sigma_ca(A.pw_p, A.pw_d);
-        A.sg_Ed_p = (float)sigma_ca(A.pw_d, A.pw_p);
-        A.sg_Ht_d = (float)sigma_ca(A.pw_t, A.pw_d);
-        A.sg_Hd_t = (float)sigma_ca(A.pw_d, A.pw_t);
-        A.incE = wsp<float>(s, L.incE);
-        A.incH = wsp<float>(s, L.incH);
-    }
+    StepArgs A{};
+    const int par = s->parity[st];
+    A.Ei = wsp<float>(s, L.Eb[st][par]);
+    A.Eo = wsp<float>(s, L.Eb[st][par ^ 1]);
+    A.Hi = wsp<float>(s, L.Hb[st][par]);
+    A.Ho = wsp<float>(s, L.Hb[st][par ^ 1]);
+    A.rowf = wsp<unsigned>(s, L.rowf[st]);
+    A.lanef = wsp<unsigned>(s, L.lanef[st]);
+    A.drive = wsp<float>(s, L.drive);
+    A.extra = wsp<int4>(s, L.extra[st]);
+    A.nextra = (long long)s->extra_host[st].size();
+    A.cstride = (unsigned)(s->npad * 4);
+    A.nx = s->g.nx; A.ny = s->g.ny; A.nz = s->g.nz;
+    A.nxp = s->nxp; A.nyp = s->nyp; A.rows = s->rows;
+    A.npml = s->g.npml;
+    A.S = (float)s->g.courant;
+    A.psi_in = par;
+    A.tslot = -1;
+    A.cold = wsp<StepCold>(s, L.cold[st]);
+    A.zr = wsp<int2>(s, L.zr);
+    A.nys = (s->g.ny + s->rows - 1) / s->rows;
+    A.nblk = A.nys * (int)s->zr_host.size();
+    return A;
 }
 
 ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st)
 {
-    int e = ccpr_launch_step(A, s->maxpairs, s->stream);
+    const StepCold& C = s->cold_host[st];
+    const long long nxs = s->g.npml > 0 ? 2LL * s->g.npml * s->g.ny * s->g.nz : 0;
+    const long long naux = (s->has_design ? s->nd : 0) + A.nextra + (C.pw_on ? C.tf_nE : 0);
+    int e = ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, s->stream);
+    if (e == 0) e = ccpr_launch_step(A, s->maxpairs, naux, s->stream);
+    if (e == 0) e = ccpr_launch_post(A, nxs, s->stream);
     if (e != 0) return fail(s, CCPR_EDEVICE, "step kernel launch: %s", hipGetErrorString((hipError_t)e));
     s->parity[st] ^= 1;
     return CCPR_OK;
 }
 
-// One forward step n of the forward state with optional recording.
-ccpr_status forward_step(ccpr_solver* s, int n, float* Tout, bool gap)
+// One forward step n of the forward state; tslot >= 0 records the gradient
+// factor of this step into that history slot.
+ccpr_status forward_step(ccpr_solver* s, int n, int tslot, bool gap)
 {
-    StepArgs A = base_args(s, 0);
-    set_forward_source(s, A);
+    StepArgs A = hot_args(s, 0);
     A.n = n;
-    A.Tout = Tout;
-    if (gap && s->has_obj) {
-        A.gap_on = 1;
-        for (int a = 0; a < 3; ++a) { A.glo[a] = s->glo[a]; A.gdim[a] = s->gdim[a]; }
-        A.gncell = s->gncell;
-        A.gap = wsp<float>(s, s->lay.gap);
-    }
+    A.tslot = tslot;
+    A.mode = (tslot >= 0 ? CCPR_MODE_RECORD : 0) | (gap && s->has_obj ? CCPR_MODE_GAP : 0);
     return launch_step(s, A, 0);
 }
 
@@ -443,7 +702,7 @@ ccpr_status checkpoint(ccpr_solver* s, int slot, bool save)
     const Layout& L = s->lay;
     float* ck = wsp<float>(s, L.ckpt + (size_t)slot * align256(L.ckpt_bytes));
     const int par = save ? s->parity[0] : 0;
-    const long long nc3 = 3 * s->ncell, nj = 2LL * s->npairs_total * std::max(s->nd, 1LL);
+    const long long nc3 = 3 * s->npad, nj = 2LL * s->npairs_total * std::max(s->nd, 1LL);
     const long long psi = psi_total(s);
     struct { float* dev; long long n; } parts[5] = {
         {wsp<float>(s, L.Eb[0][par]), nc3},
@@ -562,6 +821,14 @@ ccpr_status ccpr_create(const ccpr_grid* g, ccpr_solver** out)
     s->g = *g;
     s->dt = g->courant * g->dx / kC0;
     s->ncell = (long long)g->nx * g->ny * g->nz;
+    s->nxp = (g->nx + 63) / 64 * 64;
+    s->nyp = (g->ny + CCPR_YPAD - 1) / CCPR_YPAD * CCPR_YPAD + 2;
+    s->nzp = g->nz + 2;
+    s->npad = (long long)s->nxp * s->nyp * s->nzp;
+    if (s->npad * 12 >= 0xffffffffLL) {
+        delete s;
+        return fail(nullptr, CCPR_ENOTSUP, "grid too large for 32-bit offsets");
+    }
     *out = s;
     return CCPR_OK;
 }
@@ -772,9 +1039,11 @@ ccpr_status ccpr_step(ccpr_solver* s, int n)
         return fail(s, CCPR_ENOTSUP, "plane-wave stepping is limited to the waveform length (%d steps)",
                     s->lay.inc_steps);
     build_mats(s);
+    st = upload_cold(s, 0);
+    if (st) return st;
     s->current_state = 0;
     for (int q = 0; q < n; ++q) {
-        st = forward_step(s, s->step_count, nullptr, false);
+        st = forward_step(s, s->step_count, -1, false);
         if (st) return st;
         s->step_count++;
     }
@@ -795,13 +1064,13 @@ ccpr_status ccpr_get_field(ccpr_solver* s, int comp, float* out, int mem)
     const double eta0 = std::sqrt(kMu0 / kEps0);
     const float f = (float)(comp < 3 ? 1.0 / a : 1.0 / (a * eta0));
     const int par = s->parity[state];
-    const float* src = comp < 3 ? wsp<float>(s, s->lay.Eb[state][par]) + comp * s->ncell
-                                : wsp<float>(s, s->lay.Hb[state][par]) + (comp - 3) * s->ncell;
+    const float* src = comp < 3 ? wsp<float>(s, s->lay.Eb[state][par]) : wsp<float>(s, s->lay.Hb[state][par]);
+    const int cc = comp % 3;
     if (mem == CCPR_MEM_DEVICE) {
-        HIPCHK(ccpr_launch_scale(out, src, s->ncell, f, s->stream));
+        HIPCHK(ccpr_launch_extract(out, src, cc, s->g.nx, s->g.ny, s->g.nz, s->nxp, s->nyp, f, s->stream));
     } else {
         float* stage = wsp<float>(s, s->lay.stage);
-        HIPCHK(ccpr_launch_scale(stage, src, s->ncell, f, s->stream));
+        HIPCHK(ccpr_launch_extract(stage, src, cc, s->g.nx, s->g.ny, s->g.nz, s->nxp, s->nyp, f, s->stream));
         HIPCHK(hipMemcpyAsync(out, stage, s->ncell * 4, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
@@ -825,6 +1094,8 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
     s->M = M;
     st = zero_state(s, 0);
     if (st) return st;
+    st = upload_cold(s, 0);
+    if (st) return st;
     HIPCHK(ccpr_launch_fill(wsp<float>(s, L.gap), (long long)s->gncell * 3, 0.f, s->stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s->timing) {
@@ -838,8 +1109,7 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
             st = checkpoint(s, seg - 1, true);
             if (st) return st;
         }
-        float* T = seg == S - 1 ? wsp<float>(s, L.T) + (size_t)(n - seg * K) * 3 * std::max(s->nd, 1LL) : nullptr;
-        st = forward_step(s, n, T, true);
+        st = forward_step(s, n, seg == S - 1 ? n - seg * K : -1, true);
         if (st) return st;
     }
     if (s->timing) {
@@ -891,6 +1161,8 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
     const long long ndm = std::max(s->nd, 1LL);
     ccpr_status st = zero_state(s, 1);
     if (st) return st;
+    st = upload_cold(s, 1);
+    if (st) return st;
     HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), ndm, 0.0, s->stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms_total = 0;
@@ -902,7 +1174,7 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
             else st = checkpoint(s, seg - 1, false);
             if (st) return st;
             for (int n = n0; n < n1; ++n) {
-                st = forward_step(s, n, wsp<float>(s, L.T) + (size_t)(n - n0) * 3 * ndm, false);
+                st = forward_step(s, n, n - n0, false);
                 if (st) return st;
             }
         }
@@ -913,16 +1185,10 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const int p = M - 1 - n;  // adjoint step p pairs with forward step n
-            StepArgs A = base_args(s, 1);
+            StepArgs A = hot_args(s, 1);
             A.n = p;
-            A.src_on = 1;
-            for (int a = 0; a < 3; ++a) { A.slo[a] = s->glo[a]; A.sdim[a] = s->gdim[a]; }
-            A.sncell = s->gncell;
-            A.snsteps = M;
-            A.src = wsp<float>(s, L.src_adj);
-            A.ssh = wsp<double>(s, L.ssh[1]);
-            A.Tin = wsp<float>(s, L.T) + (size_t)(n - n0) * 3 * ndm;
-            A.grad = wsp<double>(s, L.gradacc);
+            A.tslot = n - n0;
+            A.mode = CCPR_MODE_CORREL;
             st = launch_step(s, A, 1);
             if (st) return st;
         }
@@ -994,6 +1260,15 @@ ccpr_status ccpr_set_tile_planes(ccpr_solver* s, int planes)
     if (!s) return CCPR_EINVAL;
     if (planes < 1 || planes > 4096) return fail(s, CCPR_EINVAL, "tile planes must be in [1,4096]");
     s->tz = planes;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_set_tile_rows(ccpr_solver* s, int rows)
+{
+    if (!s) return CCPR_EINVAL;
+    if (rows != 2 && rows != 4) return fail(s, CCPR_EINVAL, "tile rows must be 2 or 4");
+    if (rows == 4 && s->nxp > 512) return fail(s, CCPR_ENOTSUP, "4 tile rows need nx <= 512");
+    s->rows = rows;
     return CCPR_OK;
 }
 

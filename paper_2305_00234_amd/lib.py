@@ -30,7 +30,7 @@ EXPORTS = [
     "ccpr_set_checkpointing", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
     "ccpr_adjoint", "ccpr_gradient", "ccpr_reset", "ccpr_step", "ccpr_get_field",
     "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_info",
-    "ccpr_set_tile_planes",
+    "ccpr_set_tile_planes", "ccpr_set_tile_rows",
 ]
 
 
@@ -88,6 +88,7 @@ def load():
         "ccpr_get_timing": (_i, [_p, _dp, C.POINTER(C.c_longlong)]),
         "ccpr_get_info": (_i, [_p, _ip, _ip, _ip]),
         "ccpr_set_tile_planes": (_i, [_p, _i]),
+        "ccpr_set_tile_rows": (_i, [_p, _i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -267,3 +268,6 @@ class Solver:
 
     def set_tile_planes(self, planes):
         self._chk(self._lib.ccpr_set_tile_planes(self._h, planes), "ccpr_set_tile_planes")
+
+    def set_tile_rows(self, rows):
+        self._chk(self._lib.ccpr_set_tile_rows(self._h, rows), "ccpr_set_tile_rows")
