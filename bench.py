@@ -6,9 +6,10 @@ DFT |E|^2 over a 4^3 gap, time-exact gradient), inputs resident in HBM.
 
 Prints one JSON line.  value = cell-updates of the forward and adjoint runs
 (cells x 2 x 6000 per solve) per second, in millions.  The roofline object is
-for the fused step kernel: algorithmic bytes per launch over
-its average launch duration, timed with HIP events on the library's stream
-inside the timed region.  The CPU baseline is the FP64 oracle on a bounded
+for the grid kernel (ccpr_step_kernel, the one that streams every cell):
+algorithmic bytes per launch (algorithmic_bytes) over its average launch
+duration, timed with HIP events on the library's stream around every launch
+inside the timed region; "step" gives the same for whole leapfrog steps.  The CPU baseline is the FP64 oracle on a bounded
 sample of the same workload (a few forward + adjoint steps on the full grid).
 """
 from __future__ import annotations
@@ -41,23 +42,40 @@ def workload_by_name(name, solve_steps=None):
 
 
 def algorithmic_bytes(w):
-    """Bytes per fused step launch, averaged over the forward and adjoint
-    launches (one forward launch and one adjoint launch move these on
-    average): 48 B/cell for E,H read+write; per design voxel 16 B per pole pair
-    and component (J read+write) + 4 B density; 32 B per (cell, CPML axis)
-    for the psi memories; forward gradient record 12 B/voxel, adjoint
-    correlation 12 B read + 16 B FP64 accumulator read/write per voxel."""
+    """Algorithmic HBM bytes of one launch of the grid kernel (ccpr_step_kernel,
+    one leapfrog step over all cells): 48 B per cell (E and H, three FP32
+    components each, read once and written once); 32 B per (cell, y or z CPML
+    layer) for the two psi memories of H (read old, write new) and of E (read,
+    write); 12 B per design voxel and per source-box cell for the stored E
+    drive.  The x CPML, the design pole currents, the gradient history and the
+    TF/SF faces are moved by the small pre / aux / post kernels of the step and
+    are counted in step_bytes, not here."""
     nx, ny, nz = w.shape
-    N = nx * ny * nz
+    n = nx * ny * nz
+    nd = int(np.prod(w.design_dims))
+    p = w.npml
+    yz_layer_cells = 2 * p * nx * nz + 2 * p * nx * ny if p else 0
+    src_cells = 1 if w.source == "dipole" else 0
+    return 48 * n + 32 * yz_layer_cells + 12 * (nd + src_cells)
+
+
+def step_bytes(w):
+    """Algorithmic HBM bytes of a whole leapfrog step (all kernels), averaged
+    over a forward and an adjoint step: the grid kernel's bytes; per design
+    voxel 16 B per pole pair and component (J read + write), 4 B density, 12 B
+    E^n + 12 B drive read + 12 B E^{n+1} write; 32 B per (cell, x CPML layer)
+    (psi of H and of E, read + write) plus 16 B of E and H for each; the
+    gradient history: 12 B record (forward), 12 B read + 16 B FP64 accumulator
+    read/write (adjoint)."""
+    nx, ny, nz = w.shape
     nd = int(np.prod(w.design_dims))
     pairs = sum(w.mat1[a].npairs + w.mat2[a].npairs for a in range(3))
     p = w.npml
-    pml_axis_cells = 0
-    if p:
-        pml_axis_cells = 2 * p * (ny * nz + nx * nz + nx * ny)
-    per_launch = 48 * N + (16 * pairs + 4) * nd + 32 * pml_axis_cells
+    x_layer_cells = 2 * p * ny * nz if p else 0
+    design = (16 * pairs + 4 + 36) * nd
+    xpml = (32 + 16) * x_layer_cells
     record = (12 * nd + (12 + 16) * nd) / 2.0
-    return per_launch + record
+    return algorithmic_bytes(w) + design + xpml + record
 
 
 def traffic_from_profile(kernel_src_hash):
@@ -116,8 +134,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "layout is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): this build has no "
+              "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -140,9 +158,14 @@ def main():
         s.gradient(out=grad)
         return F
 
-    for _ in range(args.warmup):
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    progress(f"{w.name}: {w.shape} cells, {M} steps per solve, {args.warmup} warmup + {args.steps} timed")
+    for q in range(args.warmup):
         one_solve()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        progress(f"warmup solve {q + 1} done")
 
     s.set_timing(True)
     lat = []
@@ -154,18 +177,22 @@ def main():
         F = one_solve()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - a)
+        progress(f"timed solve {len(lat)} done: {lat[-1]:.2f} s")
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     step_ms, launches = s.timing()
+    grid_ms, grid_launches = s.grid_timing()
     s.set_timing(False)
     info = s.info()
 
     ms_per_step = total / args.steps * 1e3
     updates = w.cells * 2 * M
     value = updates / (total / args.steps) / 1e6
-    avg_launch_s = step_ms / 1e3 / max(launches, 1)
+    avg_step_s = step_ms / 1e3 / max(launches, 1)
+    avg_launch_s = grid_ms / 1e3 / max(grid_launches, 1)
     alg = algorithmic_bytes(w)
     achieved = alg / avg_launch_s / 1e9
+    sb = step_bytes(w)
     traffic = traffic_from_profile(kernel_hash())
 
     out = {
@@ -194,9 +221,13 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "ccpr_step_kernel",
                      "alg_bytes_per_launch": int(alg),
-                     "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": launches},
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": grid_launches},
+        "step": {"avg_step_us": round(avg_step_s * 1e6, 2), "alg_bytes_per_step": int(sb),
+                 "achieved_GBs": round(sb / avg_step_s / 1e9, 1),
+                 "frac": round(sb / avg_step_s / 1e9 / HBM_PEAK_GBS, 4), "steps": launches},
     }
     if not args.no_cpu_baseline:
+        progress("cpu baseline (FP64 oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
 

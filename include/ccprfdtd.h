@@ -200,15 +200,21 @@ int ccpr_step_count(const ccpr_solver* s);
 
 /* ---- diagnostics ------------------------------------------------------- */
 
-/* Enable (1) or disable (0) stream-event timing of the fused step-kernel
- * loops of ccpr_forward and ccpr_adjoint, and clear the counters.  Timing
- * synchronises the stream at the end of each loop. */
+/* Enable (1) or disable (0) stream-event timing of the leapfrog loops of
+ * ccpr_forward and ccpr_adjoint, and clear the counters.  Timing records HIP
+ * events on the bound stream around each loop and around every launch of the
+ * grid kernel (the one that streams all cells), and synchronises the stream
+ * at the end of each loop. */
 ccpr_status ccpr_set_timing(ccpr_solver* s, int enable);
 
-/* Accumulated event time [ms] of the timed step-kernel loops and the number of
- * step-kernel launches they contain (their ratio is the average launch
- * duration, loop gaps included). */
+/* Accumulated event time [ms] of the timed leapfrog loops and the number of
+ * leapfrog steps they contain (their ratio is the average step time, all
+ * kernels of a step and launch gaps included). */
 ccpr_status ccpr_get_timing(const ccpr_solver* s, double* step_ms_total, long long* step_launches);
+
+/* Accumulated event time [ms] of the grid-kernel launches inside the timed
+ * loops and their number (their ratio is the grid kernel's average duration). */
+ccpr_status ccpr_get_grid_timing(const ccpr_solver* s, double* grid_ms_total, long long* grid_launches);
 
 /* Segment count and length of the last ccpr_forward layout, and the number of
  * z-planes one workgroup of the step kernel marches over.  Any pointer may be

@@ -9,7 +9,7 @@
 //   eps'(rho)   = eps_inf(rho)
 //   sigma'(rho) = sigma(rho) dt / (2 eps0)
 //   k_p         = (1 + a_p dt/2)/(1 - a_p dt/2), held as k_p - 1 = a_p dt/(1 - a_p dt/2)
-//                 (FP32 keeps the pole's decay rate to full relative precision)
+//                 (keeps the pole's decay rate to full relative precision)
 //   beta'_p     = c_p dt / (1 - a_p dt/2)
 // E update (trapezoid rule on sigma E and on the pole-pair currents, bilinear
 // rule on dJ/dt = a J + eps0 c dE/dt):
@@ -45,15 +45,21 @@ struct TfEntry {
     unsigned uidx;
 };
 
+// Material constants of one axis.  The E increment and the pole-current
+// recurrences are evaluated in FP64 arithmetic from FP64 constants (a metal's
+// conductivity and its Drude pole nearly cancel in A and in the numerator, and
+// the recurrences' intermediate roundings would otherwise dominate); fields
+// and currents are stored in FP32, the gradient factor is formed in FP32.
 struct AxisMat {
-    float eps1, deps;   // eps'(rho) = eps1 + rho*deps
-    float sig1, dsig;   // sigma'(rho) = sig1 + rho*dsig + rho*(1-rho)*gam
-    float gam;
+    double eps1, deps;  // eps'(rho) = eps1 + rho*deps
+    double sig1, dsig;  // sigma'(rho) = sig1 + rho*dsig + rho*(1-rho)*gam
+    double gam;
+    double krd[CCPR_PMAX], kid[CCPR_PMAX];  // k_p - 1 (real, imag)
+    double brd[CCPR_PMAX], bid[CCPR_PMAX];  // beta'_p
+    float epsf, depsf, dsigf, gamf;         // FP32 copies for the gradient factor
     int np;             // pole pairs on this axis; the first np1 belong to slot 1
     int np1;
     int jofs;           // first flat pair index of this axis in the J arrays
-    float kr[CCPR_PMAX], ki[CCPR_PMAX];  // k_p - 1 (real, imag)
-    float br[CCPR_PMAX], bi[CCPR_PMAX];  // beta'_p
 };
 
 // Step data the kernel needs only inside rare branches (design voxels, CPML
@@ -156,8 +162,10 @@ __host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, in
 }
 
 // Launchers (ccpr_kernels.hip)
-// fused grid step, then (naux > 0) the aux kernel over nd + nextra + tf_nE threads
-int ccpr_launch_step(const StepArgs& a, int maxpairs, long long naux, void* stream);
+// fused grid step over all cells
+int ccpr_launch_grid(const StepArgs& a, void* stream);
+// aux kernel over naux = nd + nextra + tf_nE threads
+int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long naux, void* stream);
 // before a step: x-CPML and TF/SF corrections of H^{n-1/2} (nxs x-layer cells,
 // ntf TF/SF H words); after it: x-CPML of E^{n+1}
 int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* stream);

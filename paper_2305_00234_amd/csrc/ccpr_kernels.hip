@@ -54,11 +54,11 @@ __device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive,
                                         long long v, float* T, double* sh)
 {
     const AxisMat& m = c.mat[C];
-    const float om = 1.f - rho;
-    const float eps = fmaf(rho, m.deps, m.eps1);
-    const float sig = fmaf(rho, m.dsig, m.sig1) + rho * om * m.gam;
-    float A = eps + sig;
-    float acc = 0.f, rold = 0.f;
+    const double r = rho, om = 1.0 - r;
+    const double sig = fma(r, m.dsig, m.sig1) + r * om * m.gam;
+    double A = fma(r, m.deps, m.eps1) + sig;
+    double num = fma(-2.0 * sig, (double)E, (double)drive);
+    float rold = 0.f;
     float jr[PMAX > 0 ? PMAX : 1], ji[PMAX > 0 ? PMAX : 1];
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
@@ -66,17 +66,20 @@ __device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive,
             const long long q = m.jofs + p;
             jr[p] = c.J[(2 * q) * c.nd + v];
             ji[p] = c.J[(2 * q + 1) * c.nd + v];
-            const float kap = p < m.np1 ? om : rho;
-            A = fmaf(kap, m.br[p], A);
-            // Re{(1 + k_p) J} with 1 + k_p = 2 + (k_p - 1)
-            acc = fmaf(kap, fmaf(2.f + m.kr[p], jr[p], -m.ki[p] * ji[p]), acc);
+            const double kap = p < m.np1 ? om : r;
+            A = fma(kap, m.brd[p], A);
+            // num -= kap Re{(1 + k_p) J} with 1 + k_p = 2 + (k_p - 1)
+            num = fma(-kap, fma(2.0 + m.krd[p], (double)jr[p], -m.kid[p] * (double)ji[p]), num);
             rold += p < m.np1 ? -jr[p] : jr[p];
         }
     }
-    const float inc = (drive - 2.f * sig * E - acc) / A;
+    // 1/A: FP32 reciprocal refined by one Newton step (FP64 accurate)
+    double ra = (double)(1.0f / (float)A);
+    ra = ra * fma(-A, ra, 2.0);
+    const double inc = num * ra;
     float En;
-    if (sh) { *sh += (double)inc; En = (float)*sh; }
-    else En = E + inc;
+    if (sh) { *sh += inc; En = (float)*sh; }
+    else En = (float)((double)E + inc);
     const float dE = En - E;
     float rnew = 0.f;
 #pragma unroll
@@ -84,14 +87,17 @@ __device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive,
         if (p < m.np) {
             const long long q = m.jofs + p;
             // J^{n+1} = J + (k_p - 1) J + beta'_p dE
-            const float nr = jr[p] + fmaf(m.kr[p], jr[p], fmaf(-m.ki[p], ji[p], m.br[p] * dE));
-            const float ni = ji[p] + fmaf(m.kr[p], ji[p], fmaf(m.ki[p], jr[p], m.bi[p] * dE));
+            // (FP64 arithmetic, one rounding to the FP32 store)
+            const double jrd = jr[p], jid = ji[p], dEd = dE;
+            const float nr = (float)(jrd + fma(m.krd[p], jrd, fma(-m.kid[p], jid, m.brd[p] * dEd)));
+            const float ni = (float)(jid + fma(m.krd[p], jid, fma(m.kid[p], jrd, m.bid[p] * dEd)));
             c.J[(2 * q) * c.nd + v] = nr;
             c.J[(2 * q + 1) * c.nd + v] = ni;
             rnew += p < m.np1 ? -nr : nr;
         }
     }
-    *T = fmaf(m.deps, dE, fmaf(m.dsig + (1.f - 2.f * rho) * m.gam, En + E, rnew + rold));
+    const float rf = rho;
+    *T = fmaf(m.depsf, dE, fmaf(m.dsigf + (1.f - 2.f * rf) * m.gamf, En + E, rnew + rold));
     return En;
 }
 
@@ -716,22 +722,27 @@ int grid_for(long long n) { long long g = (n + 255) / 256; return (int)(g < 4096
 
 }  // namespace
 
-int ccpr_launch_step(const StepArgs& a, int maxpairs, long long naux, void* stream)
+int ccpr_launch_grid(const StepArgs& a, void* stream)
 {
     dim3 grid(a.nblk), block(a.nxp);
     hipStream_t s = (hipStream_t)stream;
     if (a.rows == 2) hipLaunchKernelGGL(ccpr_step_kernel<2>, grid, block, 0, s, a);
     else hipLaunchKernelGGL(ccpr_step_kernel<4>, grid, block, 0, s, a);
-    if (naux > 0) {
-        dim3 ag((unsigned)((naux + 255) / 256)), ab(256);
-        if (maxpairs <= 0) hipLaunchKernelGGL(ccpr_aux_kernel<0>, ag, ab, 0, s, a);
-        else if (maxpairs <= 1) hipLaunchKernelGGL(ccpr_aux_kernel<1>, ag, ab, 0, s, a);
-        else if (maxpairs <= 2) hipLaunchKernelGGL(ccpr_aux_kernel<2>, ag, ab, 0, s, a);
-        else if (maxpairs <= 3) hipLaunchKernelGGL(ccpr_aux_kernel<3>, ag, ab, 0, s, a);
-        else if (maxpairs <= 4) hipLaunchKernelGGL(ccpr_aux_kernel<4>, ag, ab, 0, s, a);
-        else if (maxpairs <= 6) hipLaunchKernelGGL(ccpr_aux_kernel<6>, ag, ab, 0, s, a);
-        else hipLaunchKernelGGL(ccpr_aux_kernel<8>, ag, ab, 0, s, a);
-    }
+    return (int)hipGetLastError();
+}
+
+int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long naux, void* stream)
+{
+    if (naux <= 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    dim3 ag((unsigned)((naux + 255) / 256)), ab(256);
+    if (maxpairs <= 0) hipLaunchKernelGGL(ccpr_aux_kernel<0>, ag, ab, 0, s, a);
+    else if (maxpairs <= 1) hipLaunchKernelGGL(ccpr_aux_kernel<1>, ag, ab, 0, s, a);
+    else if (maxpairs <= 2) hipLaunchKernelGGL(ccpr_aux_kernel<2>, ag, ab, 0, s, a);
+    else if (maxpairs <= 3) hipLaunchKernelGGL(ccpr_aux_kernel<3>, ag, ab, 0, s, a);
+    else if (maxpairs <= 4) hipLaunchKernelGGL(ccpr_aux_kernel<4>, ag, ab, 0, s, a);
+    else if (maxpairs <= 6) hipLaunchKernelGGL(ccpr_aux_kernel<6>, ag, ab, 0, s, a);
+    else hipLaunchKernelGGL(ccpr_aux_kernel<8>, ag, ab, 0, s, a);
     return (int)hipGetLastError();
 }
 

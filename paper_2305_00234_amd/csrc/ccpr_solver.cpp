@@ -111,7 +111,12 @@ struct ccpr_solver {
     // diagnostics
     double stat_ms = 0;
     long long stat_launches = 0;
+    double stat_grid_ms = 0;
+    long long stat_grid_launches = 0;
     bool timing = false;
+    std::vector<hipEvent_t> tev;    // event pairs around grid launches of the current loop
+    size_t tev_used = 0;
+    bool timed_loop = false;        // inside a forward / adjoint loop with timing on
 };
 
 namespace {
@@ -249,11 +254,15 @@ void axis_mat(const ccpr_solver* s, int ax, int jofs, AxisMat& m)
     const MatHost& m1 = s->mat[0][ax];
     const MatHost& m2 = s->mat[1][ax];
     const double dt = s->dt, h = dt / (2 * kEps0);
-    m.eps1 = (float)m1.eps;
-    m.deps = (float)(m2.eps - m1.eps);
-    m.sig1 = (float)(m1.sig * h);
-    m.dsig = (float)((m2.sig - m1.sig) * h);
-    m.gam = (float)(s->gamma * h);
+    m.eps1 = m1.eps;
+    m.deps = m2.eps - m1.eps;
+    m.sig1 = m1.sig * h;
+    m.dsig = (m2.sig - m1.sig) * h;
+    m.gam = s->gamma * h;
+    m.epsf = (float)m.eps1;
+    m.depsf = (float)m.deps;
+    m.dsigf = (float)m.dsig;
+    m.gamf = (float)m.gam;
     m.np1 = (int)m1.a.size();
     m.np = (int)(m1.a.size() + m2.a.size());
     m.jofs = jofs;
@@ -265,13 +274,13 @@ void axis_mat(const ccpr_solver* s, int ax, int jofs, AxisMat& m)
             const cd den = 1.0 - a * dt / 2.0;
             const cd km1 = a * dt / den;  // k_p - 1, free of cancellation
             const cd b = c * dt / den;
-            m.kr[q] = (float)km1.real();
-            m.ki[q] = (float)km1.imag();
-            m.br[q] = (float)b.real();
-            m.bi[q] = (float)b.imag();
+            m.krd[q] = km1.real();
+            m.kid[q] = km1.imag();
+            m.brd[q] = b.real();
+            m.bid[q] = b.imag();
         }
     }
-    for (; q < CCPR_PMAX; ++q) m.kr[q] = m.ki[q] = m.br[q] = m.bi[q] = 0.f;
+    for (; q < CCPR_PMAX; ++q) m.krd[q] = m.kid[q] = m.brd[q] = m.bid[q] = 0.0;
 }
 
 // CPML coefficient (b, a, 1/kappa) at position pos (cell units) along an axis
@@ -678,7 +687,21 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st)
     const long long nxs = s->g.npml > 0 ? 2LL * s->g.npml * s->g.ny * s->g.nz : 0;
     const long long naux = (s->has_design ? s->nd : 0) + A.nextra + (C.pw_on ? C.tf_nE : 0);
     int e = ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, s->stream);
-    if (e == 0) e = ccpr_launch_step(A, s->maxpairs, naux, s->stream);
+    const bool tm = s->timing && s->timed_loop;
+    if (tm) {
+        while (s->tev.size() < s->tev_used + 2) {
+            hipEvent_t ev;
+            HIPCHK(hipEventCreate(&ev));
+            s->tev.push_back(ev);
+        }
+        HIPCHK(hipEventRecord(s->tev[s->tev_used], s->stream));
+    }
+    if (e == 0) e = ccpr_launch_grid(A, s->stream);
+    if (tm) {
+        HIPCHK(hipEventRecord(s->tev[s->tev_used + 1], s->stream));
+        s->tev_used += 2;
+    }
+    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, naux, s->stream);
     if (e == 0) e = ccpr_launch_post(A, nxs, s->stream);
     if (e != 0) return fail(s, CCPR_EDEVICE, "step kernel launch: %s", hipGetErrorString((hipError_t)e));
     s->parity[st] ^= 1;
@@ -694,6 +717,20 @@ ccpr_status forward_step(ccpr_solver* s, int n, int tslot, bool gap)
     A.tslot = tslot;
     A.mode = (tslot >= 0 ? CCPR_MODE_RECORD : 0) | (gap && s->has_obj ? CCPR_MODE_GAP : 0);
     return launch_step(s, A, 0);
+}
+
+// add the recorded grid-kernel event pairs to the statistics (the stream is
+// synchronised by the caller)
+ccpr_status harvest_grid_events(ccpr_solver* s)
+{
+    for (size_t q = 0; q + 1 < s->tev_used; q += 2) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, s->tev[q], s->tev[q + 1]));
+        s->stat_grid_ms += ms;
+        s->stat_grid_launches += 1;
+    }
+    s->tev_used = 0;
+    return CCPR_OK;
 }
 
 // copy the forward state (current parity) to / from checkpoint slot c
@@ -837,6 +874,7 @@ void ccpr_destroy(ccpr_solver* s)
 {
     if (!s) return;
     if (s->ws) (void)hipStreamSynchronize(s->stream);
+    for (hipEvent_t ev : s->tev) (void)hipEventDestroy(ev);
     delete s;
 }
 
@@ -1103,6 +1141,7 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, s->stream));
     }
+    s->timed_loop = s->timing;
     for (int n = 0; n < M; ++n) {
         const int seg = n / K;
         if (n % K == 0 && seg >= 1 && seg < S) {
@@ -1121,7 +1160,10 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
         s->stat_launches += M;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        st = harvest_grid_events(s);
+        if (st) return st;
     }
+    s->timed_loop = false;
     s->step_count = M;
     s->current_state = 0;
     const int ne = s->gncell * 3;
@@ -1166,6 +1208,7 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
     HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), ndm, 0.0, s->stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms_total = 0;
+    s->timed_loop = s->timing;
     for (int seg = S - 1; seg >= 0; --seg) {
         const int n0 = seg * K, n1 = std::min(M, n0 + K);
         if (seg < S - 1) {
@@ -1200,8 +1243,11 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
             ms_total += ms;
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
+            st = harvest_grid_events(s);
+            if (st) return st;
         }
     }
+    s->timed_loop = false;
     if (s->timing) {
         s->stat_ms += ms_total;
         s->stat_launches += M;
@@ -1235,6 +1281,8 @@ ccpr_status ccpr_set_timing(ccpr_solver* s, int enable)
     s->timing = enable != 0;
     s->stat_ms = 0;
     s->stat_launches = 0;
+    s->stat_grid_ms = 0;
+    s->stat_grid_launches = 0;
     return CCPR_OK;
 }
 
@@ -1243,6 +1291,14 @@ ccpr_status ccpr_get_timing(const ccpr_solver* s, double* step_ms_total, long lo
     if (!s || !step_ms_total || !step_launches) return CCPR_EINVAL;
     *step_ms_total = s->stat_ms;
     *step_launches = s->stat_launches;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_get_grid_timing(const ccpr_solver* s, double* grid_ms_total, long long* grid_launches)
+{
+    if (!s || !grid_ms_total || !grid_launches) return CCPR_EINVAL;
+    *grid_ms_total = s->stat_grid_ms;
+    *grid_launches = s->stat_grid_launches;
     return CCPR_OK;
 }
 

@@ -29,7 +29,7 @@ EXPORTS = [
     "ccpr_set_source_dipole", "ccpr_set_source_planewave", "ccpr_set_objective",
     "ccpr_set_checkpointing", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
     "ccpr_adjoint", "ccpr_gradient", "ccpr_reset", "ccpr_step", "ccpr_get_field",
-    "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_info",
+    "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_grid_timing", "ccpr_get_info",
     "ccpr_set_tile_planes", "ccpr_set_tile_rows",
 ]
 
@@ -86,6 +86,7 @@ def load():
         "ccpr_step_count": (_i, [_p]),
         "ccpr_set_timing": (_i, [_p, _i]),
         "ccpr_get_timing": (_i, [_p, _dp, C.POINTER(C.c_longlong)]),
+        "ccpr_get_grid_timing": (_i, [_p, _dp, C.POINTER(C.c_longlong)]),
         "ccpr_get_info": (_i, [_p, _ip, _ip, _ip]),
         "ccpr_set_tile_planes": (_i, [_p, _i]),
         "ccpr_set_tile_rows": (_i, [_p, _i]),
@@ -258,6 +259,13 @@ class Solver:
         ms = C.c_double(0.0)
         n = C.c_longlong(0)
         self._chk(self._lib.ccpr_get_timing(self._h, C.byref(ms), C.byref(n)), "ccpr_get_timing")
+        return ms.value, n.value
+
+    def grid_timing(self):
+        """(total ms, launches) of the grid kernel inside the timed loops."""
+        ms = C.c_double(0.0)
+        n = C.c_longlong(0)
+        self._chk(self._lib.ccpr_get_grid_timing(self._h, C.byref(ms), C.byref(n)), "ccpr_get_grid_timing")
         return ms.value, n.value
 
     def info(self):
