@@ -46,12 +46,13 @@ __device__ __forceinline__ int box_index(int i, int j, int k, const int* lo, con
     return ((k - lo[2]) * dim[1] + (j - lo[1])) * dim[0] + (i - lo[0]);
 }
 
-// Dispersive E update of component C at design voxel v (see ccpr_internal.h).
-// sh (may be null): FP64 shadow of E on a source edge; E^{n+1} is then
+// Dispersive E update of component C at design voxel v (see ccpr_internal.h),
+// on currents already in registers: jr/ji hold J^n on entry and J^{n+1} on
+// exit.  sh (may be null): FP64 shadow of E on a source edge; E^{n+1} is then
 // accumulated in FP64 and rounded once.
 template <int C, int PMAX>
-__device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive, float rho,
-                                        long long v, float* T, double* sh)
+__device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive, float rho, float* jr,
+                                        float* ji, float* T, double* sh)
 {
     const AxisMat& m = c.mat[C];
     const double r = rho, om = 1.0 - r;
@@ -59,13 +60,9 @@ __device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive,
     double A = fma(r, m.deps, m.eps1) + sig;
     double num = fma(-2.0 * sig, (double)E, (double)drive);
     float rold = 0.f;
-    float jr[PMAX > 0 ? PMAX : 1], ji[PMAX > 0 ? PMAX : 1];
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
         if (p < m.np) {
-            const long long q = m.jofs + p;
-            jr[p] = c.J[(2 * q) * c.nd + v];
-            ji[p] = c.J[(2 * q + 1) * c.nd + v];
             const double kap = p < m.np1 ? om : r;
             A = fma(kap, m.brd[p], A);
             // num -= kap Re{(1 + k_p) J} with 1 + k_p = 2 + (k_p - 1)
@@ -85,20 +82,47 @@ __device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive,
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
         if (p < m.np) {
-            const long long q = m.jofs + p;
             // J^{n+1} = J + (k_p - 1) J + beta'_p dE
             // (FP64 arithmetic, one rounding to the FP32 store)
             const double jrd = jr[p], jid = ji[p], dEd = dE;
-            const float nr = (float)(jrd + fma(m.krd[p], jrd, fma(-m.kid[p], jid, m.brd[p] * dEd)));
-            const float ni = (float)(jid + fma(m.krd[p], jid, fma(m.kid[p], jrd, m.bid[p] * dEd)));
-            c.J[(2 * q) * c.nd + v] = nr;
-            c.J[(2 * q + 1) * c.nd + v] = ni;
-            rnew += p < m.np1 ? -nr : nr;
+            jr[p] = (float)(jrd + fma(m.krd[p], jrd, fma(-m.kid[p], jid, m.brd[p] * dEd)));
+            ji[p] = (float)(jid + fma(m.krd[p], jid, fma(m.kid[p], jrd, m.bid[p] * dEd)));
+            rnew += p < m.np1 ? -jr[p] : jr[p];
         }
     }
     const float rf = rho;
     *T = fmaf(m.depsf, dE, fmaf(m.dsigf + (1.f - 2.f * rf) * m.gamf, En + E, rnew + rold));
     return En;
+}
+
+// Pole currents of component C at voxel v: load / store (pairs p < np).
+template <int C, int PMAX>
+__device__ __forceinline__ void j_load(const StepCold& c, long long v, float* jr, float* ji)
+{
+    const AxisMat& m = c.mat[C];
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+        jr[p] = 0.f;
+        ji[p] = 0.f;
+        if (p < m.np) {
+            const long long q = m.jofs + p;
+            jr[p] = c.J[(2 * q) * c.nd + v];
+            ji[p] = c.J[(2 * q + 1) * c.nd + v];
+        }
+    }
+}
+template <int C, int PMAX>
+__device__ __forceinline__ void j_store(const StepCold& c, long long v, const float* jr, const float* ji)
+{
+    const AxisMat& m = c.mat[C];
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+        if (p < m.np) {
+            const long long q = m.jofs + p;
+            c.J[(2 * q) * c.nd + v] = jr[p];
+            c.J[(2 * q + 1) * c.nd + v] = ji[p];
+        }
+    }
 }
 
 // x-neighbour exchange on the 64 lanes of a wave (DPP wave shifts, one VALU
@@ -388,8 +412,24 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
         const int j = c.dlo[1] + (int)(u % c.ddim[1]);
         const int kk = c.dlo[2] + (int)(u / c.ddim[1]);
         const unsigned o = (((unsigned)(kk + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
+        // every load first (the current stores alias the later loads otherwise)
+        constexpr int PN = PMAX > 0 ? PMAX : 1;
+        float jrx[PN], jix[PN], jry[PN], jiy[PN], jrz[PN], jiz[PN];
+        j_load<0, PMAX>(c, v, jrx, jix);
+        j_load<1, PMAX>(c, v, jry, jiy);
+        j_load<2, PMAX>(c, v, jrz, jiz);
         const float e0x = ldf(a.Ei, o), e0y = ldf(a.Ei, o + cs), e0z = ldf(a.Ei, o + 2 * cs);
         float dx_ = a.drive[v], dy_ = a.drive[c.nd + v], dz_ = a.drive[2 * c.nd + v];
+        const float rho = c.rho[v];
+        float Tox = 0.f, Toy = 0.f, Toz = 0.f;
+        double g0 = 0.0;
+        float* Tslot = c.T + (long long)a.tslot * 3 * c.nd;
+        if (a.mode & CCPR_MODE_CORREL) {
+            Tox = Tslot[v];
+            Toy = Tslot[c.nd + v];
+            Toz = Tslot[2 * c.nd + v];
+            g0 = c.grad[v];
+        }
         double* sh = nullptr;
         if (c.src_on && in_box(i, j, kk, c.slo, c.sdim)) {
             const int ci = box_index(i, j, kk, c.slo, c.sdim);
@@ -401,24 +441,23 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
             }
             if (c.ssh) sh = c.ssh + (long long)ci * 3;
         }
-        const float rho = c.rho[v];
         float Tx, Ty, Tz;
-        const float nxv = e_disp<0, PMAX>(c, e0x, dx_, rho, v, &Tx, sh);
-        const float nyv = e_disp<1, PMAX>(c, e0y, dy_, rho, v, &Ty, sh ? sh + 1 : nullptr);
-        const float nzv = e_disp<2, PMAX>(c, e0z, dz_, rho, v, &Tz, sh ? sh + 2 : nullptr);
+        const float nxv = e_disp<0, PMAX>(c, e0x, dx_, rho, jrx, jix, &Tx, sh);
+        const float nyv = e_disp<1, PMAX>(c, e0y, dy_, rho, jry, jiy, &Ty, sh ? sh + 1 : nullptr);
+        const float nzv = e_disp<2, PMAX>(c, e0z, dz_, rho, jrz, jiz, &Tz, sh ? sh + 2 : nullptr);
+        j_store<0, PMAX>(c, v, jrx, jix);
+        j_store<1, PMAX>(c, v, jry, jiy);
+        j_store<2, PMAX>(c, v, jrz, jiz);
         stf(a.Eo, o, nxv);
         stf(a.Eo, o + cs, nyv);
         stf(a.Eo, o + 2 * cs, nzv);
         if (a.mode & CCPR_MODE_RECORD) {
-            float* T = c.T + (long long)a.tslot * 3 * c.nd;
-            T[v] = Tx;
-            T[c.nd + v] = Ty;
-            T[2 * c.nd + v] = Tz;
+            Tslot[v] = Tx;
+            Tslot[c.nd + v] = Ty;
+            Tslot[2 * c.nd + v] = Tz;
         }
-        if (a.mode & CCPR_MODE_CORREL) {
-            const float* T = c.T + (long long)a.tslot * 3 * c.nd;
-            c.grad[v] += (double)nxv * T[v] + (double)nyv * T[c.nd + v] + (double)nzv * T[2 * c.nd + v];
-        }
+        if (a.mode & CCPR_MODE_CORREL)
+            c.grad[v] = g0 + ((double)nxv * Tox + (double)nyv * Toy + (double)nzv * Toz);
         if ((a.mode & CCPR_MODE_GAP) && in_box(i, j, kk, c.glo, c.gdim)) {
             float* g = c.gap + ((long long)(n + 1) * c.gncell + box_index(i, j, kk, c.glo, c.gdim)) * 3;
             g[0] = nxv;

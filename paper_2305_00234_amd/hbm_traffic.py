@@ -1,0 +1,126 @@
+"""HBM traffic of the grid kernel (ccpr_step_kernel) from rocprofv3 counters.
+
+The counters are calibrated against a plain device copy of known size, run in
+the same process: the factor (bytes moved) / (counter reading) of the copy
+scales the grid kernel's readings.
+
+Steps (from the repository root; each 'run' under its own counter pass):
+
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o fetch -- \\
+      python3 paper_2305_00234_amd/hbm_traffic.py run
+  rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o write -- \\
+      python3 paper_2305_00234_amd/hbm_traffic.py run
+  python3 paper_2305_00234_amd/hbm_traffic.py summarize OUT/fetch OUT/write \\
+      profiles/step_kernel_hbm_traffic_gold_gap_320.json
+
+'run' copies a 1 GiB device buffer four times (hipMemcpy device to device),
+then runs a 10-step forward solve of the 320^3 gold gap workload.
+'summarize' writes the per-launch HBM bytes (fetch and write, calibrated),
+the calibration factors and the kernel source hash to the JSON file.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30
+GRID_KERNEL = "ccpr_step_kernel"
+
+
+def run(steps: int = 10) -> None:
+    sys.path.insert(0, ROOT)
+    import torch
+    from paper_2305_00234_amd import inputs as I
+    from paper_2305_00234_amd.solver import solver_for
+
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    w = I.gold_gap_320(steps=steps)
+    s = solver_for(w)
+    s.forward(steps)
+    torch.cuda.synchronize()
+    s.close()
+    print(f"hbm_traffic run: 4 copies of {COPY_BYTES >> 20} MiB, {steps} forward steps of {w.name}",
+          flush=True)
+
+
+def _per_dispatch(directory: str):
+    """{kernel name: [(dispatch id, counter value)]} from a rocprofv3 counter CSV."""
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no *counter_collection.csv under {directory}")
+    per = {}
+    for row in csv.DictReader(open(files[0])):
+        key = (row["Kernel_Name"], int(row.get("Dispatch_Id") or row.get("Correlation_Id")))
+        per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for (name, disp), v in sorted(per.items(), key=lambda kv: kv[0][1]):
+        out.setdefault(name, []).append((disp, v))
+    return out
+
+
+def _pick(table, needles, first=None):
+    """Counter values of the dispatches of the first kernel whose name contains
+    one of needles (the first 'first' dispatches in launch order if given)."""
+    for needle in needles:
+        names = [n for n in table if needle in n]
+        if names:
+            rows = sorted((r for n in names for r in table[n]), key=lambda r: r[0])
+            if first:
+                rows = rows[:first]
+            return names[0], [v for _, v in rows]
+    raise KeyError(f"no kernel matching {needles}: {sorted(table)[:8]}")
+
+
+def summarize(fetch_dir: str, write_dir: str, out_json: str) -> dict:
+    fetch = _per_dispatch(fetch_dir)
+    write = _per_dispatch(write_dir)
+    # the calibration copies are the first four copy dispatches of the run
+    copy_names = ("copyBuffer", "direct_copy", "copy_kernel", "elementwise")
+    copy_name, cf = _pick(fetch, copy_names, first=4)
+    _, cw = _pick(write, copy_names, first=4)
+    # counters are in KiB per dispatch; calibrate: bytes moved / bytes reported
+    f_fac = COPY_BYTES / (sum(cf) / len(cf) * 1024.0)
+    w_fac = COPY_BYTES / (sum(cw) / len(cw) * 1024.0)
+    name, gf = _pick(fetch, (GRID_KERNEL,))
+    _, gw = _pick(write, (GRID_KERNEL,))
+    fetch_b = sum(gf) / len(gf) * 1024.0 * f_fac
+    write_b = sum(gw) / len(gw) * 1024.0 * w_fac
+    src = os.path.join(ROOT, "paper_2305_00234_amd", "csrc", "ccpr_kernels.hip")
+    d = {
+        "kernel": name,
+        "workload": "gold_gap_320 (320^3 cells, 12-cell CPML, 160x160x80 gold design, TF/SF)",
+        "dispatches": len(gf),
+        "fetch_KiB_per_dispatch_raw": sum(gf) / len(gf),
+        "write_KiB_per_dispatch_raw": sum(gw) / len(gw),
+        "copy_kernel": copy_name,
+        "copy_bytes_read_and_written": COPY_BYTES,
+        "fetch_calibration_factor": f_fac,
+        "write_calibration_factor": w_fac,
+        "hbm_fetch_bytes_per_launch": fetch_b,
+        "hbm_write_bytes_per_launch": write_b,
+        "hbm_bytes_per_launch": fetch_b + write_b,
+        "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+    }
+    with open(out_json, "w") as f:
+        json.dump(d, f, indent=1)
+    return d
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 2 and sys.argv[1] == "run":
+        run(int(sys.argv[2]) if len(sys.argv) > 2 else 10)
+    elif len(sys.argv) == 5 and sys.argv[1] == "summarize":
+        print(json.dumps(summarize(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
+    else:
+        print(__doc__)
+        sys.exit(2)
