@@ -1,0 +1,56 @@
+"""Differentiable objective: rho -> F as a torch.autograd.Function.
+
+The forward solve is the library's forward run (Eqs. Maxwells2 a-c, objective
+Eq. Objective_analyitically_enhancement); the hand-written backward is the
+adjoint run plus the time-exact gradient of Eq. Gradient_FDTD, read straight
+into a device tensor.  Nothing here computes: it binds the density tensor,
+launches the library's calls on torch's current stream and returns its
+results.  Long time-domain runs use the solver's segment checkpoint /
+recompute (set it with Solver.set_checkpointing, or let the solver pick the
+segment count that fits its workspace).
+
+Use a float64 density where the objective is in SI units: the gradient of the
+time-domain objective is of order 1e-47 and underflows float32.  The solve
+itself always runs in FP32 (the density is handed to it as float32).
+"""
+from __future__ import annotations
+
+import torch
+
+from .lib import Solver
+
+
+class CCPRObjective(torch.autograd.Function):
+    """F = CCPRObjective.apply(rho, solver, nsteps, design_lo, gamma).
+
+    rho: CUDA tensor (dz, dy, dx) with values in [0, 1]; solver: a configured
+    Solver with a bound workspace (materials, source and objective set);
+    nsteps: leapfrog steps of the forward run.  Returns F as a 0-d float64
+    tensor on rho's device.  backward() runs the adjoint and returns dF/drho
+    in rho's dtype.
+    """
+
+    @staticmethod
+    def forward(ctx, rho, solver: Solver, nsteps: int, design_lo, gamma: float):
+        if not rho.is_cuda:
+            raise ValueError("rho must be a CUDA tensor")
+        r32 = rho.detach().to(torch.float32).contiguous()
+        solver.set_design(design_lo, r32, gamma)
+        F = solver.forward(int(nsteps))  # synchronises on the objective
+        ctx.solver = solver
+        ctx.rho_dtype = rho.dtype
+        ctx.shape = rho.shape
+        return torch.tensor(F, dtype=torch.float64, device=rho.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        s: Solver = ctx.solver
+        s.adjoint()
+        g = torch.empty(ctx.shape, dtype=torch.float64, device=grad_out.device)
+        s.gradient(out=g)
+        return (grad_out.to(torch.float64) * g).to(ctx.rho_dtype), None, None, None, None
+
+
+def objective(rho, solver: Solver, nsteps: int, design_lo, gamma: float = 0.0):
+    """Functional form of CCPRObjective.apply."""
+    return CCPRObjective.apply(rho, solver, nsteps, design_lo, gamma)

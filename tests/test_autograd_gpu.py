@@ -1,0 +1,112 @@
+"""The differentiable objective (torch.autograd.Function rho -> F) on the GPU:
+its backward (adjoint run + time-exact gradient) against the FP64 oracle's
+adjoint gradient and against FP64 central finite differences of the oracle's
+objective, and, at the full 512x512x256 / 8000-step time-domain size, the
+invariance of F and dF/drho under the checkpoint segment length."""
+import numpy as np
+import pytest
+
+from paper_2305_00234_amd import inputs as I
+from tests.gpu_util import oracle_gradient, rel_l2, require_gpu, say
+from tests.oracle_setup import oracle_objective
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+FD_H = 1e-4
+
+
+def _small(objective):
+    w = I.drude_dipole_32(steps=300, n=32, npml=6)
+    w.shape = (30, 27, 33)
+    w.mat2 = (I.GOLD_TABLE1,) * 3
+    w.design_lo = (10, 9, 11)
+    w.rho = np.random.default_rng(11).random((9, 8, 10)).astype(np.float32)
+    w.dipole_cell = (7, 13, 15)
+    w.gap_lo, w.gap_dims = (14, 12, 15), (2, 2, 2)
+    w.objective = objective
+    if objective == "time":
+        w.window = (60, 280)
+    return w
+
+
+def _autograd_grad(w, rho_dtype, scale=1.0):
+    torch = require_gpu()
+    from paper_2305_00234_amd.autograd import objective
+    from paper_2305_00234_amd.solver import configure
+    s = configure(w)
+    s.bind_torch(w.steps)
+    rho = torch.tensor(w.rho, dtype=rho_dtype, device="cuda", requires_grad=True)
+    F = objective(rho, s, w.steps, w.design_lo, w.gamma)
+    (scale * F).backward()
+    g = rho.grad.detach().double().cpu().numpy()
+    Fv = float(F)
+    s.close()
+    return Fv, g
+
+
+@pytest.mark.parametrize("objective", ["time", "dft"])
+def test_autograd_backward_matches_oracle_adjoint_and_fd(objective):
+    w = _small(objective)
+    say("autograd", objective, w.shape)
+    Fg, gg = _autograd_grad(w, rho_dtype=__import__("torch").float64)
+    Fo, go, _, _ = oracle_gradient(w)
+    say("F", Fg, Fo, "grad rel L2 vs oracle adjoint", rel_l2(gg, go))
+    assert abs(Fg - Fo) <= 1e-5 * abs(Fo)
+    assert rel_l2(gg, go) <= GRAD_TOL
+    # FP64 central finite differences of the oracle objective on 16 voxels
+    rng = np.random.default_rng(100)
+    flat = rng.choice(w.rho.size, size=16, replace=False)
+    fd = []
+    for f in flat:
+        vals = []
+        for sgn in (1, -1):
+            wp = _small(objective)
+            r = wp.rho.astype(np.float64).ravel()
+            r[f] += sgn * FD_H
+            wp.rho = r.reshape(w.rho.shape)
+            vals.append(oracle_objective(wp))
+        fd.append((vals[0] - vals[1]) / (2 * FD_H))
+    fd = np.array(fd)
+    sel = gg.ravel()[flat]
+    say("FD vs autograd (16 voxels) rel L2", rel_l2(sel, fd))
+    assert rel_l2(sel, fd) <= GRAD_TOL
+
+
+def test_autograd_chain_rule_and_float32_density():
+    torch = require_gpu()
+    w = _small("dft")
+    _, g1 = _autograd_grad(w, torch.float64)
+    _, g3 = _autograd_grad(w, torch.float64, scale=3.0)
+    assert np.allclose(g3, 3.0 * g1, rtol=1e-12, atol=0)
+    # float32 density: the DFT gradient of this workload is representable
+    _, g32 = _autograd_grad(w, torch.float32)
+    assert rel_l2(g32, g1) <= 1e-6
+
+
+def test_full_size_time_domain_checkpoint_invariance():
+    """512x512x256 cells, 256x256x64 design, 8000 steps, time-domain objective
+    over the whole run: F and dF/drho are bitwise identical with segments of
+    1000 and of 2000 steps, and the gradient is finite and not zero."""
+    torch = require_gpu()
+    from paper_2305_00234_amd.autograd import objective
+    from paper_2305_00234_amd.solver import configure
+    out = []
+    for every in (1000, 2000):
+        w = I.gold_gap_timedomain_512(checkpoint_every=every)
+        s = configure(w)
+        s.bind_torch(w.steps)
+        rho = torch.tensor(w.rho, dtype=torch.float64, device="cuda", requires_grad=True)
+        F = objective(rho, s, w.steps, w.design_lo, w.gamma)
+        F.backward()
+        info = s.info()
+        say("segments", info, "F", float(F))
+        out.append((float(F), rho.grad.detach().cpu().numpy(), info["segments"]))
+        s.close()
+        del s, rho, F
+        torch.cuda.empty_cache()
+    (F1, g1, s1), (F2, g2, s2) = out
+    assert (s1, s2) == (8, 4)
+    assert F1 == F2 and F1 > 0
+    assert np.array_equal(g1, g2)
+    assert np.isfinite(g1).all() and np.abs(g1).max() > 0
