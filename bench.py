@@ -120,6 +120,97 @@ def cpu_baseline(w, sample_steps):
                       f"objective and gradient ({dt:.1f} s wall)"}
 
 
+def serving(args):
+    """Serving trace (Poisson arrivals, uneven grids and pole counts): the
+    engine's continuous batching against the same solves run one after
+    another with the plain path; same results bitwise, solves/s and p50/p99
+    latency (arrival to result) for both."""
+    import torch
+    from paper_2305_00234_amd import inputs as I
+    from paper_2305_00234_amd.lib import JOB_DONE, JOB_FAILED, Engine
+    from paper_2305_00234_amd.solver import configure
+
+    trace = I.serving_trace(n_requests=args.serving, rate=args.rate, seed=3)
+    arrivals = np.array([r.arrival for r in trace]) - trace[0].arrival
+
+    def progress(msg):
+        print(f"[serving] {msg}", file=sys.stderr, flush=True)
+
+    # sequential plain solves (one at a time, back to back)
+    seq_F, service = [], []
+    for k, r in enumerate(trace):
+        w = r.workload
+        s = configure(w)
+        s.bind_torch(w.steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = s.forward(w.steps)
+        s.adjoint()
+        s.gradient()
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        seq_F.append(F)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    progress(f"sequential: {len(trace)} solves, {sum(service):.2f} s of service")
+    seq_done, t = [], 0.0
+    for a, d in zip(arrivals, service):
+        t = max(t, a) + d
+        seq_done.append(t)
+    seq_lat = np.array(seq_done) - arrivals
+
+    # continuous batching: submit at the arrival times
+    solvers = [configure(r.workload) for r in trace]
+    eng = Engine(args.arena_gb << 30, max_active=args.max_active, chunk_steps=args.chunk)
+    tickets = []
+    t0 = time.perf_counter()
+    k = 0
+    done_t = {}
+    while len(done_t) < len(trace):
+        now = time.perf_counter() - t0
+        while k < len(trace) and arrivals[k] <= now:
+            tickets.append(eng.submit(solvers[k], trace[k].workload.steps))
+            k += 1
+        for q, tk in enumerate(tickets):
+            if q not in done_t:
+                st = eng.poll(tk)
+                if st == JOB_FAILED:
+                    raise RuntimeError(f"served solve {q} failed")
+                if st == JOB_DONE:
+                    done_t[q] = time.perf_counter() - t0
+        time.sleep(0.0005)
+    wall = max(done_t.values())
+    bat_lat = np.array([done_t[q] for q in range(len(trace))]) - arrivals
+    same = True
+    for q, tk in enumerate(tickets):
+        F, _, _ = eng.result(tk)
+        same &= F == seq_F[q]
+        eng.release(tk)
+    eng.close()
+    progress(f"batched: wall {wall:.2f} s, results identical: {same}")
+    seq_wall = seq_done[-1]
+    out = {
+        "metric": "served solves/s (continuous batching) vs sequential plain solves; p50/p99 latency",
+        "value": round(len(trace) / wall, 3),
+        "unit": "solves/s",
+        "sequential_solves_per_s": round(len(trace) / seq_wall, 3),
+        "speedup": round(seq_wall / wall, 3),
+        "latency_ms": {"p50": round(float(np.percentile(bat_lat, 50)) * 1e3, 1),
+                       "p99": round(float(np.percentile(bat_lat, 99)) * 1e3, 1)},
+        "sequential_latency_ms": {"p50": round(float(np.percentile(seq_lat, 50)) * 1e3, 1),
+                                  "p99": round(float(np.percentile(seq_lat, 99)) * 1e3, 1)},
+        "results_identical": bool(same),
+        "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving_trace", "requests": len(trace), "rate_per_s": args.rate,
+                   "sides": "U{64..192}", "pole_pairs": "U{1..3}", "steps": "U{1500..4000}",
+                   "max_active": args.max_active, "chunk_steps": args.chunk,
+                   "arena_GiB": args.arena_gb,
+                   "cell_updates": int(sum(2 * r.workload.cells * r.workload.steps for r in trace))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +222,12 @@ def main():
     ap.add_argument("--tile-planes", type=int, default=None)
     ap.add_argument("--cpu-sample-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="run the serving trace with this many requests instead")
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--max-active", type=int, default=8)
+    ap.add_argument("--chunk", type=int, default=32)
+    ap.add_argument("--arena-gb", type=int, default=96)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -142,6 +239,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
+    if args.serving:
+        serving(args)
+        return
     from paper_2305_00234_amd.solver import solver_for
 
     w = workload_by_name(args.workload, args.solve_steps)

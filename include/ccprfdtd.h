@@ -231,6 +231,59 @@ ccpr_status ccpr_set_tile_planes(ccpr_solver* s, int planes);
  * it. */
 ccpr_status ccpr_set_tile_rows(ccpr_solver* s, int rows);
 
+/* ---- serving engine ----------------------------------------------------- */
+/* Continuous batching of whole solves (forward run, objective, adjoint run,
+ * gradient: the path of ccpr_forward + ccpr_adjoint + ccpr_gradient) for many
+ * solvers of different grids and pole counts.  The engine owns one device
+ * arena and a worker thread: it admits submitted solves in arrival order
+ * while the arena (first fit) and the slot limit allow, binds each to its own
+ * slice of the arena and its own HIP stream (default priority), and keeps all
+ * admitted solves fed with chunks of leapfrog steps so their kernels overlap
+ * on the device.  A solve's objective and gradient are the same as on its own
+ * (the same kernels in the same order).  When a solve finishes, its results
+ * are copied to host memory and its slice and stream are released. */
+
+typedef struct ccpr_engine ccpr_engine;
+
+enum { CCPR_JOB_QUEUED = 0, CCPR_JOB_RUNNING = 1, CCPR_JOB_DONE = 2, CCPR_JOB_FAILED = 3 };
+
+/* arena: device memory the engine sub-allocates for the solves' workspaces
+ * (256-byte aligned, caller-owned, valid until ccpr_engine_destroy returns);
+ * max_active: solves on the device at once (1..64); chunk_steps: leapfrog
+ * steps enqueued per solve per turn.  CCPR_EINVAL on bad arguments. */
+ccpr_status ccpr_engine_create(void* arena, uint64_t arena_bytes, int max_active, int chunk_steps,
+                               ccpr_engine** out);
+
+/* Queue a solve of nsteps forward (and as many adjoint) steps.  The solver must
+ * have its materials, host densities (CCPR_MEM_HOST), source and objective
+ * set; the engine binds it to arena memory while the job runs, so the caller
+ * must not use it until the job is DONE or FAILED (afterwards it is unbound).
+ * CCPR_ENOMEM if its workspace (ccpr_workspace_size) exceeds the arena,
+ * CCPR_ESTATE if the solver already has a job in flight.  *ticket names the
+ * job. */
+ccpr_status ccpr_engine_submit(ccpr_engine* e, ccpr_solver* s, int nsteps, uint64_t* ticket);
+
+/* Current state of a job (CCPR_JOB_*); CCPR_EINVAL for an unknown ticket. */
+ccpr_status ccpr_engine_poll(ccpr_engine* e, uint64_t ticket, int* state);
+
+/* Block until the job is DONE or FAILED; *state (may be NULL) receives it. */
+ccpr_status ccpr_engine_wait(ccpr_engine* e, uint64_t ticket, int* state);
+
+/* Results of a DONE job: the objective (SI), the gradient (host, design-box
+ * shape, x fastest, FP64) and times[3] = {queued, on the device, total} in
+ * seconds; any pointer may be NULL.  CCPR_ESTATE before DONE, CCPR_EDEVICE
+ * for a FAILED job (ccpr_engine_last_error says why). */
+ccpr_status ccpr_engine_result(ccpr_engine* e, uint64_t ticket, double* objective, double* grad,
+                               double* times);
+
+/* Forget a DONE or FAILED job. */
+ccpr_status ccpr_engine_release(ccpr_engine* e, uint64_t ticket);
+
+const char* ccpr_engine_last_error(const ccpr_engine* e);
+
+/* Finish every queued and running job, stop the worker, free the engine. */
+void ccpr_engine_destroy(ccpr_engine* e);
+
 #ifdef __cplusplus
 }
 #endif

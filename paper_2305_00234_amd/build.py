@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libccprfdtd.so")
 ARCH = os.environ.get("CCPR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["ccpr_kernels.hip", "ccpr_solver.cpp"]
+SOURCES = ["ccpr_kernels.hip", "ccpr_solver.cpp", "ccpr_engine.cpp"]
 
 # -packed-fp32-ops: no v_pk_*_f32 from the compiler (they are avoided on this
 # hardware); -ffp-contract=fast lets hipcc fuse a*b+c into FMA.
@@ -31,7 +31,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-fPIC"] + objs + ["-o", tmp]
+    cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-fPIC"] + objs + ["-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,378 @@
+// Serving engine: continuous batching of forward + adjoint + gradient solves.
+//
+// The caller hands over one device arena (allocated by torch in the binding)
+// and submits configured solvers.  A worker thread admits queued solves in
+// arrival order while the arena (first fit) and the slot limit allow, binds
+// each to its own slice of the arena and its own HIP stream, and then keeps
+// every admitted solve fed with chunks of leapfrog steps, round robin, so the
+// small kernels of different solves overlap on the device.  A finished solve's
+// objective and gradient are copied to pinned host memory, its slice and
+// stream are released, and the next queued solve is admitted.  Every solve
+// runs the same kernels in the same order as a solve on its own, so its
+// results do not depend on what else is running.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ccprfdtd.h"
+#include "ccpr_pipeline.h"
+
+namespace {
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Job {
+    uint64_t ticket = 0;
+    ccpr_solver* s = nullptr;
+    int nsteps = 0;
+    uint64_t bytes = 0;
+    int state = CCPR_JOB_QUEUED;
+    uint64_t off = 0;             // arena slice
+    hipStream_t stream = nullptr;
+    std::deque<hipEvent_t> inflight;  // one event per enqueued chunk
+    bool enqueued_all = false;
+    hipEvent_t done_ev = nullptr;
+    double* scal_host = nullptr;  // pinned [8]
+    double* grad_host = nullptr;  // pinned [nd]
+    long long nd = 0;
+    double F = 0;
+    std::vector<double> grad;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    std::string err;
+};
+
+struct Block {
+    uint64_t off, len;
+};
+
+}  // namespace
+
+struct ccpr_engine {
+    char* arena = nullptr;
+    uint64_t arena_bytes = 0;
+    int max_active = 4;
+    int chunk = 32;
+    std::vector<Block> free_list;  // sorted by offset
+    std::mutex mu;
+    std::condition_variable cv;   // worker wake-up and job completion
+    bool stop = false;
+    std::deque<Job*> queue;
+    std::vector<Job*> active;
+    std::map<uint64_t, Job*> jobs;
+    uint64_t next_ticket = 1;
+    std::thread worker;
+    std::string err;
+};
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+
+bool arena_alloc(ccpr_engine* e, uint64_t bytes, uint64_t* off)
+{
+    bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
+    for (size_t q = 0; q < e->free_list.size(); ++q) {
+        Block& b = e->free_list[q];
+        if (b.len >= bytes) {
+            *off = b.off;
+            b.off += bytes;
+            b.len -= bytes;
+            if (b.len == 0) e->free_list.erase(e->free_list.begin() + q);
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(ccpr_engine* e, uint64_t off, uint64_t bytes)
+{
+    bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
+    auto it = std::lower_bound(e->free_list.begin(), e->free_list.end(), off,
+                               [](const Block& b, uint64_t o) { return b.off < o; });
+    it = e->free_list.insert(it, Block{off, bytes});
+    // merge with the neighbours
+    size_t q = it - e->free_list.begin();
+    if (q + 1 < e->free_list.size() && e->free_list[q].off + e->free_list[q].len == e->free_list[q + 1].off) {
+        e->free_list[q].len += e->free_list[q + 1].len;
+        e->free_list.erase(e->free_list.begin() + q + 1);
+    }
+    if (q > 0 && e->free_list[q - 1].off + e->free_list[q - 1].len == e->free_list[q].off) {
+        e->free_list[q - 1].len += e->free_list[q].len;
+        e->free_list.erase(e->free_list.begin() + q);
+    }
+}
+
+void release_device(ccpr_engine* e, Job* j)
+{
+    for (hipEvent_t ev : j->inflight) (void)hipEventDestroy(ev);
+    j->inflight.clear();
+    if (j->done_ev) (void)hipEventDestroy(j->done_ev);
+    j->done_ev = nullptr;
+    if (j->stream) (void)hipStreamDestroy(j->stream);
+    j->stream = nullptr;
+    if (j->scal_host) (void)hipHostFree(j->scal_host);
+    if (j->grad_host) (void)hipHostFree(j->grad_host);
+    j->scal_host = j->grad_host = nullptr;
+    ccpr_pipe_unbind(j->s);
+    arena_free(e, j->off, j->bytes);
+}
+
+void fail_job(ccpr_engine* e, Job* j, const std::string& why)
+{
+    if (j->stream) (void)hipStreamSynchronize(j->stream);
+    j->err = why;
+    release_device(e, j);
+    j->t_done = now_s();
+    j->state = CCPR_JOB_FAILED;
+}
+
+// Admit a queued job: arena slice, stream, pinned result buffers, host set-up.
+// Called by the worker with the lock held (set-up is short and synchronous on
+// the job's new, idle stream).
+bool admit(ccpr_engine* e, Job* j)
+{
+    uint64_t off;
+    if (!arena_alloc(e, j->bytes, &off)) return false;
+    j->off = off;
+    std::string why;
+    if (hipStreamCreateWithFlags(&j->stream, hipStreamNonBlocking) != hipSuccess) why = "hipStreamCreate failed";
+    j->nd = ccpr_pipe_design_voxels(j->s);
+    if (why.empty() && (hipHostMalloc((void**)&j->scal_host, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+                        hipHostMalloc((void**)&j->grad_host, std::max(j->nd, 1LL) * sizeof(double),
+                                      hipHostMallocDefault) != hipSuccess))
+        why = "hipHostMalloc failed";
+    if (why.empty() && ccpr_bind_workspace(j->s, e->arena + off, j->bytes, j->stream) != CCPR_OK)
+        why = std::string("bind: ") + ccpr_last_error(j->s);
+    if (why.empty() && ccpr_pipe_begin(j->s, j->nsteps) != CCPR_OK)
+        why = std::string("set-up: ") + ccpr_last_error(j->s);
+    j->t_admit = now_s();
+    if (!why.empty()) {
+        fail_job(e, j, why);
+        return true;
+    }
+    j->state = CCPR_JOB_RUNNING;
+    return true;
+}
+
+// Feed one running job: retire finished chunks, enqueue up to two chunks in
+// flight, and after the last chunk the result copies.  Returns true if it did
+// any work.
+bool feed(ccpr_engine* e, Job* j)
+{
+    bool worked = false;
+    while (!j->inflight.empty() && hipEventQuery(j->inflight.front()) == hipSuccess) {
+        (void)hipEventDestroy(j->inflight.front());
+        j->inflight.pop_front();
+        worked = true;
+    }
+    while (!j->enqueued_all && j->inflight.size() < 2) {
+        const int n = ccpr_pipe_advance(j->s, e->chunk);
+        if (n < 0) {
+            fail_job(e, j, std::string("step: ") + ccpr_last_error(j->s));
+            return true;
+        }
+        if (n == 0) {
+            if (ccpr_pipe_results(j->s, j->scal_host, j->grad_host) != CCPR_OK ||
+                hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming) != hipSuccess ||
+                hipEventRecord(j->done_ev, j->stream) != hipSuccess) {
+                fail_job(e, j, std::string("results: ") + ccpr_last_error(j->s));
+                return true;
+            }
+            j->enqueued_all = true;
+            worked = true;
+            break;
+        }
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ev, j->stream) != hipSuccess) {
+            fail_job(e, j, "hipEventRecord failed");
+            return true;
+        }
+        j->inflight.push_back(ev);
+        worked = true;
+    }
+    if (j->enqueued_all && hipEventQuery(j->done_ev) == hipSuccess) {
+        double F = 0;
+        if (ccpr_pipe_check(j->s, j->scal_host, &F) != CCPR_OK) {
+            fail_job(e, j, std::string("check: ") + ccpr_last_error(j->s));
+            return true;
+        }
+        j->F = F;
+        j->grad.assign(j->grad_host, j->grad_host + j->nd);
+        release_device(e, j);
+        j->t_done = now_s();
+        j->state = CCPR_JOB_DONE;
+        worked = true;
+    }
+    return worked;
+}
+
+void worker_loop(ccpr_engine* e)
+{
+    std::unique_lock<std::mutex> lk(e->mu);
+    while (true) {
+        if (e->stop && e->queue.empty() && e->active.empty()) break;
+        // admission in arrival order while slots and arena allow
+        while (!e->queue.empty() && (int)e->active.size() < e->max_active) {
+            Job* j = e->queue.front();
+            if (!admit(e, j)) break;
+            e->queue.pop_front();
+            if (j->state == CCPR_JOB_RUNNING) e->active.push_back(j);
+            else e->cv.notify_all();
+        }
+        bool worked = false;
+        for (size_t q = 0; q < e->active.size();) {
+            Job* j = e->active[q];
+            worked |= feed(e, j);
+            if (j->state == CCPR_JOB_DONE || j->state == CCPR_JOB_FAILED) {
+                e->active.erase(e->active.begin() + q);
+                e->cv.notify_all();
+            } else {
+                ++q;
+            }
+        }
+        if (!worked) {
+            // nothing retired or enqueued: let the device progress
+            e->cv.wait_for(lk, std::chrono::microseconds(50));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+ccpr_status ccpr_engine_create(void* arena, uint64_t arena_bytes, int max_active, int chunk_steps,
+                               ccpr_engine** out)
+{
+    if (!out) return CCPR_EINVAL;
+    *out = nullptr;
+    if (!arena || ((uintptr_t)arena & 255) || arena_bytes < kAlign || max_active < 1 || max_active > 64 ||
+        chunk_steps < 1)
+        return CCPR_EINVAL;
+    ccpr_engine* e = new ccpr_engine();
+    e->arena = (char*)arena;
+    e->arena_bytes = arena_bytes & ~(kAlign - 1);
+    e->max_active = max_active;
+    e->chunk = chunk_steps;
+    e->free_list.push_back(Block{0, e->arena_bytes});
+    e->worker = std::thread(worker_loop, e);
+    *out = e;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_engine_submit(ccpr_engine* e, ccpr_solver* s, int nsteps, uint64_t* ticket)
+{
+    if (!e || !s || !ticket || nsteps < 1) return CCPR_EINVAL;
+    uint64_t bytes = 0;
+    ccpr_status st = ccpr_workspace_size(s, nsteps, &bytes);
+    if (st) return st;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (e->stop) return CCPR_ESTATE;
+    if (((bytes + kAlign - 1) & ~(kAlign - 1)) > e->arena_bytes) {
+        e->err = "the solve's workspace exceeds the engine's arena";
+        return CCPR_ENOMEM;
+    }
+    for (auto& kv : e->jobs)
+        if (kv.second->s == s && (kv.second->state == CCPR_JOB_QUEUED || kv.second->state == CCPR_JOB_RUNNING)) {
+            e->err = "this solver already has a job in flight";
+            return CCPR_ESTATE;
+        }
+    Job* j = new Job();
+    j->ticket = e->next_ticket++;
+    j->s = s;
+    j->nsteps = nsteps;
+    j->bytes = bytes;
+    j->t_submit = now_s();
+    e->jobs[j->ticket] = j;
+    e->queue.push_back(j);
+    *ticket = j->ticket;
+    e->cv.notify_all();
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_engine_poll(ccpr_engine* e, uint64_t ticket, int* state)
+{
+    if (!e || !state) return CCPR_EINVAL;
+    std::lock_guard<std::mutex> lk(e->mu);
+    auto it = e->jobs.find(ticket);
+    if (it == e->jobs.end()) return CCPR_EINVAL;
+    *state = it->second->state;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_engine_wait(ccpr_engine* e, uint64_t ticket, int* state)
+{
+    if (!e) return CCPR_EINVAL;
+    std::unique_lock<std::mutex> lk(e->mu);
+    auto it = e->jobs.find(ticket);
+    if (it == e->jobs.end()) return CCPR_EINVAL;
+    Job* j = it->second;
+    e->cv.wait(lk, [&] { return j->state == CCPR_JOB_DONE || j->state == CCPR_JOB_FAILED; });
+    if (state) *state = j->state;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_engine_result(ccpr_engine* e, uint64_t ticket, double* objective, double* grad,
+                               double* times)
+{
+    if (!e) return CCPR_EINVAL;
+    std::lock_guard<std::mutex> lk(e->mu);
+    auto it = e->jobs.find(ticket);
+    if (it == e->jobs.end()) return CCPR_EINVAL;
+    Job* j = it->second;
+    if (j->state == CCPR_JOB_FAILED) {
+        e->err = j->err;
+        return CCPR_EDEVICE;
+    }
+    if (j->state != CCPR_JOB_DONE) return CCPR_ESTATE;
+    if (objective) *objective = j->F;
+    if (grad) std::memcpy(grad, j->grad.data(), j->grad.size() * sizeof(double));
+    if (times) {
+        times[0] = j->t_admit - j->t_submit;
+        times[1] = j->t_done - j->t_admit;
+        times[2] = j->t_done - j->t_submit;
+    }
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_engine_release(ccpr_engine* e, uint64_t ticket)
+{
+    if (!e) return CCPR_EINVAL;
+    std::lock_guard<std::mutex> lk(e->mu);
+    auto it = e->jobs.find(ticket);
+    if (it == e->jobs.end()) return CCPR_EINVAL;
+    if (it->second->state != CCPR_JOB_DONE && it->second->state != CCPR_JOB_FAILED) return CCPR_ESTATE;
+    delete it->second;
+    e->jobs.erase(it);
+    return CCPR_OK;
+}
+
+const char* ccpr_engine_last_error(const ccpr_engine* e) { return e ? e->err.c_str() : ""; }
+
+void ccpr_engine_destroy(ccpr_engine* e)
+{
+    if (!e) return;
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        e->stop = true;
+        e->cv.notify_all();
+    }
+    e->worker.join();
+    for (auto& kv : e->jobs) delete kv.second;
+    delete e;
+}
+
+}  // extern "C"

@@ -176,7 +176,10 @@ int ccpr_launch_copy(float* dst, const float* src, long long n, void* stream);
 int ccpr_launch_scale(float* dst, const float* src, long long n, float s, void* stream);
 int ccpr_launch_extract(float* dst, const float* src, int comp, int nx, int ny, int nz, int nxp, int nyp,
                         float f, void* stream);
-int ccpr_launch_grad_out(double* dst, const double* acc, long long n, double s, void* stream);
+// dst = acc * (*scale)
+int ccpr_launch_grad_out(double* dst, const double* acc, long long n, const double* scale, void* stream);
+// SI objective and scales of a forward run into scal[4..6] (kind 1: DFT, 0: time)
+int ccpr_launch_finish(double* scal, int kind, double a, double dt, double dx, double eps0, void* stream);
 int ccpr_launch_copy_d(double* dst, const double* src, long long n, void* stream);
 int ccpr_launch_incident_line(const double* wave, int nw, int M, int L, double coef, int lo_d,
                               int hi_d, int sgn, int ref, double* lineE, double* lineH,

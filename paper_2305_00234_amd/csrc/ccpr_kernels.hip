@@ -634,11 +634,34 @@ __global__ void extract_kernel(float* __restrict__ d, const float* __restrict__ 
 }
 
 __global__ void grad_out_kernel(double* __restrict__ d, const double* __restrict__ acc, long long n,
-                                double f)
+                                const double* __restrict__ scale)
 {
+    const double f = *scale;
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (long long)gridDim.x * blockDim.x)
         d[t] = acc[t] * f;
+}
+
+// SI results of a forward run from the objective kernel's scaled sums
+// (scal[0] = F', scal[1] = adjoint source scale) and the run's field scale a:
+//   DFT objective:  F = (dt/a)^2 F',  gradient scale 2 dt^2 s / a^2,
+//                   adjoint field scale eps0 a / (2 dt^2 s);
+//   time objective: F = (eps0/2) dx^3 dt F' / a^2,  gradient scale
+//                   eps0 dt dx^3 s / a^2, adjoint field scale a / (dt dx^3 s).
+// Written to scal[4] (F), scal[5] (gradient scale), scal[6] (adjoint scale).
+__global__ void finish_kernel(double* scal, int kind, double a, double dt, double dx, double eps0)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double s = scal[1], dx3 = dx * dx * dx;
+    if (kind == 1) {
+        scal[4] = (dt / a) * (dt / a) * scal[0];
+        scal[5] = 2.0 * dt * dt * s / (a * a);
+        scal[6] = eps0 * a / (2.0 * dt * dt * s);
+    } else {
+        scal[4] = 0.5 * eps0 * dx3 * dt * scal[0] / (a * a);
+        scal[5] = eps0 * dt * dx3 * s / (a * a);
+        scal[6] = a / (dt * dx3 * s);
+    }
 }
 
 __global__ void copy_d_kernel(double* __restrict__ d, const double* __restrict__ s, long long n)
@@ -846,11 +869,17 @@ int ccpr_launch_extract(float* d, const float* src, int comp, int nx, int ny, in
     return (int)hipGetLastError();
 }
 
-int ccpr_launch_grad_out(double* d, const double* acc, long long n, double f, void* stream)
+int ccpr_launch_grad_out(double* d, const double* acc, long long n, const double* scale, void* stream)
 {
     if (n <= 0) return 0;
     hipLaunchKernelGGL(grad_out_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, d, acc,
-                       n, f);
+                       n, scale);
+    return (int)hipGetLastError();
+}
+
+int ccpr_launch_finish(double* scal, int kind, double a, double dt, double dx, double eps0, void* stream)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, scal, kind, a, dt, dx, eps0);
     return (int)hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 
 #include "../../include/ccprfdtd.h"
 #include "ccpr_internal.h"
+#include "ccpr_pipeline.h"
 
 namespace {
 
@@ -117,6 +118,9 @@ struct ccpr_solver {
     std::vector<hipEvent_t> tev;    // event pairs around grid launches of the current loop
     size_t tev_used = 0;
     bool timed_loop = false;        // inside a forward / adjoint loop with timing on
+    // resumable solve (serving engine): phase 0 forward, 1 objective,
+    // 2 adjoint (sub 0: recompute the segment, 1: adjoint steps), 3 all enqueued
+    int pipe_phase = 3, pipe_n = 0, pipe_seg = 0, pipe_sub = 0, pipe_k = 0;
 };
 
 namespace {
@@ -833,6 +837,35 @@ ccpr_status adopt_layout(ccpr_solver* s, int M)
     return CCPR_OK;
 }
 
+// Objective of the finished forward run (gap record -> F', adjoint source
+// table) and its SI values on the device (scal[4..6]).
+ccpr_status launch_objective(ccpr_solver* s)
+{
+    const Layout& L = s->lay;
+    const int M = s->M;
+    const int ne = s->gncell * 3;
+    const int nend = s->ne < 0 ? M + 1 : s->ne;
+    const int kind = s->obj_kind == CCPR_OBJ_DFT_E2 ? 1 : 0;
+    HIPCHK(ccpr_launch_objective(wsp<float>(s, L.gap), M, ne, kind, s->omega * s->dt, s->nb, nend,
+                                 wsp<double>(s, L.scal), wsp<double>(s, L.work), wsp<float>(s, L.src_adj),
+                                 s->stream));
+    HIPCHK(ccpr_launch_finish(wsp<double>(s, L.scal), kind, s->alpha, s->dt, s->g.dx, kEps0, s->stream));
+    return CCPR_OK;
+}
+
+// Host copy of scal[0..7] after a forward run: validity checks and the SI values.
+ccpr_status check_results(ccpr_solver* s, const double* scal)
+{
+    if (!s->rho_on_host && scal[2] != 0.0)
+        return fail(s, CCPR_EINVAL, "device densities must be finite and within [0,1]");
+    s->F = scal[4];
+    s->grad_scale = scal[5];
+    s->adj_alpha = scal[6];
+    if (!std::isfinite(s->F) || !std::isfinite(scal[1]))
+        return fail(s, CCPR_EDIVERGED, "objective is not finite: the fields diverged");
+    return CCPR_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -1168,26 +1201,13 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
     s->current_state = 0;
     const int ne = s->gncell * 3;
     const int nend = s->ne < 0 ? M + 1 : s->ne;
-    HIPCHK(ccpr_launch_objective(wsp<float>(s, L.gap), M, ne, s->obj_kind == CCPR_OBJ_DFT_E2 ? 1 : 0,
-                                 s->omega * s->dt, s->nb, nend, wsp<double>(s, L.scal), wsp<double>(s, L.work),
-                                 wsp<float>(s, L.src_adj), s->stream));
-    double scal[4];
+    st = launch_objective(s);
+    if (st) return st;
+    double scal[8];
     HIPCHK(hipMemcpyAsync(scal, wsp<double>(s, L.scal), sizeof scal, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    if (!s->rho_on_host && scal[2] != 0.0)
-        return fail(s, CCPR_EINVAL, "device densities must be finite and within [0,1]");
-    const double a = s->alpha, dt = s->dt, dx = s->g.dx;
-    if (s->obj_kind == CCPR_OBJ_DFT_E2) {
-        s->F = (dt / a) * (dt / a) * scal[0];
-        s->adj_alpha = kEps0 * a / (2 * dt * dt * scal[1]);
-        s->grad_scale = 2 * dt * dt * scal[1] / (a * a);
-    } else {
-        s->F = 0.5 * kEps0 * dx * dx * dx * dt * scal[0] / (a * a);
-        s->adj_alpha = a / (dt * dx * dx * dx * scal[1]);
-        s->grad_scale = kEps0 * dt * dx * dx * dx * scal[1] / (a * a);
-    }
-    if (!std::isfinite(s->F) || !std::isfinite(scal[1]))
-        return fail(s, CCPR_EDIVERGED, "objective is not finite: the fields diverged");
+    st = check_results(s, scal);
+    if (st) return st;
     s->have_forward = true;
     s->have_adjoint = false;
     if (objective_out) *objective_out = s->F;
@@ -1262,7 +1282,7 @@ ccpr_status ccpr_gradient(ccpr_solver* s, double* grad, int mem)
     if (!s) return CCPR_EINVAL;
     if (!grad || (mem != CCPR_MEM_HOST && mem != CCPR_MEM_DEVICE)) return fail(s, CCPR_EINVAL, "bad gradient arguments");
     if (!s->have_adjoint) return fail(s, CCPR_ESTATE, "gradient needs a completed adjoint run");
-    const double f = s->grad_scale;
+    const double* f = wsp<double>(s, s->lay.scal) + 5;  // gradient scale, on the device
     if (mem == CCPR_MEM_DEVICE) {
         HIPCHK(ccpr_launch_grad_out(grad, wsp<double>(s, s->lay.gradacc), s->nd, f, s->stream));
     } else {
@@ -1329,3 +1349,139 @@ ccpr_status ccpr_set_tile_rows(ccpr_solver* s, int rows)
 }
 
 }  // extern "C"
+
+// ================================================== resumable solve (engine)
+
+ccpr_status ccpr_pipe_begin(ccpr_solver* s, int nsteps)
+{
+    if (!s) return CCPR_EINVAL;
+    if (nsteps < 1) return fail(s, CCPR_EINVAL, "nsteps must be >= 1");
+    ccpr_status st = check_ready(s, true);
+    if (st) return st;
+    if (!s->rho_on_host) return fail(s, CCPR_ENOTSUP, "served solves take host densities");
+    st = adopt_layout(s, nsteps);
+    if (st) return st;
+    st = upload_rho(s);
+    if (st) return st;
+    st = prepare_source(s, nsteps);
+    if (st) return st;
+    s->M = nsteps;
+    st = zero_state(s, 0);
+    if (st) return st;
+    st = upload_cold(s, 0);
+    if (st) return st;
+    st = upload_cold(s, 1);
+    if (st) return st;
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, s->lay.gap), (long long)s->gncell * 3, 0.f, s->stream));
+    s->have_forward = s->have_adjoint = false;
+    s->pipe_phase = 0;
+    s->pipe_n = 0;
+    return CCPR_OK;
+}
+
+int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
+{
+    const Layout& L = s->lay;
+    const int M = s->M, K = L.K, S = L.S;
+    int done = 0;
+    ccpr_status st = CCPR_OK;
+    while (done < max_steps && s->pipe_phase != 3) {
+        if (s->pipe_phase == 0) {  // forward step n
+            const int n = s->pipe_n;
+            if (n == M) {
+                s->pipe_phase = 1;
+                continue;
+            }
+            const int seg = n / K;
+            if (n % K == 0 && seg >= 1 && seg < S) {
+                st = checkpoint(s, seg - 1, true);
+                if (st) return st;
+            }
+            st = forward_step(s, n, seg == S - 1 ? n - seg * K : -1, true);
+            if (st) return st;
+            ++s->pipe_n;
+            ++done;
+        } else if (s->pipe_phase == 1) {  // objective, adjoint set-up
+            st = launch_objective(s);
+            if (st) return st;
+            st = zero_state(s, 1);
+            if (st) return st;
+            HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), std::max(s->nd, 1LL), 0.0, s->stream));
+            s->pipe_phase = 2;
+            s->pipe_seg = S - 1;
+            s->pipe_sub = 1;  // the last segment's history is already written
+            s->pipe_k = 0;
+        } else {  // adjoint over segment pipe_seg
+            const int seg = s->pipe_seg;
+            const int n0 = seg * K, n1 = std::min(M, n0 + K);
+            if (s->pipe_sub == 0) {  // recompute the forward segment, writing the history
+                if (s->pipe_k == 0) {
+                    st = seg == 0 ? zero_state(s, 0) : checkpoint(s, seg - 1, false);
+                    if (st) return st;
+                }
+                const int n = n0 + s->pipe_k;
+                st = forward_step(s, n, n - n0, false);
+                if (st) return st;
+                ++done;
+                if (++s->pipe_k == n1 - n0) {
+                    s->pipe_sub = 1;
+                    s->pipe_k = 0;
+                }
+            } else {  // adjoint step p pairs with forward step n
+                const int n = n1 - 1 - s->pipe_k;
+                StepArgs A = hot_args(s, 1);
+                A.n = M - 1 - n;
+                A.tslot = n - n0;
+                A.mode = CCPR_MODE_CORREL;
+                st = launch_step(s, A, 1);
+                if (st) return st;
+                ++done;
+                if (n == n0) {
+                    if (--s->pipe_seg < 0) {
+                        s->pipe_phase = 3;
+                        s->step_count = M;
+                        s->current_state = 1;
+                    } else {
+                        s->pipe_sub = 0;
+                        s->pipe_k = 0;
+                    }
+                } else {
+                    ++s->pipe_k;
+                }
+            }
+        }
+    }
+    return done;
+}
+
+ccpr_status ccpr_pipe_results(ccpr_solver* s, double* scal_host, double* grad_host)
+{
+    const Layout& L = s->lay;
+    double* stage = wsp<double>(s, L.stage);
+    HIPCHK(ccpr_launch_grad_out(stage, wsp<double>(s, L.gradacc), s->nd, wsp<double>(s, L.scal) + 5, s->stream));
+    HIPCHK(hipMemcpyAsync(grad_host, stage, s->nd * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(scal_host, wsp<double>(s, L.scal), 8 * sizeof(double), hipMemcpyDeviceToHost,
+                          s->stream));
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_pipe_check(ccpr_solver* s, const double* scal_host, double* F)
+{
+    ccpr_status st = check_results(s, scal_host);
+    if (st) return st;
+    s->have_forward = s->have_adjoint = true;
+    if (F) *F = s->F;
+    return CCPR_OK;
+}
+
+long long ccpr_pipe_design_voxels(const ccpr_solver* s) { return s->has_design ? s->nd : 0; }
+
+void ccpr_pipe_unbind(ccpr_solver* s)
+{
+    s->ws = nullptr;
+    s->ws_bytes = 0;
+    s->stream = nullptr;
+    s->have_forward = s->have_adjoint = false;
+    s->rho_uploaded = false;
+    std::memset(s->fixed_key, 0xff, sizeof s->fixed_key);
+}

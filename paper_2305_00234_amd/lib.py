@@ -31,7 +31,10 @@ EXPORTS = [
     "ccpr_adjoint", "ccpr_gradient", "ccpr_reset", "ccpr_step", "ccpr_get_field",
     "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_grid_timing", "ccpr_get_info",
     "ccpr_set_tile_planes", "ccpr_set_tile_rows",
+    "ccpr_engine_create", "ccpr_engine_submit", "ccpr_engine_poll", "ccpr_engine_wait",
+    "ccpr_engine_result", "ccpr_engine_release", "ccpr_engine_last_error", "ccpr_engine_destroy",
 ]
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 
 class CcprGrid(C.Structure):
@@ -90,6 +93,14 @@ def load():
         "ccpr_get_info": (_i, [_p, _ip, _ip, _ip]),
         "ccpr_set_tile_planes": (_i, [_p, _i]),
         "ccpr_set_tile_rows": (_i, [_p, _i]),
+        "ccpr_engine_create": (_i, [_p, C.c_uint64, _i, _i, C.POINTER(_p)]),
+        "ccpr_engine_submit": (_i, [_p, _p, _i, C.POINTER(C.c_uint64)]),
+        "ccpr_engine_poll": (_i, [_p, C.c_uint64, _ip]),
+        "ccpr_engine_wait": (_i, [_p, C.c_uint64, _ip]),
+        "ccpr_engine_result": (_i, [_p, C.c_uint64, _dp, _dp, _dp]),
+        "ccpr_engine_release": (_i, [_p, C.c_uint64]),
+        "ccpr_engine_last_error": (C.c_char_p, [_p]),
+        "ccpr_engine_destroy": (None, [_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -279,3 +290,71 @@ class Solver:
 
     def set_tile_rows(self, rows):
         self._chk(self._lib.ccpr_set_tile_rows(self._h, rows), "ccpr_set_tile_rows")
+
+
+class Engine:
+    """Serving engine (ccpr_engine_*): continuous batching of whole solves.
+
+    The arena is a torch uint8 CUDA tensor owned by this object; the engine
+    sub-allocates the solves' workspaces from it.  Solvers passed to submit()
+    are kept alive here until their job is released."""
+
+    def __init__(self, arena_bytes: int, max_active: int = 4, chunk_steps: int = 32, device=None):
+        import torch
+        self._lib = load()
+        self._arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=torch.device(device or "cuda"))
+        h = _p()
+        st = self._lib.ccpr_engine_create(C.c_void_p(self._arena.data_ptr()), int(arena_bytes), max_active,
+                                          chunk_steps, C.byref(h))
+        if st != OK:
+            raise CcprError(st, "ccpr_engine_create", "bad engine arguments")
+        self._h = h
+        self._solvers = {}
+
+    def _chk(self, st, what):
+        if st != OK:
+            raise CcprError(st, what, self._lib.ccpr_engine_last_error(self._h).decode())
+
+    def submit(self, solver: Solver, nsteps: int) -> int:
+        t = C.c_uint64(0)
+        self._chk(self._lib.ccpr_engine_submit(self._h, solver.handle, int(nsteps), C.byref(t)),
+                  "ccpr_engine_submit")
+        self._solvers[t.value] = solver
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        st = C.c_int(0)
+        self._chk(self._lib.ccpr_engine_poll(self._h, ticket, C.byref(st)), "ccpr_engine_poll")
+        return st.value
+
+    def wait(self, ticket: int) -> int:
+        st = C.c_int(0)
+        self._chk(self._lib.ccpr_engine_wait(self._h, ticket, C.byref(st)), "ccpr_engine_wait")
+        return st.value
+
+    def result(self, ticket: int):
+        """(objective, gradient (dz, dy, dx) float64, (queued, device, total) seconds)."""
+        s = self._solvers[ticket]
+        d = s.design_dims
+        g = np.empty((d[2], d[1], d[0]), dtype=np.float64)
+        F = C.c_double(0.0)
+        times = (C.c_double * 3)()
+        self._chk(self._lib.ccpr_engine_result(self._h, ticket, C.byref(F), g.ctypes.data_as(_dp), times),
+                  "ccpr_engine_result")
+        return F.value, g, tuple(times)
+
+    def release(self, ticket: int):
+        self._chk(self._lib.ccpr_engine_release(self._h, ticket), "ccpr_engine_release")
+        self._solvers.pop(ticket, None)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ccpr_engine_destroy(self._h)
+            self._h = None
+            self._arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

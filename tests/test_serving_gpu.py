@@ -1,0 +1,112 @@
+"""Serving engine (continuous batching) on the GPU: every solve's objective and
+gradient are bitwise the same in the mix as alone, solves arriving while
+others run are admitted as slots and arena memory free up, several solves are
+on the device at once, and a served result meets the oracle bars."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2305_00234_amd import inputs as I
+from tests.gpu_util import oracle_gradient, rel_l2, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [(40, 1, 300), (56, 3, 260), (48, 2, 340), (64, 3, 240), (44, 1, 280), (60, 2, 300)]
+
+
+def _requests():
+    return [I.serving_workload(side, p, steps, seed=500 + k) for k, (side, p, steps) in enumerate(SPECS)]
+
+
+def _alone(w):
+    from paper_2305_00234_amd.solver import configure
+    s = configure(w)
+    s.bind_torch(w.steps)
+    F = s.forward(w.steps)
+    s.adjoint()
+    g = s.gradient()
+    s.close()
+    return F, g
+
+
+def test_mix_equals_alone_and_overlaps():
+    torch = require_gpu()
+    from paper_2305_00234_amd.lib import JOB_DONE, JOB_RUNNING, Engine
+    from paper_2305_00234_amd.solver import configure
+    ws = _requests()
+    alone = [_alone(w) for w in ws]
+    torch.cuda.synchronize()
+    solvers = [configure(w) for w in ws]
+    sizes = [s.workspace_size(w.steps) for s, w in zip(solvers, ws)]
+    arena = int(2.5 * max(sizes))  # not every solve fits at once
+    say("workspaces MB", [round(b / 2**20, 1) for b in sizes], "arena MB", round(arena / 2**20, 1))
+    eng = Engine(arena, max_active=4, chunk_steps=16)
+    tickets = [eng.submit(solvers[0], ws[0].steps), eng.submit(solvers[1], ws[1].steps)]
+    t0 = time.time()
+    while eng.poll(tickets[0]) != JOB_RUNNING and eng.poll(tickets[0]) != JOB_DONE:
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    # later arrivals, admitted while the first ones run
+    tickets += [eng.submit(s, w.steps) for s, w in zip(solvers[2:], ws[2:])]
+    max_running = 0
+    while True:
+        states = [eng.poll(t) for t in tickets]
+        max_running = max(max_running, sum(st == JOB_RUNNING for st in states))
+        if all(st == JOB_DONE for st in states):
+            break
+        assert all(st != 3 for st in states), states
+        assert time.time() - t0 < 120
+        time.sleep(0.0005)
+    say("max solves on the device at once", max_running)
+    assert max_running >= 2
+    for k, (t, (Fa, ga)) in enumerate(zip(tickets, alone)):
+        F, g, times = eng.result(t)
+        say("request", k, ws[k].name, "F", F, Fa, "times", [round(x, 3) for x in times])
+        assert F == Fa
+        assert np.array_equal(g, ga)
+        eng.release(t)
+    eng.close()
+    for s in solvers:
+        s.close()
+
+
+def test_served_result_meets_oracle_bars():
+    require_gpu()
+    from paper_2305_00234_amd.lib import Engine
+    from paper_2305_00234_amd.solver import configure
+    w = I.serving_workload(36, 3, 220, seed=77)
+    s = configure(w)
+    eng = Engine(2 * s.workspace_size(w.steps), max_active=2, chunk_steps=8)
+    t = eng.submit(s, w.steps)
+    eng.wait(t)
+    F, g, _ = eng.result(t)
+    eng.release(t)
+    eng.close()
+    s.close()
+    Fo, go, _, _ = oracle_gradient(w)
+    say("served F", F, Fo, "grad rel L2", rel_l2(g, go))
+    assert abs(F - Fo) <= 1e-5 * abs(Fo)
+    assert rel_l2(g, go) <= 1e-3
+
+
+def test_submit_rejects_oversized_and_duplicate():
+    require_gpu()
+    from paper_2305_00234_amd.lib import CcprError, ENOMEM, ESTATE, Engine
+    from paper_2305_00234_amd.solver import configure
+    w = I.serving_workload(40, 1, 200, seed=5)
+    s = configure(w)
+    eng = Engine(s.workspace_size(w.steps) // 2, max_active=1)
+    with pytest.raises(CcprError) as ei:
+        eng.submit(s, w.steps)
+    assert ei.value.status == ENOMEM
+    eng.close()
+    eng = Engine(4 * s.workspace_size(w.steps), max_active=1)
+    t = eng.submit(s, w.steps)
+    with pytest.raises(CcprError) as ei:
+        eng.submit(s, w.steps)
+    assert ei.value.status == ESTATE
+    eng.wait(t)
+    eng.release(t)
+    eng.close()
+    s.close()
