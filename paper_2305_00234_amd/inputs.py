@@ -250,17 +250,24 @@ def gold_gap_timedomain_512(steps: int = 8000, checkpoint_every: int = 1000) -> 
     return w
 
 
-def aniso_two_material_384(steps: int = 8000) -> Workload:
-    """Anisotropic multi-material: 384^3, dx=4 nm; rho=0 is a dispersive
+def aniso_two_material(n: Tuple[int, int, int], design: Tuple[int, int, int], steps: int,
+                       npml: int = 12, seed: int = 4, name: Optional[str] = None,
+                       gap: int = 4) -> Workload:
+    """Anisotropic multi-material gap problem (dx=4 nm): rho=0 is a dispersive
     dielectric (eps_inf 2.1, Lorentz at 150 nm, d_eps 1, damping 1e14), rho=1
     a diagonal-anisotropic metal (x: Table-1 gold, y: Table-1 aluminium set,
-    z: gold with Im a_p x 1.1); 4 pole pairs per component."""
-    w = gold_gap(n=(384, 384, 384), design=(192, 192, 96), dx=4e-9, steps=steps, seed=4,
-                 name="aniso_two_material_384")
+    z: gold with Im a_p x 1.1); 4 pole pairs per component, different per axis."""
+    w = gold_gap(n=n, design=design, dx=4e-9, steps=steps, seed=seed, npml=npml, gap=gap,
+                 name=name or f"aniso_two_material_{n[0]}x{n[1]}x{n[2]}")
     diel = lorentz(2.1, 1.0, 2 * math.pi * C0 / 150e-9, 1e14)
     w.mat1 = _iso(diel)
     w.mat2 = (GOLD_TABLE1, ALUMINIUM_TABLE1, GOLD_TABLE1.scaled_imag_a(1.1))
     return w
+
+
+def aniso_two_material_384(steps: int = 8000) -> Workload:
+    """The 384^3 anisotropic two-material workload: 192x192x96 design, 8000 steps."""
+    return aniso_two_material((384, 384, 384), (192, 192, 96), steps, name="aniso_two_material_384")
 
 
 @dataclasses.dataclass

@@ -171,3 +171,35 @@ def test_tile_shape_invariance_bitwise():
     b = gpu_fields_after_steps(w, 80, tile_planes=16)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_aniso_two_material_fields_objective_gradient():
+    """Diagonal anisotropy with two dispersive materials: rho=0 a Lorentz
+    dielectric, rho=1 a metal whose pole set differs per axis (4 pairs per
+    component); TF/SF source; fields, objective and gradient vs the oracle."""
+    w = I.aniso_two_material((52, 48, 44), (20, 18, 10), steps=260, npml=6, gap=2, seed=9)
+    _short_pulse(w)
+    say("aniso two-material", w.shape, [m.npairs for m in w.mat1], [m.npairs for m in w.mat2])
+    Fg, gg, fg, _, _ = gpu_gradient(w)
+    Fo, go, fo, _ = oracle_gradient(w)
+    st, eE, eH = field_errors(fg, fo)
+    say("forward state", st, "E", eE, "H", eH, "F", Fg, Fo, "grad rel L2", rel_l2(gg, go))
+    assert st <= FIELD_TOL
+    assert abs(Fg - Fo) <= FIELD_TOL * abs(Fo)
+    assert rel_l2(gg, go) <= GRAD_TOL
+
+
+def test_full_size_320_fields_vs_oracle():
+    """The 320^3 gold gap grid in the launch configuration of the benchmark
+    (2 rows per thread, nominal 8-plane z-chunks balanced over the XCDs,
+    12-cell CPML, TF/SF box): all six field components after 60 steps of an
+    early-starting pulse against the oracle on the full grid."""
+    w = I.gold_gap_320(steps=60)
+    t = np.arange(w.steps + 1) * w.dt
+    w.wave = I.gaussian_sine(t, 300e-9, 0.15e-15, 0.25e-15)
+    say("full-size 320^3 fields, 60 steps")
+    g = gpu_fields_after_steps(w, 60)
+    o = oracle_fields_after_steps(w, 60)
+    st, eE, eH = field_errors(g, o)
+    say("rel L2 state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
