@@ -250,7 +250,9 @@ enum { CCPR_JOB_QUEUED = 0, CCPR_JOB_RUNNING = 1, CCPR_JOB_DONE = 2, CCPR_JOB_FA
 /* arena: device memory the engine sub-allocates for the solves' workspaces
  * (256-byte aligned, caller-owned, valid until ccpr_engine_destroy returns);
  * max_active: solves on the device at once (1..64); chunk_steps: leapfrog
- * steps enqueued per solve per turn.  CCPR_EINVAL on bad arguments. */
+ * steps enqueued per solve per turn.  The engine creates its HIP streams (two
+ * per slot, default priority) here.  CCPR_EINVAL on bad arguments,
+ * CCPR_EDEVICE if the streams cannot be created. */
 ccpr_status ccpr_engine_create(void* arena, uint64_t arena_bytes, int max_active, int chunk_steps,
                                ccpr_engine** out);
 
@@ -270,9 +272,10 @@ ccpr_status ccpr_engine_poll(ccpr_engine* e, uint64_t ticket, int* state);
 ccpr_status ccpr_engine_wait(ccpr_engine* e, uint64_t ticket, int* state);
 
 /* Results of a DONE job: the objective (SI), the gradient (host, design-box
- * shape, x fastest, FP64) and times[3] = {queued, on the device, total} in
- * seconds; any pointer may be NULL.  CCPR_ESTATE before DONE, CCPR_EDEVICE
- * for a FAILED job (ccpr_engine_last_error says why). */
+ * shape, x fastest, FP64) and times[3] = {submitted, admitted to the device,
+ * done} in seconds since the engine was created; any pointer may be NULL.
+ * CCPR_ESTATE before DONE, CCPR_EDEVICE for a FAILED job
+ * (ccpr_engine_last_error says why). */
 ccpr_status ccpr_engine_result(ccpr_engine* e, uint64_t ticket, double* objective, double* grad,
                                double* times);
 

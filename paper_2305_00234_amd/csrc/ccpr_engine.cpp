@@ -40,7 +40,7 @@ struct Job {
     uint64_t bytes = 0;
     int state = CCPR_JOB_QUEUED;
     uint64_t off = 0;             // arena slice
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr, stream2 = nullptr;  // from the engine's pool
     std::deque<hipEvent_t> inflight;  // one event per enqueued chunk
     bool enqueued_all = false;
     hipEvent_t done_ev = nullptr;
@@ -72,6 +72,8 @@ struct ccpr_engine {
     std::vector<Job*> active;
     std::map<uint64_t, Job*> jobs;
     uint64_t next_ticket = 1;
+    std::vector<hipStream_t> streams;  // pool: two per slot, created once
+    double t0 = 0;                     // creation time (job times are relative to it)
     std::thread worker;
     std::string err;
 };
@@ -120,8 +122,9 @@ void release_device(ccpr_engine* e, Job* j)
     j->inflight.clear();
     if (j->done_ev) (void)hipEventDestroy(j->done_ev);
     j->done_ev = nullptr;
-    if (j->stream) (void)hipStreamDestroy(j->stream);
-    j->stream = nullptr;
+    if (j->stream) e->streams.push_back(j->stream);
+    if (j->stream2) e->streams.push_back(j->stream2);
+    j->stream = j->stream2 = nullptr;
     if (j->scal_host) (void)hipHostFree(j->scal_host);
     if (j->grad_host) (void)hipHostFree(j->grad_host);
     j->scal_host = j->grad_host = nullptr;
@@ -147,12 +150,21 @@ bool admit(ccpr_engine* e, Job* j)
     if (!arena_alloc(e, j->bytes, &off)) return false;
     j->off = off;
     std::string why;
-    if (hipStreamCreateWithFlags(&j->stream, hipStreamNonBlocking) != hipSuccess) why = "hipStreamCreate failed";
+    if (e->streams.size() < 2) {
+        why = "no free stream";
+    } else {
+        j->stream = e->streams.back();
+        e->streams.pop_back();
+        j->stream2 = e->streams.back();
+        e->streams.pop_back();
+    }
     j->nd = ccpr_pipe_design_voxels(j->s);
     if (why.empty() && (hipHostMalloc((void**)&j->scal_host, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
                         hipHostMalloc((void**)&j->grad_host, std::max(j->nd, 1LL) * sizeof(double),
                                       hipHostMallocDefault) != hipSuccess))
         why = "hipHostMalloc failed";
+    if (why.empty() && ccpr_pipe_set_stream2(j->s, j->stream2) != CCPR_OK)
+        why = std::string("stream: ") + ccpr_last_error(j->s);
     if (why.empty() && ccpr_bind_workspace(j->s, e->arena + off, j->bytes, j->stream) != CCPR_OK)
         why = std::string("bind: ") + ccpr_last_error(j->s);
     if (why.empty() && ccpr_pipe_begin(j->s, j->nsteps) != CCPR_OK)
@@ -268,6 +280,16 @@ ccpr_status ccpr_engine_create(void* arena, uint64_t arena_bytes, int max_active
     e->max_active = max_active;
     e->chunk = chunk_steps;
     e->free_list.push_back(Block{0, e->arena_bytes});
+    for (int q = 0; q < 2 * max_active; ++q) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (hipStream_t x : e->streams) (void)hipStreamDestroy(x);
+            delete e;
+            return CCPR_EDEVICE;
+        }
+        e->streams.push_back(st);
+    }
+    e->t0 = now_s();
     e->worker = std::thread(worker_loop, e);
     *out = e;
     return CCPR_OK;
@@ -341,9 +363,9 @@ ccpr_status ccpr_engine_result(ccpr_engine* e, uint64_t ticket, double* objectiv
     if (objective) *objective = j->F;
     if (grad) std::memcpy(grad, j->grad.data(), j->grad.size() * sizeof(double));
     if (times) {
-        times[0] = j->t_admit - j->t_submit;
-        times[1] = j->t_done - j->t_admit;
-        times[2] = j->t_done - j->t_submit;
+        times[0] = j->t_submit - e->t0;
+        times[1] = j->t_admit - e->t0;
+        times[2] = j->t_done - e->t0;
     }
     return CCPR_OK;
 }
@@ -372,6 +394,7 @@ void ccpr_engine_destroy(ccpr_engine* e)
     }
     e->worker.join();
     for (auto& kv : e->jobs) delete kv.second;
+    for (hipStream_t st : e->streams) (void)hipStreamDestroy(st);
     delete e;
 }
 

@@ -143,8 +143,9 @@ struct StepArgs {
     int mode;                   // CCPR_MODE_* bits
     const StepCold* cold;
     const int2* zr;             // plane range [k0, k1) of each logical z-chunk
+    const int2* tiles;          // this launch's tiles: (y-strip, logical z-chunk)
     int nys;                    // y strips
-    int nblk;                   // total blocks (nys * z-chunks)
+    int nblk;                   // blocks of this launch (tiles in the list)
 };
 
 #define CCPR_EXTRA_SOURCE 1     // source cell outside the design box
@@ -162,10 +163,10 @@ __host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, in
 }
 
 // Launchers (ccpr_kernels.hip)
-// fused grid step over all cells
-int ccpr_launch_grid(const StepArgs& a, void* stream);
-// aux kernel over naux = nd + nextra + tf_nE threads
-int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long naux, void* stream);
+// fused grid step over the tiles of a.tiles (pml: the CPML variant)
+int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream);
+// aux kernels: nd design voxels, then nmisc = nextra + tf_nE other cells and words
+int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, long long nmisc, void* stream);
 // before a step: x-CPML and TF/SF corrections of H^{n-1/2} (nxs x-layer cells,
 // ntf TF/SF H words); after it: x-CPML of E^{n+1}
 int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* stream);

@@ -149,7 +149,7 @@ __device__ __forceinline__ void stf(float* base, unsigned boff, float v)
     *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff) = v;
 }
 
-// CPML memory update on one derivative d with the old memory p:
+// CPML memory update on one derivative d with the (prefetched) old memory p:
 // p' = b p + a d (stored by the owner only); returns d/kappa + p'.
 __device__ __forceinline__ float cpml(float d, float4 cf, float p, float* pout, unsigned idx, bool store)
 {
@@ -165,8 +165,12 @@ __device__ __forceinline__ float cpml(float d, float4 cf, float p, float* pout, 
 // ccpr_pre_kernel, the x CPML of E^{n+1} afterwards by ccpr_post_kernel: the
 // x layers then cost no extra work inside the x-spanning workgroup.
 // R = 2 rows per thread for any nx (blockDim up to 1024); R = 4 keeps more
-// rows in registers and is limited to blockDim <= 512.
-template <int R>
+// rows in registers and is limited to blockDim <= 512.  PML = false is the
+// variant for tiles that touch no y or z CPML layer (no CPML code at all);
+// PML = true fetches the tile's CPML memories together with the fields at the
+// top of every plane.  The two variants run concurrently on their own tile
+// lists.
+template <int R, bool PML>
 __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const StepArgs a)
 {
     __shared__ float xe[2][R + 1][16];
@@ -174,7 +178,7 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
     const StepCold& c = *a.cold;
 
     // XCD-aware tile order: hardware hands workgroups to the 8 XCDs round
-    // robin; give each XCD a contiguous range of logical tiles (neighbouring
+    // robin; give each XCD a contiguous range of the tile list (neighbouring
     // y-strips share halo rows in that XCD's L2).  Logical z-chunk zl covers
     // planes zr[zl] = [k0, k1): the host sizes chunks to equal work (CPML
     // planes cost more) and spreads them over the XCDs.
@@ -182,8 +186,9 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
     const int per = a.nblk >> 3, rem = a.nblk & 7;
     const int xcd = b & 7, q = b >> 3;
     const int L = xcd * per + (xcd < rem ? xcd : rem) + q;
-    const int ys = L % a.nys, zl = L / a.nys;
-    const int2 kr = a.zr[zl];
+    const int2 tile = a.tiles[L];  // (y-strip, logical z-chunk)
+    const int ys = tile.x;
+    const int2 kr = a.zr[tile.y];
     const int j0 = ys * R;
     const int k0 = kr.x, k1 = kr.y;
 
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
     const int npml = a.npml;
     const int ny = a.ny, nz = a.nz;
     const unsigned lf = a.lanef[i];
-    const bool anypml = npml > 0;
+    const bool anypml = PML && npml > 0;
     const unsigned np2 = 2u * (unsigned)npml;
     const unsigned szy = (unsigned)nz * np2 * nxp;
     const unsigned szz = np2 * ny * nxp;
@@ -259,6 +264,35 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
             rowv[r] = j >= 0 && j < ny && kk >= 0;
             rf[r] = rowv[r] ? a.rowf[(unsigned)kk * ny + j] : 0u;
         }
+        // ---- CPML memories of this plane (PML variant), fetched with the fields
+        float pyh[R + 1][2], pzh[R + 1][2], pye[R + 1][2], pze[R + 1][2];
+        if (anypml) {
+            const bool ecur = kk >= k0;
+#pragma unroll
+            for (int r = 0; r <= R; ++r) {
+                const int j = j0 - 1 + r;
+                pyh[r][0] = pyh[r][1] = pzh[r][0] = pzh[r][1] = 0.f;
+                pye[r][0] = pye[r][1] = pze[r][0] = pze[r][1] = 0.f;
+                if (rf[r] & CCPR_ROW_YPML) {
+                    const unsigned y = yidx(kk, j);
+                    pyh[r][0] = psiHi[1][szy + y];
+                    pyh[r][1] = psiHi[1][y];
+                    if (r >= 1 && ecur) {
+                        pye[r][0] = c.psiE[1][szy + y];
+                        pye[r][1] = c.psiE[1][y];
+                    }
+                }
+                if (rf[r] & CCPR_ROW_ZPML) {
+                    const unsigned z = zidx(kk, j);
+                    pzh[r][0] = psiHi[2][z];
+                    pzh[r][1] = psiHi[2][szz + z];
+                    if (r >= 1 && ecur) {
+                        pze[r][0] = c.psiE[2][z];
+                        pze[r][1] = c.psiE[2][szz + z];
+                    }
+                }
+            }
+        }
 
         // ---- E^n at x+1 (Ey, Ez on rows 0..R)
         if (lane == 0) {
@@ -288,16 +322,14 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
                 if (rf[r] & CCPR_ROW_YPML) {
                     const float4 cf = c.pmlH[1][j];
                     const unsigned y = yidx(kk, j);
-                    const float q0 = psiHi[1][szy + y], q1 = psiHi[1][y];
-                    dxA = cpml(dxA, cf, q0, psiHo[1], szy + y, own && xin);
-                    dzB = cpml(dzB, cf, q1, psiHo[1], y, own && xin);
+                    dxA = cpml(dxA, cf, pyh[r][0], psiHo[1], szy + y, own && xin);
+                    dzB = cpml(dzB, cf, pyh[r][1], psiHo[1], y, own && xin);
                 }
                 if (rf[r] & CCPR_ROW_ZPML) {
                     const float4 cf = c.pmlH[2][kk];
                     const unsigned z = zidx(kk, j);
-                    const float q0 = psiHi[2][z], q1 = psiHi[2][szz + z];
-                    dxB = cpml(dxB, cf, q0, psiHo[2], z, own && xin);
-                    dyA = cpml(dyA, cf, q1, psiHo[2], szz + z, own && xin);
+                    dxB = cpml(dxB, cf, pzh[r][0], psiHo[2], z, own && xin);
+                    dyA = cpml(dyA, cf, pzh[r][1], psiHo[2], szz + z, own && xin);
                 }
             }
             hx[r] = fmaf(-S, dxA - dxB, hxo[r]);
@@ -340,16 +372,14 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
                     if (rf[r] & CCPR_ROW_YPML) {
                         const float4 cf = c.pmlE[1][j];
                         const unsigned y = yidx(kk, j);
-                        const float q0 = c.psiE[1][szy + y], q1 = c.psiE[1][y];
-                        gxA = cpml(gxA, cf, q0, c.psiE[1], szy + y, xin);
-                        gzB = cpml(gzB, cf, q1, c.psiE[1], y, xin);
+                        gxA = cpml(gxA, cf, pye[r][0], c.psiE[1], szy + y, xin);
+                        gzB = cpml(gzB, cf, pye[r][1], c.psiE[1], y, xin);
                     }
                     if (rf[r] & CCPR_ROW_ZPML) {
                         const float4 cf = c.pmlE[2][kk];
                         const unsigned z = zidx(kk, j);
-                        const float q0 = c.psiE[2][z], q1 = c.psiE[2][szz + z];
-                        gxB = cpml(gxB, cf, q0, c.psiE[2], z, xin);
-                        gyA = cpml(gyA, cf, q1, c.psiE[2], szz + z, xin);
+                        gxB = cpml(gxB, cf, pze[r][0], c.psiE[2], z, xin);
+                        gyA = cpml(gyA, cf, pze[r][1], c.psiE[2], szz + z, xin);
                     }
                 }
                 const float dx_ = S * (gxA - gxB), dy_ = S * (gyA - gyB), dz_ = S * (gzA - gzB);
@@ -398,75 +428,84 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
 //  - TF/SF E face words (the next tf_nE threads).  Their cells lie outside
 //    the design, source and gap boxes, so no two threads touch one word.
 // E^{n+1} of these cells is written over the fused kernel's vacuum value.
+// Design voxels, one thread per voxel in box order (x fastest).
 template <int PMAX>
 __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
 {
     const StepCold& c = *a.cold;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned cs = a.cstride;
     const int n = a.n;
-    if (t < c.nd) {
-        const long long v = t;
-        const int i = c.dlo[0] + (int)(v % c.ddim[0]);
-        const long long u = v / c.ddim[0];
-        const int j = c.dlo[1] + (int)(u % c.ddim[1]);
-        const int kk = c.dlo[2] + (int)(u / c.ddim[1]);
-        const unsigned o = (((unsigned)(kk + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
-        // every load first (the current stores alias the later loads otherwise)
-        constexpr int PN = PMAX > 0 ? PMAX : 1;
-        float jrx[PN], jix[PN], jry[PN], jiy[PN], jrz[PN], jiz[PN];
-        j_load<0, PMAX>(c, v, jrx, jix);
-        j_load<1, PMAX>(c, v, jry, jiy);
-        j_load<2, PMAX>(c, v, jrz, jiz);
-        const float e0x = ldf(a.Ei, o), e0y = ldf(a.Ei, o + cs), e0z = ldf(a.Ei, o + 2 * cs);
-        float dx_ = a.drive[v], dy_ = a.drive[c.nd + v], dz_ = a.drive[2 * c.nd + v];
-        const float rho = c.rho[v];
-        float Tox = 0.f, Toy = 0.f, Toz = 0.f;
-        double g0 = 0.0;
-        float* Tslot = c.T + (long long)a.tslot * 3 * c.nd;
-        if (a.mode & CCPR_MODE_CORREL) {
-            Tox = Tslot[v];
-            Toy = Tslot[c.nd + v];
-            Toz = Tslot[2 * c.nd + v];
-            g0 = c.grad[v];
-        }
-        double* sh = nullptr;
-        if (c.src_on && in_box(i, j, kk, c.slo, c.sdim)) {
-            const int ci = box_index(i, j, kk, c.slo, c.sdim);
-            if (n < c.snsteps) {
-                const float* s = c.src + ((long long)n * c.sncell + ci) * 3;
-                dx_ -= s[0];
-                dy_ -= s[1];
-                dz_ -= s[2];
-            }
-            if (c.ssh) sh = c.ssh + (long long)ci * 3;
-        }
-        float Tx, Ty, Tz;
-        const float nxv = e_disp<0, PMAX>(c, e0x, dx_, rho, jrx, jix, &Tx, sh);
-        const float nyv = e_disp<1, PMAX>(c, e0y, dy_, rho, jry, jiy, &Ty, sh ? sh + 1 : nullptr);
-        const float nzv = e_disp<2, PMAX>(c, e0z, dz_, rho, jrz, jiz, &Tz, sh ? sh + 2 : nullptr);
-        j_store<0, PMAX>(c, v, jrx, jix);
-        j_store<1, PMAX>(c, v, jry, jiy);
-        j_store<2, PMAX>(c, v, jrz, jiz);
-        stf(a.Eo, o, nxv);
-        stf(a.Eo, o + cs, nyv);
-        stf(a.Eo, o + 2 * cs, nzv);
-        if (a.mode & CCPR_MODE_RECORD) {
-            Tslot[v] = Tx;
-            Tslot[c.nd + v] = Ty;
-            Tslot[2 * c.nd + v] = Tz;
-        }
-        if (a.mode & CCPR_MODE_CORREL)
-            c.grad[v] = g0 + ((double)nxv * Tox + (double)nyv * Toy + (double)nzv * Toz);
-        if ((a.mode & CCPR_MODE_GAP) && in_box(i, j, kk, c.glo, c.gdim)) {
-            float* g = c.gap + ((long long)(n + 1) * c.gncell + box_index(i, j, kk, c.glo, c.gdim)) * 3;
-            g[0] = nxv;
-            g[1] = nyv;
-            g[2] = nzv;
-        }
-        return;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (unsigned)c.nd) return;
+    const long long v = t;
+    const unsigned dx = c.ddim[0], dy = c.ddim[1];
+    const unsigned row = t / dx;  // 32-bit: the design box holds < 2^31 voxels
+    const int i = c.dlo[0] + (int)(t - row * dx);
+    const int j = c.dlo[1] + (int)(row % dy);
+    const int kk = c.dlo[2] + (int)(row / dy);
+    const unsigned o = (((unsigned)(kk + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
+    // every load first (the current stores alias the later loads otherwise)
+    constexpr int PN = PMAX > 0 ? PMAX : 1;
+    float jrx[PN], jix[PN], jry[PN], jiy[PN], jrz[PN], jiz[PN];
+    j_load<0, PMAX>(c, v, jrx, jix);
+    j_load<1, PMAX>(c, v, jry, jiy);
+    j_load<2, PMAX>(c, v, jrz, jiz);
+    const float e0x = ldf(a.Ei, o), e0y = ldf(a.Ei, o + cs), e0z = ldf(a.Ei, o + 2 * cs);
+    float dx_ = a.drive[v], dy_ = a.drive[c.nd + v], dz_ = a.drive[2 * c.nd + v];
+    const float rho = c.rho[v];
+    float Tox = 0.f, Toy = 0.f, Toz = 0.f;
+    double g0 = 0.0;
+    float* Tslot = c.T + (long long)a.tslot * 3 * c.nd;
+    if (a.mode & CCPR_MODE_CORREL) {
+        Tox = Tslot[v];
+        Toy = Tslot[c.nd + v];
+        Toz = Tslot[2 * c.nd + v];
+        g0 = c.grad[v];
     }
-    const long long e = t - c.nd;
+    double* sh = nullptr;
+    if (c.src_on && in_box(i, j, kk, c.slo, c.sdim)) {
+        const int ci = box_index(i, j, kk, c.slo, c.sdim);
+        if (n < c.snsteps) {
+            const float* s = c.src + ((long long)n * c.sncell + ci) * 3;
+            dx_ -= s[0];
+            dy_ -= s[1];
+            dz_ -= s[2];
+        }
+        if (c.ssh) sh = c.ssh + (long long)ci * 3;
+    }
+    float Tx, Ty, Tz;
+    const float nxv = e_disp<0, PMAX>(c, e0x, dx_, rho, jrx, jix, &Tx, sh);
+    const float nyv = e_disp<1, PMAX>(c, e0y, dy_, rho, jry, jiy, &Ty, sh ? sh + 1 : nullptr);
+    const float nzv = e_disp<2, PMAX>(c, e0z, dz_, rho, jrz, jiz, &Tz, sh ? sh + 2 : nullptr);
+    j_store<0, PMAX>(c, v, jrx, jix);
+    j_store<1, PMAX>(c, v, jry, jiy);
+    j_store<2, PMAX>(c, v, jrz, jiz);
+    stf(a.Eo, o, nxv);
+    stf(a.Eo, o + cs, nyv);
+    stf(a.Eo, o + 2 * cs, nzv);
+    if (a.mode & CCPR_MODE_RECORD) {
+        Tslot[v] = Tx;
+        Tslot[c.nd + v] = Ty;
+        Tslot[2 * c.nd + v] = Tz;
+    }
+    if (a.mode & CCPR_MODE_CORREL)
+        c.grad[v] = g0 + ((double)nxv * Tox + (double)nyv * Toy + (double)nzv * Toz);
+    if ((a.mode & CCPR_MODE_GAP) && in_box(i, j, kk, c.glo, c.gdim)) {
+        float* g = c.gap + ((long long)(n + 1) * c.gncell + box_index(i, j, kk, c.glo, c.gdim)) * 3;
+        g[0] = nxv;
+        g[1] = nyv;
+        g[2] = nzv;
+    }
+}
+
+// Cells outside the design box: source and gap cells (threads [0, nextra)),
+// then the TF/SF E face words.
+__global__ __launch_bounds__(256) void ccpr_aux_misc_kernel(const StepArgs a)
+{
+    const StepCold& c = *a.cold;
+    const unsigned cs = a.cstride;
+    const int n = a.n;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.nextra) {
         // TF/SF E faces: E^{n+1} += coef*incH[n][m]
         const long long f = e - a.nextra;
@@ -784,27 +823,36 @@ int grid_for(long long n) { long long g = (n + 255) / 256; return (int)(g < 4096
 
 }  // namespace
 
-int ccpr_launch_grid(const StepArgs& a, void* stream)
+int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream)
 {
+    if (a.nblk <= 0) return 0;
     dim3 grid(a.nblk), block(a.nxp);
     hipStream_t s = (hipStream_t)stream;
-    if (a.rows == 2) hipLaunchKernelGGL(ccpr_step_kernel<2>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(ccpr_step_kernel<4>, grid, block, 0, s, a);
+    if (a.rows == 2) {
+        if (pml) hipLaunchKernelGGL((ccpr_step_kernel<2, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((ccpr_step_kernel<2, false>), grid, block, 0, s, a);
+    } else {
+        if (pml) hipLaunchKernelGGL((ccpr_step_kernel<4, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((ccpr_step_kernel<4, false>), grid, block, 0, s, a);
+    }
     return (int)hipGetLastError();
 }
 
-int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long naux, void* stream)
+int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, long long nmisc, void* stream)
 {
-    if (naux <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
-    dim3 ag((unsigned)((naux + 255) / 256)), ab(256);
-    if (maxpairs <= 0) hipLaunchKernelGGL(ccpr_aux_kernel<0>, ag, ab, 0, s, a);
-    else if (maxpairs <= 1) hipLaunchKernelGGL(ccpr_aux_kernel<1>, ag, ab, 0, s, a);
-    else if (maxpairs <= 2) hipLaunchKernelGGL(ccpr_aux_kernel<2>, ag, ab, 0, s, a);
-    else if (maxpairs <= 3) hipLaunchKernelGGL(ccpr_aux_kernel<3>, ag, ab, 0, s, a);
-    else if (maxpairs <= 4) hipLaunchKernelGGL(ccpr_aux_kernel<4>, ag, ab, 0, s, a);
-    else if (maxpairs <= 6) hipLaunchKernelGGL(ccpr_aux_kernel<6>, ag, ab, 0, s, a);
-    else hipLaunchKernelGGL(ccpr_aux_kernel<8>, ag, ab, 0, s, a);
+    if (nd > 0) {
+        dim3 ag((unsigned)((nd + 255) / 256)), ab(256);
+        if (maxpairs <= 0) hipLaunchKernelGGL(ccpr_aux_kernel<0>, ag, ab, 0, s, a);
+        else if (maxpairs <= 1) hipLaunchKernelGGL(ccpr_aux_kernel<1>, ag, ab, 0, s, a);
+        else if (maxpairs <= 2) hipLaunchKernelGGL(ccpr_aux_kernel<2>, ag, ab, 0, s, a);
+        else if (maxpairs <= 3) hipLaunchKernelGGL(ccpr_aux_kernel<3>, ag, ab, 0, s, a);
+        else if (maxpairs <= 4) hipLaunchKernelGGL(ccpr_aux_kernel<4>, ag, ab, 0, s, a);
+        else if (maxpairs <= 6) hipLaunchKernelGGL(ccpr_aux_kernel<6>, ag, ab, 0, s, a);
+        else hipLaunchKernelGGL(ccpr_aux_kernel<8>, ag, ab, 0, s, a);
+    }
+    if (nmisc > 0)
+        hipLaunchKernelGGL(ccpr_aux_misc_kernel, dim3((unsigned)((nmisc + 255) / 256)), dim3(256), 0, s, a);
     return (int)hipGetLastError();
 }
 

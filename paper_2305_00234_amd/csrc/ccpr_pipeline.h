@@ -30,3 +30,7 @@ long long ccpr_pipe_design_voxels(const ccpr_solver* s);
 
 // Forget the bound workspace (the engine reuses its memory).
 void ccpr_pipe_unbind(ccpr_solver* s);
+
+// Second stream for the solver's concurrent grid launches (owned by the
+// caller, default priority); must be set before ccpr_pipe_begin.
+ccpr_status ccpr_pipe_set_stream2(ccpr_solver* s, void* stream2);

@@ -46,6 +46,7 @@ struct Layout {
     size_t rowf[2], lanef[2];    // [state] row / lane class words
     size_t extra[2];             // [state] aux-kernel cell list
     size_t zr;                   // z-chunk plane ranges of the step kernel
+    size_t tiles;                // tile lists of the step kernel (interior, then CPML)
     size_t drive;                // S curl H' of the aux kernel's cells (scratch of one step)
     size_t rho, pmlE, pmlH, scal, gradacc, work;
     size_t fixed_end;
@@ -107,6 +108,11 @@ struct ccpr_solver {
     std::vector<int4> extra_host[2];
     std::vector<TfEntry> tf_host;
     std::vector<int2> zr_host;  // plane range of each logical z-chunk
+    std::vector<int2> tiles_host;  // interior tiles, then CPML tiles: (y-strip, logical z-chunk)
+    int ntiles_int = 0, ntiles_pml = 0;
+    hipStream_t stream2 = nullptr;  // second stream: CPML tiles run beside the interior ones
+    bool own_stream2 = false;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int tf_nE = 0, tf_nH = 0;
     long long fixed_key[4] = {-1, -1, -1, -1};
     // diagnostics
@@ -206,6 +212,7 @@ Layout make_layout(const ccpr_solver* s, int M, int K_req)
     }
     L.drive = take((3 * nd + 3 * nsrc) * 4);
     L.zr = take((size_t)(s->g.nz + 1) * sizeof(int2));
+    L.tiles = take((size_t)((s->g.ny + 1) / 2 + 1) * (s->g.nz + 1) * sizeof(int2));
     L.rho = take(nd * 4);
     L.pmlE = take((size_t)(s->g.nx + s->g.ny + s->g.nz) * 16);
     L.pmlH = take((size_t)(s->g.nx + s->g.ny + s->g.nz) * 16);
@@ -615,6 +622,25 @@ void plan_chunks(ccpr_solver* s)
     for (int m = 0; m < n; ++m) phys[m] = make_int2(b[m], b[m + 1]);
     s->zr_host.resize(n);
     for (int q = 0; q < n; ++q) s->zr_host[q] = phys[n % 8 == 0 ? (q % 8) * (n / 8) + q / 8 : q];
+    // tiles (y-strip of 'rows' rows, logical z-chunk) in logical order, split
+    // by whether any of their H or E rows (halo row and plane included) lies
+    // in a y or z CPML layer
+    const int ny = s->g.ny, R = s->rows, nys = (ny + R - 1) / R;
+    std::vector<int2> in, pm;
+    for (int q = 0; q < n; ++q)
+        for (int ys = 0; ys < nys; ++ys) {
+            bool pml = false;
+            if (np > 0) {
+                const int j0 = ys * R - 1, j1 = std::min(ys * R + R, ny);  // rows j0..j1-1
+                const int k0 = s->zr_host[q].x - 1, k1 = s->zr_host[q].y;  // planes k0..k1-1
+                pml = j0 < np || j1 > ny - np || k0 < np || k1 > nz - np;
+            }
+            (pml ? pm : in).push_back(make_int2(ys, q));
+        }
+    s->ntiles_int = (int)in.size();
+    s->ntiles_pml = (int)pm.size();
+    s->tiles_host = in;
+    s->tiles_host.insert(s->tiles_host.end(), pm.begin(), pm.end());
 }
 
 ccpr_status upload_cold(ccpr_solver* s, int st)
@@ -622,6 +648,16 @@ ccpr_status upload_cold(ccpr_solver* s, int st)
     plan_chunks(s);
     HIPCHK(hipMemcpyAsync(s->ws + s->lay.zr, s->zr_host.data(), s->zr_host.size() * sizeof(int2),
                           hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->ws + s->lay.tiles, s->tiles_host.data(), s->tiles_host.size() * sizeof(int2),
+                          hipMemcpyHostToDevice, s->stream));
+    if (s->ntiles_pml > 0 && s->ntiles_int > 0 && !s->stream2) {
+        HIPCHK(hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking));
+        s->own_stream2 = true;
+    }
+    if (s->stream2 && !s->fork_ev) {
+        HIPCHK(hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming));
+    }
     // source and gap cells are finished by the aux kernel before the x-CPML
     // pass of E: they must lie outside the x layers
     if (s->g.npml > 0) {
@@ -680,8 +716,9 @@ StepArgs hot_args(ccpr_solver* s, int st)
     A.tslot = -1;
     A.cold = wsp<StepCold>(s, L.cold[st]);
     A.zr = wsp<int2>(s, L.zr);
+    A.tiles = wsp<int2>(s, L.tiles);
     A.nys = (s->g.ny + s->rows - 1) / s->rows;
-    A.nblk = A.nys * (int)s->zr_host.size();
+    A.nblk = s->ntiles_int;
     return A;
 }
 
@@ -689,7 +726,8 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st)
 {
     const StepCold& C = s->cold_host[st];
     const long long nxs = s->g.npml > 0 ? 2LL * s->g.npml * s->g.ny * s->g.nz : 0;
-    const long long naux = (s->has_design ? s->nd : 0) + A.nextra + (C.pw_on ? C.tf_nE : 0);
+    const long long ndes = s->has_design ? s->nd : 0;
+    const long long nmisc = A.nextra + (C.pw_on ? C.tf_nE : 0);
     int e = ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, s->stream);
     const bool tm = s->timing && s->timed_loop;
     if (tm) {
@@ -700,12 +738,34 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st)
         }
         HIPCHK(hipEventRecord(s->tev[s->tev_used], s->stream));
     }
-    if (e == 0) e = ccpr_launch_grid(A, s->stream);
+    // grid kernel: CPML tiles and interior tiles as two concurrent launches
+    // (both read step-n state only and write disjoint cells)
+    StepArgs Ap = A;
+    Ap.tiles = A.tiles + s->ntiles_int;
+    Ap.nblk = s->ntiles_pml;
+    if (e == 0) {
+        if (s->ntiles_int == 0) {
+            e = ccpr_launch_grid(Ap, true, s->stream);
+        } else if (s->ntiles_pml == 0) {
+            e = ccpr_launch_grid(A, false, s->stream);
+        } else {
+            // the slower CPML tiles go first, on the solver's stream; the
+            // interior tiles fill the device around them
+            HIPCHK(hipEventRecord(s->fork_ev, s->stream));
+            e = ccpr_launch_grid(Ap, true, s->stream);
+            HIPCHK(hipStreamWaitEvent(s->stream2, s->fork_ev, 0));
+            if (e == 0) e = ccpr_launch_grid(A, false, s->stream2);
+            HIPCHK(hipEventRecord(s->join_ev, s->stream2));
+            HIPCHK(hipStreamWaitEvent(s->stream, s->join_ev, 0));
+        }
+    }
     if (tm) {
         HIPCHK(hipEventRecord(s->tev[s->tev_used + 1], s->stream));
         s->tev_used += 2;
     }
-    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, naux, s->stream);
+    // aux and post touch disjoint cells but share the device better in
+    // sequence than side by side (measured)
+    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, ndes, nmisc, s->stream);
     if (e == 0) e = ccpr_launch_post(A, nxs, s->stream);
     if (e != 0) return fail(s, CCPR_EDEVICE, "step kernel launch: %s", hipGetErrorString((hipError_t)e));
     s->parity[st] ^= 1;
@@ -908,6 +968,10 @@ void ccpr_destroy(ccpr_solver* s)
     if (!s) return;
     if (s->ws) (void)hipStreamSynchronize(s->stream);
     for (hipEvent_t ev : s->tev) (void)hipEventDestroy(ev);
+    if (s->stream2) (void)hipStreamSynchronize(s->stream2);
+    if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
+    if (s->join_ev) (void)hipEventDestroy(s->join_ev);
+    if (s->stream2 && s->own_stream2) (void)hipStreamDestroy(s->stream2);
     delete s;
 }
 
@@ -954,6 +1018,7 @@ ccpr_status ccpr_set_design(ccpr_solver* s, const int lo[3], const int dims[3], 
             return fail(s, CCPR_EINVAL, "design box must lie inside the grid, off the walls and outside the CPML");
     if (!std::isfinite(gamma) || gamma < 0) return fail(s, CCPR_EINVAL, "gamma must be finite and >= 0");
     const long long nd = (long long)dims[0] * dims[1] * dims[2];
+    if (nd > 0x7fffffffLL) return fail(s, CCPR_ENOTSUP, "design box above 2^31 voxels");
     if (mem == CCPR_MEM_HOST) {
         for (long long v = 0; v < nd; ++v)
             if (!(rho[v] >= 0.f && rho[v] <= 1.f))
@@ -1476,11 +1541,23 @@ ccpr_status ccpr_pipe_check(ccpr_solver* s, const double* scal_host, double* F)
 
 long long ccpr_pipe_design_voxels(const ccpr_solver* s) { return s->has_design ? s->nd : 0; }
 
+ccpr_status ccpr_pipe_set_stream2(ccpr_solver* s, void* stream2)
+{
+    if (s->stream2 && s->own_stream2) {
+        HIPCHK(hipStreamSynchronize(s->stream2));
+        HIPCHK(hipStreamDestroy(s->stream2));
+    }
+    s->stream2 = (hipStream_t)stream2;
+    s->own_stream2 = false;
+    return CCPR_OK;
+}
+
 void ccpr_pipe_unbind(ccpr_solver* s)
 {
     s->ws = nullptr;
     s->ws_bytes = 0;
     s->stream = nullptr;
+    if (!s->own_stream2) s->stream2 = nullptr;  // the engine's stream goes back to its pool
     s->have_forward = s->have_adjoint = false;
     s->rho_uploaded = false;
     std::memset(s->fixed_key, 0xff, sizeof s->fixed_key);

@@ -333,7 +333,8 @@ class Engine:
         return st.value
 
     def result(self, ticket: int):
-        """(objective, gradient (dz, dy, dx) float64, (queued, device, total) seconds)."""
+        """(objective, gradient (dz, dy, dx) float64, (submitted, admitted, done)
+        in seconds since the engine was created)."""
         s = self._solvers[ticket]
         d = s.design_dims
         g = np.empty((d[2], d[1], d[0]), dtype=np.float64)
