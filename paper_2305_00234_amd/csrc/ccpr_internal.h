@@ -133,6 +133,7 @@ struct StepArgs {
     const int4* extra;          // non-design cells finished by the aux kernel: (i, j, k, kind)
     long long nextra;
     unsigned cstride;           // bytes between field components (npad*4)
+    int stream_st;              // 1: write the streamed state with nontemporal stores
     int nx, ny, nz, nxp, nyp;
     int rows;                   // y rows per thread (2 or 4)
     int npml;
@@ -165,12 +166,14 @@ __host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, in
 // Launchers (ccpr_kernels.hip)
 // fused grid step over the tiles of a.tiles (pml: the CPML variant)
 int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream);
-// aux kernels: nd design voxels, then nmisc = nextra + tf_nE other cells and words
-int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, long long nmisc, void* stream);
+// aux kernel over the nd design voxels
+int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, void* stream);
 // before a step: x-CPML and TF/SF corrections of H^{n-1/2} (nxs x-layer cells,
 // ntf TF/SF H words); after it: x-CPML of E^{n+1}
 int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* stream);
-int ccpr_launch_post(const StepArgs& a, long long nxs, void* stream);
+// after the aux kernel: x-CPML of E^{n+1} (nxs x-layer cells) and the
+// nmisc = nextra + tf_nE source / gap cells and TF/SF E words
+int ccpr_launch_post(const StepArgs& a, long long nxs, long long nmisc, void* stream);
 int ccpr_launch_fill(float* p, long long n, float v, void* stream);
 int ccpr_launch_fill_d(double* p, long long n, double v, void* stream);
 int ccpr_launch_copy(float* dst, const float* src, long long n, void* stream);

@@ -95,6 +95,21 @@ __device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive,
     return En;
 }
 
+// Store of a value that is not read again within the step.  When the state
+// is larger than the last-level cache (StepArgs::stream_st, set by the host)
+// it is written with a nontemporal store: the state then streams through HBM
+// once per step, and keeping these writes out of the caches leaves them to the
+// reads (measured: 670 -> 643 us per step on the 320^3 gold workload).  Small
+// states that fit in the cache keep ordinary stores.  The choice is a
+// template parameter: a run-time flag lets the compiler merge the two stores
+// into one ordinary store before the flag is known.
+template <bool NT>
+__device__ __forceinline__ void st_stream(float* p, float v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Pole currents of component C at voxel v: load / store (pairs p < np).
 template <int C, int PMAX>
 __device__ __forceinline__ void j_load(const StepCold& c, long long v, float* jr, float* ji)
@@ -111,7 +126,7 @@ __device__ __forceinline__ void j_load(const StepCold& c, long long v, float* jr
         }
     }
 }
-template <int C, int PMAX>
+template <int C, int PMAX, bool NT>
 __device__ __forceinline__ void j_store(const StepCold& c, long long v, const float* jr, const float* ji)
 {
     const AxisMat& m = c.mat[C];
@@ -119,8 +134,8 @@ __device__ __forceinline__ void j_store(const StepCold& c, long long v, const fl
     for (int p = 0; p < PMAX; ++p) {
         if (p < m.np) {
             const long long q = m.jofs + p;
-            __builtin_nontemporal_store(jr[p], &c.J[(2 * q) * c.nd + v]);
-            __builtin_nontemporal_store(ji[p], &c.J[(2 * q + 1) * c.nd + v]);
+            st_stream<NT>(&c.J[(2 * q) * c.nd + v], jr[p]);
+            st_stream<NT>(&c.J[(2 * q + 1) * c.nd + v], ji[p]);
         }
     }
 }
@@ -148,13 +163,11 @@ __device__ __forceinline__ void stf(float* base, unsigned boff, float v)
 {
     *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff) = v;
 }
-// Streaming (nontemporal) store of a value that is not read again within the
-// step: the state streams through HBM once per step, and keeping these writes
-// out of the caches leaves them to the reads (measured: 670 -> 643 us per
-// step on the 320^3 gold workload with this and the aux kernel's streams).
+// st_stream at a byte offset from a field base.
+template <bool NT>
 __device__ __forceinline__ void stf_nt(float* base, unsigned boff, float v)
 {
-    __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff));
+    st_stream<NT>(reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff), v);
 }
 
 // CPML memory update on one derivative d with the (prefetched) old memory p:
@@ -177,8 +190,8 @@ __device__ __forceinline__ float cpml(float d, float4 cf, float p, float* pout, 
 // variant for tiles that touch no y or z CPML layer (no CPML code at all);
 // PML = true fetches the tile's CPML memories together with the fields at the
 // top of every plane.  The two variants run concurrently on their own tile
-// lists.
-template <int R, bool PML>
+// lists.  NT: nontemporal stores of the new fields (large states).
+template <int R, bool PML, bool NT>
 __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const StepArgs a)
 {
     __shared__ float xe[2][R + 1][16];
@@ -345,9 +358,9 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
             hz[r] = fmaf(-S, dzA - dzB, hzo[r]);
             if (own && xin) {
                 const unsigned o = poff(kk, r);
-                stf_nt(a.Ho, o, hx[r]);
-                stf_nt(a.Ho, o + cs, hy[r]);
-                stf_nt(a.Ho, o + 2 * cs, hz[r]);
+                stf_nt<NT>(a.Ho, o, hx[r]);
+                stf_nt<NT>(a.Ho, o + cs, hy[r]);
+                stf_nt<NT>(a.Ho, o + 2 * cs, hz[r]);
             }
         }
 
@@ -399,9 +412,9 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
                 if (i == 0) { nyv = 0.f; nzv = 0.f; }
                 if (xin) {
                     const unsigned o = poff(kk, r);
-                    stf_nt(a.Eo, o, nxv);
-                    stf_nt(a.Eo, o + cs, nyv);
-                    stf_nt(a.Eo, o + 2 * cs, nzv);
+                    stf_nt<NT>(a.Eo, o, nxv);
+                    stf_nt<NT>(a.Eo, o + cs, nyv);
+                    stf_nt<NT>(a.Eo, o + 2 * cs, nzv);
                 }
                 // design / source cells: hand the drive to the aux kernel
                 if ((rf[r] & CCPR_ROW_DES) && (lf & CCPR_LANE_DES)) {
@@ -436,8 +449,9 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
 //  - TF/SF E face words (the next tf_nE threads).  Their cells lie outside
 //    the design, source and gap boxes, so no two threads touch one word.
 // E^{n+1} of these cells is written over the fused kernel's vacuum value.
-// Design voxels, one thread per voxel in box order (x fastest).
-template <int PMAX>
+// Design voxels, one thread per voxel in box order (x fastest).  NT:
+// nontemporal stores of the currents, fields and history (large states).
+template <int PMAX, bool NT>
 __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
 {
     const StepCold& c = *a.cold;
@@ -485,16 +499,16 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
     const float nxv = e_disp<0, PMAX>(c, e0x, dx_, rho, jrx, jix, &Tx, sh);
     const float nyv = e_disp<1, PMAX>(c, e0y, dy_, rho, jry, jiy, &Ty, sh ? sh + 1 : nullptr);
     const float nzv = e_disp<2, PMAX>(c, e0z, dz_, rho, jrz, jiz, &Tz, sh ? sh + 2 : nullptr);
-    j_store<0, PMAX>(c, v, jrx, jix);
-    j_store<1, PMAX>(c, v, jry, jiy);
-    j_store<2, PMAX>(c, v, jrz, jiz);
-    stf_nt(a.Eo, o, nxv);
-    stf_nt(a.Eo, o + cs, nyv);
-    stf_nt(a.Eo, o + 2 * cs, nzv);
+    j_store<0, PMAX, NT>(c, v, jrx, jix);
+    j_store<1, PMAX, NT>(c, v, jry, jiy);
+    j_store<2, PMAX, NT>(c, v, jrz, jiz);
+    stf_nt<NT>(a.Eo, o, nxv);
+    stf_nt<NT>(a.Eo, o + cs, nyv);
+    stf_nt<NT>(a.Eo, o + 2 * cs, nzv);
     if (a.mode & CCPR_MODE_RECORD) {
-        __builtin_nontemporal_store(Tx, &Tslot[v]);
-        __builtin_nontemporal_store(Ty, &Tslot[c.nd + v]);
-        __builtin_nontemporal_store(Tz, &Tslot[2 * c.nd + v]);
+        st_stream<NT>(&Tslot[v], Tx);
+        st_stream<NT>(&Tslot[c.nd + v], Ty);
+        st_stream<NT>(&Tslot[2 * c.nd + v], Tz);
     }
     if (a.mode & CCPR_MODE_CORREL)
         c.grad[v] = g0 + ((double)nxv * Tox + (double)nyv * Toy + (double)nzv * Toz);
@@ -506,14 +520,13 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
     }
 }
 
-// Cells outside the design box: source and gap cells (threads [0, nextra)),
-// then the TF/SF E face words.
-__global__ __launch_bounds__(256) void ccpr_aux_misc_kernel(const StepArgs a)
+// Cells outside the design box: source and gap cells (e in [0, nextra)),
+// then the TF/SF E face words.  Runs in the post kernel's launch.
+__device__ __forceinline__ void aux_misc(const StepArgs& a, long long e)
 {
     const StepCold& c = *a.cold;
     const unsigned cs = a.cstride;
     const int n = a.n;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.nextra) {
         // TF/SF E faces: E^{n+1} += coef*incH[n][m]
         const long long f = e - a.nextra;
@@ -607,14 +620,18 @@ __global__ __launch_bounds__(256) void ccpr_pre_kernel(const StepArgs a, long lo
 }
 
 // After step n (grid and aux kernels): the x CPML of E^{n+1} (a.Eo) from
-// H^{n+1/2} (a.Ho), with d the backward x-difference of H:
+// H^{n+1/2} (a.Ho) (threads [0, nxs)), and the cells of aux_misc (the next
+// nmisc threads).  With d the backward x-difference of H:
 //   Ey -= S((1/kappa - 1) d(Hz) + psi'),  Ez += S((1/kappa - 1) d(Hy) + psi').
 // Tangential E on the walls stays zero.
-__global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long long nxs)
+__global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long long nxs, long long nmisc)
 {
     const StepCold& c = *a.cold;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nxs) return;
+    if (t >= nxs) {
+        if (t - nxs < nmisc) aux_misc(a, t - nxs);
+        return;
+    }
     const unsigned cs = a.cstride;
     const int np2 = 2 * a.npml;
     const int xs = (int)(t % np2);
@@ -831,36 +848,47 @@ int grid_for(long long n) { long long g = (n + 255) / 256; return (int)(g < 4096
 
 }  // namespace
 
+template <int R, bool NT>
+void launch_grid_rows(const StepArgs& a, bool pml, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (pml) hipLaunchKernelGGL((ccpr_step_kernel<R, true, NT>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((ccpr_step_kernel<R, false, NT>), grid, block, 0, s, a);
+}
+
 int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream)
 {
     if (a.nblk <= 0) return 0;
     dim3 grid(a.nblk), block(a.nxp);
     hipStream_t s = (hipStream_t)stream;
     if (a.rows == 2) {
-        if (pml) hipLaunchKernelGGL((ccpr_step_kernel<2, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((ccpr_step_kernel<2, false>), grid, block, 0, s, a);
+        if (a.stream_st) launch_grid_rows<2, true>(a, pml, grid, block, s);
+        else launch_grid_rows<2, false>(a, pml, grid, block, s);
     } else {
-        if (pml) hipLaunchKernelGGL((ccpr_step_kernel<4, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((ccpr_step_kernel<4, false>), grid, block, 0, s, a);
+        if (a.stream_st) launch_grid_rows<4, true>(a, pml, grid, block, s);
+        else launch_grid_rows<4, false>(a, pml, grid, block, s);
     }
     return (int)hipGetLastError();
 }
 
-int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, long long nmisc, void* stream)
+template <bool NT>
+void launch_aux_nt(const StepArgs& a, int maxpairs, dim3 ag, dim3 ab, hipStream_t s)
 {
+    if (maxpairs <= 0) hipLaunchKernelGGL((ccpr_aux_kernel<0, NT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 1) hipLaunchKernelGGL((ccpr_aux_kernel<1, NT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 2) hipLaunchKernelGGL((ccpr_aux_kernel<2, NT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 3) hipLaunchKernelGGL((ccpr_aux_kernel<3, NT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 4) hipLaunchKernelGGL((ccpr_aux_kernel<4, NT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 6) hipLaunchKernelGGL((ccpr_aux_kernel<6, NT>), ag, ab, 0, s, a);
+    else hipLaunchKernelGGL((ccpr_aux_kernel<8, NT>), ag, ab, 0, s, a);
+}
+
+int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, void* stream)
+{
+    if (nd <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
-    if (nd > 0) {
-        dim3 ag((unsigned)((nd + 255) / 256)), ab(256);
-        if (maxpairs <= 0) hipLaunchKernelGGL(ccpr_aux_kernel<0>, ag, ab, 0, s, a);
-        else if (maxpairs <= 1) hipLaunchKernelGGL(ccpr_aux_kernel<1>, ag, ab, 0, s, a);
-        else if (maxpairs <= 2) hipLaunchKernelGGL(ccpr_aux_kernel<2>, ag, ab, 0, s, a);
-        else if (maxpairs <= 3) hipLaunchKernelGGL(ccpr_aux_kernel<3>, ag, ab, 0, s, a);
-        else if (maxpairs <= 4) hipLaunchKernelGGL(ccpr_aux_kernel<4>, ag, ab, 0, s, a);
-        else if (maxpairs <= 6) hipLaunchKernelGGL(ccpr_aux_kernel<6>, ag, ab, 0, s, a);
-        else hipLaunchKernelGGL(ccpr_aux_kernel<8>, ag, ab, 0, s, a);
-    }
-    if (nmisc > 0)
-        hipLaunchKernelGGL(ccpr_aux_misc_kernel, dim3((unsigned)((nmisc + 255) / 256)), dim3(256), 0, s, a);
+    dim3 ag((unsigned)((nd + 255) / 256)), ab(256);
+    if (a.stream_st) launch_aux_nt<true>(a, maxpairs, ag, ab, s);
+    else launch_aux_nt<false>(a, maxpairs, ag, ab, s);
     return (int)hipGetLastError();
 }
 
@@ -873,11 +901,12 @@ int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* strea
     return (int)hipGetLastError();
 }
 
-int ccpr_launch_post(const StepArgs& a, long long nxs, void* stream)
+int ccpr_launch_post(const StepArgs& a, long long nxs, long long nmisc, void* stream)
 {
-    if (nxs <= 0) return 0;
-    hipLaunchKernelGGL(ccpr_post_kernel, dim3((unsigned)((nxs + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       a, nxs);
+    const long long n = nxs + nmisc;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(ccpr_post_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       a, nxs, nmisc);
     return (int)hipGetLastError();
 }
 

@@ -708,6 +708,9 @@ StepArgs hot_args(ccpr_solver* s, int st)
     A.extra = wsp<int4>(s, L.extra[st]);
     A.nextra = (long long)s->extra_host[st].size();
     A.cstride = (unsigned)(s->npad * 4);
+    // nontemporal stores once the double-buffered fields exceed the 256 MB
+    // last-level cache (smaller states are reused from it between steps)
+    A.stream_st = 48.0 * (double)s->npad > 256.0 * (1 << 20) ? 1 : 0;
     A.nx = s->g.nx; A.ny = s->g.ny; A.nz = s->g.nz;
     A.nxp = s->nxp; A.nyp = s->nyp; A.rows = s->rows;
     A.npml = s->g.npml;
@@ -743,8 +746,12 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st)
     StepArgs Ap = A;
     Ap.tiles = A.tiles + s->ntiles_int;
     Ap.nblk = s->ntiles_pml;
+    // the split pays for its fork/join only with enough tiles on both sides
+    const bool split = s->stream2 && s->ntiles_int >= 1024 && s->ntiles_pml >= 128;
     if (e == 0) {
-        if (s->ntiles_int == 0) {
+        if (s->ntiles_int == 0 || (!split && s->ntiles_pml > 0)) {
+            Ap.tiles = A.tiles;  // one launch over all tiles
+            Ap.nblk = s->ntiles_int + s->ntiles_pml;
             e = ccpr_launch_grid(Ap, true, s->stream);
         } else if (s->ntiles_pml == 0) {
             e = ccpr_launch_grid(A, false, s->stream);
@@ -765,8 +772,8 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st)
     }
     // aux and post touch disjoint cells but share the device better in
     // sequence than side by side (measured)
-    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, ndes, nmisc, s->stream);
-    if (e == 0) e = ccpr_launch_post(A, nxs, s->stream);
+    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, ndes, s->stream);
+    if (e == 0) e = ccpr_launch_post(A, nxs, nmisc, s->stream);
     if (e != 0) return fail(s, CCPR_EDEVICE, "step kernel launch: %s", hipGetErrorString((hipError_t)e));
     s->parity[st] ^= 1;
     return CCPR_OK;
