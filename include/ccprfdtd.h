@@ -212,8 +212,12 @@ ccpr_status ccpr_set_timing(ccpr_solver* s, int enable);
  * kernels of a step and launch gaps included). */
 ccpr_status ccpr_get_timing(const ccpr_solver* s, double* step_ms_total, long long* step_launches);
 
-/* Accumulated event time [ms] of the grid-kernel launches inside the timed
- * loops and their number (their ratio is the grid kernel's average duration). */
+/* Accumulated event time [ms] of the grid passes inside the timed loops and
+ * their number (their ratio is the grid pass's average duration).  A pass is
+ * one launch of the grid kernel, or two concurrent launches (CPML tiles on
+ * the bound stream, interior tiles on a second stream); it is timed from an
+ * event on the bound stream before the first launch to the later of the
+ * events recorded after each launch on its own stream. */
 ccpr_status ccpr_get_grid_timing(const ccpr_solver* s, double* grid_ms_total, long long* grid_launches);
 
 /* Segment count and length of the last ccpr_forward layout, and the number of

@@ -49,10 +49,12 @@ __device__ __forceinline__ int box_index(int i, int j, int k, const int* lo, con
 // Dispersive E update of component C at design voxel v (see ccpr_internal.h),
 // on currents already in registers: jr/ji hold J^n on entry and J^{n+1} on
 // exit.  sh (may be null): FP64 shadow of E on a source edge; E^{n+1} is then
-// accumulated in FP64 and rounded once.
+// accumulated in FP64 and rounded once, and the new shadow value returned in
+// *shn for the caller to store (no store here: the material constants of the
+// later components then stay scalar loads).
 template <int C, int PMAX>
 __device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive, float rho, float* jr,
-                                        float* ji, float* T, double* sh)
+                                        float* ji, float* T, const double* sh, double* shn)
 {
     const AxisMat& m = c.mat[C];
     const double r = rho, om = 1.0 - r;
@@ -75,7 +77,7 @@ __device__ __forceinline__ float e_disp(const StepCold& c, float E, float drive,
     ra = ra * fma(-A, ra, 2.0);
     const double inc = num * ra;
     float En;
-    if (sh) { *sh += inc; En = (float)*sh; }
+    if (sh) { *shn = *sh + inc; En = (float)*shn; }
     else En = (float)((double)E + inc);
     const float dE = En - E;
     float rnew = 0.f;
@@ -227,8 +229,19 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
     const unsigned np2 = 2u * (unsigned)npml;
     const unsigned szy = (unsigned)nz * np2 * nxp;
     const unsigned szz = np2 * ny * nxp;
-    const float* const* psiHi = c.psiH[a.psi_in];
-    float* const* psiHo = c.psiH[a.psi_in ^ 1];
+    // CPML memory and coefficient pointers, read once before the first store
+    // (scalar loads of global pointers; reloaded inside the loop they would
+    // be vector loads and flat accesses)
+    const float* const pyHi = c.psiH[a.psi_in][1];
+    const float* const pzHi = c.psiH[a.psi_in][2];
+    float* const pyHo = c.psiH[a.psi_in ^ 1][1];
+    float* const pzHo = c.psiH[a.psi_in ^ 1][2];
+    float* const pyE = c.psiE[1];
+    float* const pzE = c.psiE[2];
+    const float4* const cfHy = c.pmlH[1];
+    const float4* const cfHz = c.pmlH[2];
+    const float4* const cfEy = c.pmlE[1];
+    const float4* const cfEz = c.pmlE[2];
 
     auto poff = [&](int k, int r) -> unsigned {
         return (((unsigned)(k + 1) * nyp + (unsigned)(j0 + r)) * nxp + (unsigned)i) * 4u;
@@ -296,20 +309,20 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
                 pye[r][0] = pye[r][1] = pze[r][0] = pze[r][1] = 0.f;
                 if (rf[r] & CCPR_ROW_YPML) {
                     const unsigned y = yidx(kk, j);
-                    pyh[r][0] = psiHi[1][szy + y];
-                    pyh[r][1] = psiHi[1][y];
+                    pyh[r][0] = pyHi[szy + y];
+                    pyh[r][1] = pyHi[y];
                     if (r >= 1 && ecur) {
-                        pye[r][0] = c.psiE[1][szy + y];
-                        pye[r][1] = c.psiE[1][y];
+                        pye[r][0] = pyE[szy + y];
+                        pye[r][1] = pyE[y];
                     }
                 }
                 if (rf[r] & CCPR_ROW_ZPML) {
                     const unsigned z = zidx(kk, j);
-                    pzh[r][0] = psiHi[2][z];
-                    pzh[r][1] = psiHi[2][szz + z];
+                    pzh[r][0] = pzHi[z];
+                    pzh[r][1] = pzHi[szz + z];
                     if (r >= 1 && ecur) {
-                        pze[r][0] = c.psiE[2][z];
-                        pze[r][1] = c.psiE[2][szz + z];
+                        pze[r][0] = pzE[z];
+                        pze[r][1] = pzE[szz + z];
                     }
                 }
             }
@@ -341,16 +354,16 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
             float dzA = eyr[r] - ey[r], dzB = ex[r + 1] - ex[r];
             if (anypml) {
                 if (rf[r] & CCPR_ROW_YPML) {
-                    const float4 cf = c.pmlH[1][j];
+                    const float4 cf = cfHy[j];
                     const unsigned y = yidx(kk, j);
-                    dxA = cpml(dxA, cf, pyh[r][0], psiHo[1], szy + y, own && xin);
-                    dzB = cpml(dzB, cf, pyh[r][1], psiHo[1], y, own && xin);
+                    dxA = cpml(dxA, cf, pyh[r][0], pyHo, szy + y, own && xin);
+                    dzB = cpml(dzB, cf, pyh[r][1], pyHo, y, own && xin);
                 }
                 if (rf[r] & CCPR_ROW_ZPML) {
-                    const float4 cf = c.pmlH[2][kk];
+                    const float4 cf = cfHz[kk];
                     const unsigned z = zidx(kk, j);
-                    dxB = cpml(dxB, cf, pzh[r][0], psiHo[2], z, own && xin);
-                    dyA = cpml(dyA, cf, pzh[r][1], psiHo[2], szz + z, own && xin);
+                    dxB = cpml(dxB, cf, pzh[r][0], pzHo, z, own && xin);
+                    dyA = cpml(dyA, cf, pzh[r][1], pzHo, szz + z, own && xin);
                 }
             }
             hx[r] = fmaf(-S, dxA - dxB, hxo[r]);
@@ -391,16 +404,16 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
                 float gzA = hy[r] - hyl[r], gzB = hx[r] - hx[r - 1];
                 if (anypml) {
                     if (rf[r] & CCPR_ROW_YPML) {
-                        const float4 cf = c.pmlE[1][j];
+                        const float4 cf = cfEy[j];
                         const unsigned y = yidx(kk, j);
-                        gxA = cpml(gxA, cf, pye[r][0], c.psiE[1], szy + y, xin);
-                        gzB = cpml(gzB, cf, pye[r][1], c.psiE[1], y, xin);
+                        gxA = cpml(gxA, cf, pye[r][0], pyE, szy + y, xin);
+                        gzB = cpml(gzB, cf, pye[r][1], pyE, y, xin);
                     }
                     if (rf[r] & CCPR_ROW_ZPML) {
-                        const float4 cf = c.pmlE[2][kk];
+                        const float4 cf = cfEz[kk];
                         const unsigned z = zidx(kk, j);
-                        gxB = cpml(gxB, cf, pze[r][0], c.psiE[2], z, xin);
-                        gyA = cpml(gyA, cf, pze[r][1], c.psiE[2], szz + z, xin);
+                        gxB = cpml(gxB, cf, pze[r][0], pzE, z, xin);
+                        gyA = cpml(gyA, cf, pze[r][1], pzE, szz + z, xin);
                     }
                 }
                 const float dx_ = S * (gxA - gxB), dy_ = S * (gyA - gyB), dz_ = S * (gzA - gzB);
@@ -439,16 +452,11 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
     }
 }
 
-// Finish the cells the fused step left to it, one thread per cell or word:
-//  - design voxels (threads [0, nd)): CCPR pole-pair update of the three E
-//    edges from E^n and the stored drive (minus a source current if the voxel
-//    is also a source cell), the gradient record (forward) or correlation
-//    (adjoint), and the gap monitor;
-//  - extra cells (threads [nd, nd+nextra)): source cells outside the design
-//    (vacuum update with FP64 accumulation) and gap cells outside both;
-//  - TF/SF E face words (the next tf_nE threads).  Their cells lie outside
-//    the design, source and gap boxes, so no two threads touch one word.
-// E^{n+1} of these cells is written over the fused kernel's vacuum value.
+// Finish the design voxels the fused step left to it, one thread per voxel:
+// CCPR pole-pair update of the three E edges from E^n and the stored drive
+// (minus a source current if the voxel is also a source cell), the gradient
+// record (forward) or correlation (adjoint), and the gap monitor.  E^{n+1} of
+// these cells is written over the fused kernel's vacuum value.
 // Design voxels, one thread per voxel in box order (x fastest).  NT:
 // nontemporal stores of the currents, fields and history (large states).
 template <int PMAX, bool NT>
@@ -496,9 +504,15 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
         if (c.ssh) sh = c.ssh + (long long)ci * 3;
     }
     float Tx, Ty, Tz;
-    const float nxv = e_disp<0, PMAX>(c, e0x, dx_, rho, jrx, jix, &Tx, sh);
-    const float nyv = e_disp<1, PMAX>(c, e0y, dy_, rho, jry, jiy, &Ty, sh ? sh + 1 : nullptr);
-    const float nzv = e_disp<2, PMAX>(c, e0z, dz_, rho, jrz, jiz, &Tz, sh ? sh + 2 : nullptr);
+    double shn[3];
+    const float nxv = e_disp<0, PMAX>(c, e0x, dx_, rho, jrx, jix, &Tx, sh, &shn[0]);
+    const float nyv = e_disp<1, PMAX>(c, e0y, dy_, rho, jry, jiy, &Ty, sh ? sh + 1 : nullptr, &shn[1]);
+    const float nzv = e_disp<2, PMAX>(c, e0z, dz_, rho, jrz, jiz, &Tz, sh ? sh + 2 : nullptr, &shn[2]);
+    if (sh) {
+        sh[0] = shn[0];
+        sh[1] = shn[1];
+        sh[2] = shn[2];
+    }
     j_store<0, PMAX, NT>(c, v, jrx, jix);
     j_store<1, PMAX, NT>(c, v, jry, jiy);
     j_store<2, PMAX, NT>(c, v, jrz, jiz);
