@@ -226,7 +226,7 @@ ccpr_status ccpr_get_grid_timing(const ccpr_solver* s, double* grid_ms_total, lo
 ccpr_status ccpr_get_info(const ccpr_solver* s, int* segments, int* segment_steps, int* tile_planes);
 
 /* Launch shape: nominal z-planes per workgroup of the step kernel (default
- * 8; the planes are split into about nz/planes chunks of equal estimated
+ * 5; the planes are split into about nz/planes chunks of equal estimated
  * cost, so chunks in the CPML are thinner).  Results do not depend on it. */
 ccpr_status ccpr_set_tile_planes(ccpr_solver* s, int planes);
 

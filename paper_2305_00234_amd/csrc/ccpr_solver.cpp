@@ -92,7 +92,7 @@ struct ccpr_solver {
     uint64_t ws_bytes = 0;
     hipStream_t stream = nullptr;
     int maxpairs = 0, npairs_total = 0;
-    int tz = 8;                 // nominal planes per z-chunk of the step kernel
+    int tz = 5;                 // nominal planes per z-chunk of the step kernel
     // run state
     int parity[2] = {0, 0};
     int step_count = 0;
@@ -601,13 +601,17 @@ void fill_extra(const StepCold& C, std::vector<int4>& ex)
 // together.  Logical chunk q of XCD-contiguous order gets physical chunk
 // (q % 8) * (n/8) + q / 8 when n is a multiple of 8, which spreads the
 // expensive chunks over the XCDs.
+#ifndef CCPR_ZPML_PLANE_COST
+#define CCPR_ZPML_PLANE_COST 1.6
+#endif
 void plan_chunks(ccpr_solver* s)
 {
     const int nz = s->g.nz, np = s->g.npml;
     int n = std::max(1, std::min(nz, (nz + s->tz - 1) / s->tz));
     if (n >= 8 && nz >= 8 * ((n + 7) / 8)) n = (n + 7) / 8 * 8;
     std::vector<double> cum(nz + 1, 0.0);
-    for (int k = 0; k < nz; ++k) cum[k + 1] = cum[k] + ((np > 0 && (k < np || k >= nz - np)) ? 1.6 : 1.0);
+    for (int k = 0; k < nz; ++k)
+        cum[k + 1] = cum[k] + ((np > 0 && (k < np || k >= nz - np)) ? CCPR_ZPML_PLANE_COST : 1.0);
     std::vector<int> b(n + 1);
     b[0] = 0;
     b[n] = nz;
@@ -621,7 +625,10 @@ void plan_chunks(ccpr_solver* s)
     std::vector<int2> phys(n);
     for (int m = 0; m < n; ++m) phys[m] = make_int2(b[m], b[m + 1]);
     s->zr_host.resize(n);
-    for (int q = 0; q < n; ++q) s->zr_host[q] = phys[n % 8 == 0 ? (q % 8) * (n / 8) + q / 8 : q];
+#ifndef CCPR_CHUNK_SPREAD
+#define CCPR_CHUNK_SPREAD 1
+#endif
+    for (int q = 0; q < n; ++q) s->zr_host[q] = phys[CCPR_CHUNK_SPREAD && n % 8 == 0 ? (q % 8) * (n / 8) + q / 8 : q];
     // tiles (y-strip of 'rows' rows, logical z-chunk) in logical order, split
     // by whether any of their H or E rows (halo row and plane included) lies
     // in a y or z CPML layer
