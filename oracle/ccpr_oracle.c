@@ -572,19 +572,29 @@ static void record_gap(const or_sim* s, const int* lo, const int* dims, double* 
                 for (int a = 0; a < 3; ++a) out[c * 3 + a] = s->F[a][idx3(s, i, j, k)];
 }
 
-/* Forward run with gap recording (and the gradient factors when T_hist is not
- * NULL), then the objective and its derivative dF/dE^n at every gap edge. */
+/* Forward run with gap recording, then the objective and its derivative
+ * dF/dE^n at every gap edge.  Gradient factors: with T_hist the whole history
+ * T^{n+1/2} is kept; with T_hat (and T_hist NULL) only its transform at omega,
+ * T_hat[v*3+k] = sum_{n=0}^{M-1} T_k^{n+1/2}(v) exp(-j omega n dt). */
 static int forward_and_objective(or_sim* s, int M, int kind, const int* glo, const int* gdim,
-                                 double omega, int nb, int ne, double* T_hist, double* F_out,
-                                 double* hist, double* dFdE)
+                                 double omega, int nb, int ne, double* T_hist, cplx* T_hat,
+                                 double* F_out, double* hist, double* dFdE)
 {
     int ncell = gdim[0] * gdim[1] * gdim[2];
+    double* T_step = (!T_hist && T_hat) ? malloc((size_t)s->nd * 3 * sizeof(double)) : NULL;
+    if (T_hat) memset(T_hat, 0, (size_t)s->nd * 3 * sizeof(cplx));
     or_reset(s);
     record_gap(s, glo, gdim, hist);
     for (int n = 0; n < M; ++n) {
-        step_once(s, T_hist ? T_hist + (size_t)n * s->nd * 3 : NULL);
+        double* T = T_hist ? T_hist + (size_t)n * s->nd * 3 : T_step;
+        step_once(s, T);
         record_gap(s, glo, gdim, hist + (size_t)(n + 1) * ncell * 3);
+        if (T_hat) {
+            cplx ph = cexp(-I * omega * n * s->dt);
+            for (size_t q = 0; q < (size_t)s->nd * 3; ++q) T_hat[q] += T[q] * ph;
+        }
     }
+    free(T_step);
     double dt = s->dt, F = 0.0;
     size_t ne_tot = (size_t)(M + 1) * ncell * 3;
     memset(dFdE, 0, ne_tot * sizeof(double));
@@ -621,36 +631,22 @@ int or_objective(or_sim* s, int nsteps, int obj_kind, const int* gap_lo, const i
     double* hist = malloc(ne * sizeof(double));
     double* dFdE = malloc(ne * sizeof(double));
     forward_and_objective(s, nsteps, obj_kind, gap_lo, gap_dims, omega, n_begin, n_end, NULL,
-                          F_out, hist, dFdE);
+                          NULL, F_out, hist, dFdE);
     free(hist); free(dFdE);
     return 0;
 }
 
-/* Time-exact discrete adjoint.  The adjoint system (supplement Eqs.
- * Tranformations, AdjointSystem) is the forward update run again from zero
- * fields with the time-reversed source S_adj = dF/dE: at adjoint step p the gap
- * edges carry the current (1/dt) dF/dE^{M-p}, injected exactly like J_src.
- * Writing Et^m for the adjoint E after m steps, the gradient (Eq. Gradient_FDTD
- * with the index pairing of the exact discrete adjoint) is
- *   dF/drho_v = sum_k sum_{n=0}^{M-1} Et_k^{M-n}(v) T_k^{n+1/2}(v),
- * where T is the per-edge factor recorded by edge_update. */
-int or_gradient(or_sim* s, int nsteps, int obj_kind, const int* gap_lo, const int* gap_dims,
-                double omega, int n_begin, int n_end, double* F_out, double* grad_out,
-                double* gap_hist_out)
+/* Adjoint run shared by both gradient estimators.  The adjoint system
+ * (supplement Eqs. Tranformations, AdjointSystem) is the forward update run
+ * again from zero fields with the time-reversed source S_adj = dF/dE: at
+ * adjoint step p the gap edges carry the current (1/dt) dF/dE^{M-p}, injected
+ * exactly like J_src, and the forward sources are off.  After adjoint step p
+ * visit(s, p, ctx) sees the adjoint fields Et^{p+1}.  The forward sources are
+ * restored afterwards; the simulation is left holding the adjoint fields. */
+static void adjoint_run(or_sim* s, int M, const int* gap_lo, const int* gap_dims,
+                        const double* dFdE, void (*visit)(or_sim*, int, void*), void* ctx)
 {
-    if (nsteps < 1 || s->nd < 1 || !gap_ok(s, gap_lo, gap_dims)) return -1;
-    const int M = nsteps, nd = s->nd;
     int ncell = gap_dims[0] * gap_dims[1] * gap_dims[2];
-    size_t ne = (size_t)(M + 1) * ncell * 3;
-    double* hist = malloc(ne * sizeof(double));
-    double* dFdE = malloc(ne * sizeof(double));
-    double* T_hist = malloc((size_t)M * nd * 3 * sizeof(double));
-    if (!hist || !dFdE || !T_hist) { free(hist); free(dFdE); free(T_hist); return -1; }
-    forward_and_objective(s, M, obj_kind, gap_lo, gap_dims, omega, n_begin, n_end, T_hist,
-                          F_out, hist, dFdE);
-    if (gap_hist_out) memcpy(gap_hist_out, hist, ne * sizeof(double));
-
-    /* adjoint source table, adjoint step p uses (1/dt) dF/dE^{M-p} */
     double* adj = malloc((size_t)M * ncell * 3 * sizeof(double));
     for (int p = 0; p < M; ++p)
         for (int e = 0; e < ncell * 3; ++e)
@@ -666,17 +662,9 @@ int or_gradient(or_sim* s, int nsteps, int obj_kind, const int* gap_lo, const in
     s->pw_on = 0;
     or_set_box_source(s, gap_lo, gap_dims, adj, M);
     or_reset(s);
-    for (int v = 0; v < nd; ++v) grad_out[v] = 0.0;
     for (int p = 0; p < M; ++p) {
         step_once(s, NULL);
-        const double* T = T_hist + (size_t)(M - 1 - p) * nd * 3;
-        for (int k = 0; k < s->ddim[2]; ++k)
-            for (int j = 0; j < s->ddim[1]; ++j)
-                for (int i = 0; i < s->ddim[0]; ++i) {
-                    int v = (k * s->ddim[1] + j) * s->ddim[0] + i;
-                    size_t id = idx3(s, s->dlo[0] + i, s->dlo[1] + j, s->dlo[2] + k);
-                    for (int a = 0; a < 3; ++a) grad_out[v] += s->F[a][id] * T[(size_t)v * 3 + a];
-                }
+        visit(s, p, ctx);
     }
     /* restore the forward sources */
     free(s->bs_table);
@@ -688,7 +676,141 @@ int or_gradient(or_sim* s, int nsteps, int obj_kind, const int* gap_lo, const in
     s->bs_on = bs_on;
     s->dip_on = dip_on;
     s->pw_on = pw_on;
-    free(adj); free(hist); free(dFdE); free(T_hist);
+    free(adj);
+}
+
+/* adjoint E of the three edges of design voxel v */
+static void design_E(const or_sim* s, int v, double* e3)
+{
+    int i = v % s->ddim[0], j = (v / s->ddim[0]) % s->ddim[1], k = v / (s->ddim[0] * s->ddim[1]);
+    size_t id = idx3(s, s->dlo[0] + i, s->dlo[1] + j, s->dlo[2] + k);
+    for (int a = 0; a < 3; ++a) e3[a] = s->F[a][id];
+}
+
+typedef struct {
+    int M;
+    const double* T_hist;
+    double* grad;
+} exact_ctx;
+
+static void exact_visit(or_sim* s, int p, void* vctx)
+{
+    exact_ctx* c = (exact_ctx*)vctx;
+    const double* T = c->T_hist + (size_t)(c->M - 1 - p) * s->nd * 3;
+    for (int v = 0; v < s->nd; ++v) {
+        double e3[3];
+        design_E(s, v, e3);
+        for (int a = 0; a < 3; ++a) c->grad[v] += e3[a] * T[(size_t)v * 3 + a];
+    }
+}
+
+/* Time-exact discrete gradient.  Writing Et^m for the adjoint E after m
+ * adjoint steps, the gradient (Eq. Gradient_FDTD with the index pairing of
+ * the exact discrete adjoint) is
+ *   dF/drho_v = sum_k sum_{n=0}^{M-1} Et_k^{M-n}(v) T_k^{n+1/2}(v),
+ * where T is the per-edge factor recorded by edge_update. */
+int or_gradient(or_sim* s, int nsteps, int obj_kind, const int* gap_lo, const int* gap_dims,
+                double omega, int n_begin, int n_end, double* F_out, double* grad_out,
+                double* gap_hist_out)
+{
+    if (nsteps < 1 || s->nd < 1 || !gap_ok(s, gap_lo, gap_dims)) return -1;
+    const int M = nsteps, nd = s->nd;
+    int ncell = gap_dims[0] * gap_dims[1] * gap_dims[2];
+    size_t ne = (size_t)(M + 1) * ncell * 3;
+    double* hist = malloc(ne * sizeof(double));
+    double* dFdE = malloc(ne * sizeof(double));
+    double* T_hist = malloc((size_t)M * nd * 3 * sizeof(double));
+    if (!hist || !dFdE || !T_hist) { free(hist); free(dFdE); free(T_hist); return -1; }
+    forward_and_objective(s, M, obj_kind, gap_lo, gap_dims, omega, n_begin, n_end, T_hist, NULL,
+                          F_out, hist, dFdE);
+    if (gap_hist_out) memcpy(gap_hist_out, hist, ne * sizeof(double));
+    for (int v = 0; v < nd; ++v) grad_out[v] = 0.0;
+    exact_ctx c = {M, T_hist, grad_out};
+    adjoint_run(s, M, gap_lo, gap_dims, dFdE, exact_visit, &c);
+    free(hist); free(dFdE); free(T_hist);
+    return 0;
+}
+
+int or_dft_window(int nsteps, double omega, double dt)
+{
+    const double per = 2.0 * acos(-1.0) / (omega * dt);   /* steps per period */
+    const int q = (int)floor(0.5 * nsteps / per);   /* whole periods in half the run */
+    int L = q >= 1 ? (int)lround(q * per) : nsteps / 2;
+    if (L < 2) L = nsteps < 2 ? nsteps : 2;
+    if (L > nsteps) L = nsteps;
+    return L;
+}
+
+typedef struct {
+    int m0;                 /* first adjoint field index of the window */
+    double theta;           /* omega dt */
+    cplx* P;                /* [nd*3]: sum over the window of Et^m exp(-j theta m) */
+    double scc, sss, scs;   /* the window's normal matrix */
+} dft_ctx;
+
+static void dft_visit(or_sim* s, int p, void* vctx)
+{
+    dft_ctx* c = (dft_ctx*)vctx;
+    const int m = p + 1;
+    if (m < c->m0) return;
+    const double cs = cos(c->theta * m), sn = sin(c->theta * m);
+    c->scc += cs * cs;
+    c->sss += sn * sn;
+    c->scs += cs * sn;
+    const cplx ph = cexp(-I * c->theta * m);
+    for (int v = 0; v < s->nd; ++v) {
+        double e3[3];
+        design_E(s, v, e3);
+        for (int a = 0; a < 3; ++a) c->P[(size_t)v * 3 + a] += e3[a] * ph;
+    }
+}
+
+/* Single-frequency (DFT-mode) gradient estimator for OR_OBJ_DFT.  The adjoint
+ * source of the DFT objective is a sinusoid of frequency omega; once its
+ * transient has died out the adjoint field is Et^m = Re{A exp(j theta m)},
+ * theta = omega dt, with one complex amplitude A per design edge.  Put into
+ * the time-exact sum above this gives
+ *   dF/drho_v ~ sum_k Re{ A_k(v) exp(j theta M) T_hat_k(v) },
+ *   T_hat_k(v) = sum_{n=0}^{M-1} T_k^{n+1/2}(v) exp(-j theta n),
+ * so the forward run keeps only T_hat and the adjoint run only a projection.
+ * A is the least-squares fit of a cos(theta m) + b sin(theta m) (A = a - j b)
+ * to Et^m over the window of the last L adjoint fields, m in [M-L+1, M], with
+ * L = or_dft_window(M, omega, dt): the whole periods that fit in half the
+ * run (half the run if that is less than one period).  The estimate tends to
+ * the time-exact gradient as the run outlasts the forward pulse and the
+ * adjoint transient. */
+int or_gradient_dft(or_sim* s, int nsteps, const int* gap_lo, const int* gap_dims, double omega,
+                    double* F_out, double* grad_out)
+{
+    if (nsteps < 2 || s->nd < 1 || !(omega > 0) || !gap_ok(s, gap_lo, gap_dims)) return -1;
+    const int M = nsteps, nd = s->nd;
+    int ncell = gap_dims[0] * gap_dims[1] * gap_dims[2];
+    size_t ne = (size_t)(M + 1) * ncell * 3;
+    double* hist = malloc(ne * sizeof(double));
+    double* dFdE = malloc(ne * sizeof(double));
+    cplx* T_hat = malloc((size_t)nd * 3 * sizeof(cplx));
+    cplx* P = calloc((size_t)nd * 3, sizeof(cplx));
+    if (!hist || !dFdE || !T_hat || !P) { free(hist); free(dFdE); free(T_hat); free(P); return -1; }
+    forward_and_objective(s, M, OR_OBJ_DFT, gap_lo, gap_dims, omega, 0, -1, NULL, T_hat, F_out,
+                          hist, dFdE);
+    const int L = or_dft_window(M, omega, s->dt);
+    dft_ctx c = {M - L + 1, omega * s->dt, P, 0.0, 0.0, 0.0};
+    adjoint_run(s, M, gap_lo, gap_dims, dFdE, dft_visit, &c);
+    /* [scc scs; scs sss] [a; b] = [sum Et cos; sum Et sin] = [Re P; -Im P] */
+    const double det = c.scc * c.sss - c.scs * c.scs;
+    const cplx W = cexp(I * omega * s->dt * M);
+    for (int v = 0; v < nd; ++v) {
+        double g = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const cplx Pk = P[(size_t)v * 3 + k];
+            const double rc = creal(Pk), rs = -cimag(Pk);
+            const double a = (c.sss * rc - c.scs * rs) / det;
+            const double b = (c.scc * rs - c.scs * rc) / det;
+            g += creal((a - I * b) * W * T_hat[(size_t)v * 3 + k]);
+        }
+        grad_out[v] = g;
+    }
+    free(hist); free(dFdE); free(T_hat); free(P);
     return 0;
 }
 

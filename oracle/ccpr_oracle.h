@@ -91,6 +91,22 @@ int or_gradient(or_sim* s, int nsteps, int obj_kind, const int* gap_lo,
                 const int* gap_dims, double omega, int n_begin, int n_end,
                 double* F_out, double* grad_out, double* gap_hist_out);
 
+/* DFT-mode gradient estimator for OR_OBJ_DFT (single frequency omega): the
+ * forward run keeps T_hat_k(v) = sum_n T_k^{n+1/2}(v) exp(-j omega n dt)
+ * instead of the history; the adjoint field's steady state is fitted as
+ * Et^m = Re{A exp(j omega dt m)} (least squares over the last L adjoint
+ * fields, L = or_dft_window); grad_v = sum_k Re{A_k exp(j omega dt M) T_hat_k}.
+ * Approximate: tends to or_gradient's result as the fields decay within the
+ * run.  Leaves the simulation holding the adjoint fields.  Returns 0 or -1. */
+int or_gradient_dft(or_sim* s, int nsteps, const int* gap_lo, const int* gap_dims,
+                    double omega, double* F_out, double* grad_out);
+
+/* Adjoint fields in the DFT-mode fit window: the whole periods of
+ * 2 pi / (omega dt) steps that fit in half the run, rounded to whole steps
+ * (half the run when that is less than one period; at least 2, at most
+ * nsteps). */
+int or_dft_window(int nsteps, double omega, double dt);
+
 /* Objective only (forward run, no adjoint). */
 int or_objective(or_sim* s, int nsteps, int obj_kind, const int* gap_lo,
                  const int* gap_dims, double omega, int n_begin, int n_end,

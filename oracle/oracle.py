@@ -51,6 +51,9 @@ def _lib():
         lib.or_set_field.argtypes = [_p, _i, _dp]
         lib.or_gradient.argtypes = [_p, _i, _i, _ip, _ip, _d, _i, _i, _dp, _dp, _dp]
         lib.or_objective.argtypes = [_p, _i, _i, _ip, _ip, _d, _i, _i, _dp]
+        lib.or_gradient_dft.argtypes = [_p, _i, _ip, _ip, _d, _dp, _dp]
+        lib.or_dft_window.restype = _i
+        lib.or_dft_window.argtypes = [_i, _d, _d]
         lib.or_edge_response.argtypes = [_p, _i, _d, _d, _dp, _i, _dp]
         lib.or_eps_ccpr.argtypes = [_p, _i, _d, _d, _d, _dp, _dp]
         lib.or_num_threads.restype = _i
@@ -181,6 +184,16 @@ class OracleSim:
         g = g.reshape(d[2], d[1], d[0])
         return (F.value, g, hist) if want_hist else (F.value, g)
 
+    def gradient_dft(self, nsteps, gap_lo, gap_dims, omega):
+        """DFT-mode gradient estimator of the DFT objective (or_gradient_dft)."""
+        nd = int(np.prod(self.design_dims))
+        F = C.c_double(0.0)
+        g = np.zeros(nd, dtype=np.float64)
+        self._chk(_lib().or_gradient_dft(self._h, nsteps, _iv(gap_lo), _iv(gap_dims), omega,
+                                         C.byref(F), g.ctypes.data_as(_dp)), "DFT-mode gradient")
+        d = self.design_dims
+        return F.value, g.reshape(d[2], d[1], d[0])
+
     def objective(self, nsteps, kind, gap_lo, gap_dims, omega=0.0, n_begin=0, n_end=None):
         if n_end is None:
             n_end = nsteps + 1
@@ -188,6 +201,10 @@ class OracleSim:
         self._chk(_lib().or_objective(self._h, nsteps, kind, _iv(gap_lo), _iv(gap_dims), omega,
                                       n_begin, n_end, C.byref(F)), "objective")
         return F.value
+
+    @staticmethod
+    def dft_window(nsteps, omega, dt):
+        return int(_lib().or_dft_window(nsteps, omega, dt))
 
     def edge_response(self, axis, rho, gamma, src):
         s, sp = _dv(src)
