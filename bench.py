@@ -66,7 +66,9 @@ def step_bytes(w):
     E^n + 12 B drive read + 12 B E^{n+1} write; 32 B per (cell, x CPML layer)
     (psi of H and of E, read + write) plus 16 B of E and H for each; the
     gradient history: 12 B record (forward), 12 B read + 16 B FP64 accumulator
-    read/write (adjoint)."""
+    read/write (adjoint); DFT-mode gradient instead: 24 B complex transform
+    of T read + write (forward), 24 B projection of the adjoint E read + write
+    over the fit window (about half the adjoint steps)."""
     nx, ny, nz = w.shape
     nd = int(np.prod(w.design_dims))
     pairs = sum(w.mat1[a].npairs + w.mat2[a].npairs for a in range(3))
@@ -74,7 +76,10 @@ def step_bytes(w):
     x_layer_cells = 2 * p * ny * nz if p else 0
     design = (16 * pairs + 4 + 36) * nd
     xpml = (32 + 16) * x_layer_cells
-    record = (12 * nd + (12 + 16) * nd) / 2.0
+    if w.gradient == "dft":
+        record = (48 * nd + 48 * nd * 0.5) / 2.0
+    else:
+        record = (12 * nd + (12 + 16) * nd) / 2.0
     return algorithmic_bytes(w) + design + xpml + record
 
 
@@ -220,6 +225,8 @@ def main():
     ap.add_argument("--solve-steps", type=int, default=None,
                     help="leapfrog steps per solve (default: the workload's)")
     ap.add_argument("--tile-planes", type=int, default=None)
+    ap.add_argument("--gradient", choices=["time", "dft"], default="time",
+                    help="time: exact discrete gradient (default); dft: single-frequency estimator")
     ap.add_argument("--cpu-sample-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=0,
@@ -245,6 +252,7 @@ def main():
     from paper_2305_00234_amd.solver import solver_for
 
     w = workload_by_name(args.workload, args.solve_steps)
+    w.gradient = args.gradient
     M = w.steps
     s = solver_for(w)
     if args.tile_planes:
@@ -312,7 +320,7 @@ def main():
                    "leapfrog_steps_per_solve": M, "design": list(w.design_dims),
                    "pole_pairs_per_axis": w.max_pairs(), "cpml": w.npml,
                    "source": w.source, "objective": w.objective,
-                   "gradient": "time-exact",
+                   "gradient": "time-exact" if w.gradient == "time" else "dft",
                    "history_segments": info["segments"], "tile_planes": info["tile_planes"]},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 2)},

@@ -56,6 +56,7 @@ typedef enum {
 
 enum { CCPR_MEM_HOST = 0, CCPR_MEM_DEVICE = 1 };
 enum { CCPR_OBJ_TIME_E2 = 0, CCPR_OBJ_DFT_E2 = 1 };
+enum { CCPR_GRAD_TIME_EXACT = 0, CCPR_GRAD_DFT = 1 };
 enum { CCPR_EX = 0, CCPR_EY, CCPR_EZ, CCPR_HX, CCPR_HY, CCPR_HZ };
 
 #define CCPR_MAX_PAIRS_PER_AXIS 8 /* pole pairs over both materials, per axis */
@@ -150,6 +151,26 @@ ccpr_status ccpr_set_objective(ccpr_solver* s, int kind, const int lo[3], const 
  * Results are bit-identical for every segment size. */
 ccpr_status ccpr_set_checkpointing(ccpr_solver* s, int checkpoint_every);
 
+/* Gradient estimator (default CCPR_GRAD_TIME_EXACT: the exact discrete
+ * gradient of ccpr_gradient, from the stored or recomputed forward history).
+ * CCPR_GRAD_DFT, for the single-frequency objective CCPR_OBJ_DFT_E2 only
+ * (CCPR_EINVAL at ccpr_forward otherwise): on-the-fly DFT correlation.  The
+ * adjoint source of that objective is a sinusoid of frequency omega, so once
+ * its transient has died out the adjoint field is Et^m = Re{A exp(j th m)},
+ * th = omega dt, one complex amplitude A per design edge; in the sum of Eq.
+ * Gradient_FDTD this gives
+ *   dF/drho_v ~ sum_k Re{ A_k(v) exp(j th M) That_k(v) },
+ *   That_k(v) = sum_{n=0}^{M-1} T_k^{n+1/2}(v) exp(-j th n).
+ * The forward run keeps That (6 floats per voxel) instead of the history, the
+ * adjoint run projects Et^m onto exp(-j th m) over the window of its last L
+ * fields (L: the whole periods of 2 pi / th steps that fit in half the run,
+ * rounded to whole steps; half the run if shorter than one period), and A is
+ * the least-squares fit a - j b of a cos(th m) + b sin(th m) over that window.
+ * Needs no checkpoints (checkpoint_every is ignored) and 48 bytes per design
+ * voxel; approximate: it tends to the time-exact gradient as the run
+ * outlasts the forward pulse and the adjoint transient. */
+ccpr_status ccpr_set_gradient_mode(ccpr_solver* s, int mode);
+
 /* Device bytes needed for a forward + adjoint + gradient solve of nsteps
  * (nsteps = 0: field stepping only) with the current configuration and
  * checkpoint_every (0: full history).  Drives admission in serving. */
@@ -161,8 +182,8 @@ ccpr_status ccpr_workspace_size(const ccpr_solver* s, int nsteps, uint64_t* byte
 ccpr_status ccpr_bind_workspace(ccpr_solver* s, void* dev_ptr, uint64_t bytes, void* hip_stream);
 
 /* Forward run of nsteps from zero fields, recording the gap monitor and the
- * gradient history, then the objective (synchronises the stream to return
- * *objective_out, which may be NULL). */
+ * gradient history (DFT gradient mode: its transform), then the objective
+ * (synchronises the stream to return *objective_out, which may be NULL). */
 ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out);
 
 /* Adjoint run (same update, zero initial fields, time-reversed source
@@ -178,7 +199,8 @@ ccpr_status ccpr_adjoint(ccpr_solver* s);
  *   dF/drho_v = sum_k sum_{n=0}^{M-1} Et_k^{M-n}(v) T_k^{n+1/2}(v),
  *   T = eps0 deps_k (E^{n+1}-E^n) + dsig_k,eff dt (E^{n+1}+E^n)/2
  *       + dt sum_p dkappa_p Re{J_p^{n+1}+J_p^n},
- * Et^m the adjoint E after m adjoint steps, dsig_eff = sig2-sig1+(1-2 rho) gamma.
+ * Et^m the adjoint E after m adjoint steps, dsig_eff = sig2-sig1+(1-2 rho) gamma
+ * (DFT gradient mode: the estimate of ccpr_set_gradient_mode).
  * CCPR_ESTATE before ccpr_adjoint. */
 ccpr_status ccpr_gradient(ccpr_solver* s, double* grad, int mem);
 

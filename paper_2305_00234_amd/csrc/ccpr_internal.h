@@ -106,7 +106,9 @@ struct StepCold {
     int gap_on, glo[3], gdim[3], gncell;
     float* gap;
 
-    float* T;                   // gradient history [slot][3][nd]
+    float* T;                   // time-exact mode: gradient history [slot][3][nd];
+                                // DFT mode: [12][nd], the forward transform of T
+                                // (re, im of x, y, z) then the adjoint projection
     double* grad;               // adjoint: per-voxel accumulator
 };
 
@@ -142,6 +144,8 @@ struct StepArgs {
     int psi_in;                 // which H-side psi buffer holds psi^{n-1/2}
     int tslot;                  // gradient-history slot of this step (-1: none)
     int mode;                   // CCPR_MODE_* bits
+    float phc, phs;             // DFT modes: cos, sin of omega dt n (forward step n)
+                                // or of omega dt m (adjoint field m)
     const StepCold* cold;
     const int2* zr;             // plane range [k0, k1) of each logical z-chunk
     const int2* tiles;          // this launch's tiles: (y-strip, logical z-chunk)
@@ -155,6 +159,8 @@ struct StepArgs {
 #define CCPR_MODE_RECORD 1      // forward: write T of this step to slot tslot
 #define CCPR_MODE_CORREL 2      // adjoint: grad += E^{n+1} . T[tslot]
 #define CCPR_MODE_GAP 4         // forward: record the gap monitor
+#define CCPR_MODE_DFT_T 8       // forward, DFT mode: T_hat += T exp(-j phase)
+#define CCPR_MODE_DFT_P 16      // adjoint, DFT mode: P += E^{n+1} exp(-j phase)
 
 // floats of the psi memory of derivative axis a (both components)
 __host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, int nxp, int npml)
@@ -181,6 +187,11 @@ int ccpr_launch_scale(float* dst, const float* src, long long n, float s, void* 
 int ccpr_launch_extract(float* dst, const float* src, int comp, int nx, int ny, int nz, int nxp, int nyp,
                         float f, void* stream);
 // dst = acc * (*scale)
+// DFT-mode gradient: grad[v] = sum_k Re{A_k W T_hat_k} with A_k from the
+// adjoint projection P_k and the inverse window normal matrix (i00, i01, i11),
+// W = (wc, ws)
+int ccpr_launch_dft_grad(double* grad, const float* acc, long long nd, double i00, double i01, double i11,
+                         double wc, double ws, void* stream);
 int ccpr_launch_grad_out(double* dst, const double* acc, long long n, const double* scale, void* stream);
 // SI objective and scales of a forward run into scal[4..6] (kind 1: DFT, 0: time)
 int ccpr_launch_finish(double* scal, int kind, double a, double dt, double dx, double eps0, void* stream);

@@ -459,7 +459,7 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
 // these cells is written over the fused kernel's vacuum value.
 // Design voxels, one thread per voxel in box order (x fastest).  NT:
 // nontemporal stores of the currents, fields and history (large states).
-template <int PMAX, bool NT>
+template <int PMAX, bool NT, bool DFT>
 __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
 {
     const StepCold& c = *a.cold;
@@ -491,6 +491,15 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
         Toy = Tslot[c.nd + v];
         Toz = Tslot[2 * c.nd + v];
         g0 = c.grad[v];
+    }
+    // DFT mode (DFT: the launch carries CCPR_MODE_DFT_T or _P): running
+    // transforms (re, im per component) of T (forward) or of the adjoint E
+    // (adjoint window)
+    float* const dacc = c.T + ((a.mode & CCPR_MODE_DFT_P) ? 6 * c.nd : 0);
+    float dq[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if constexpr (DFT) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) dq[q] = dacc[q * c.nd + v];
     }
     double* sh = nullptr;
     if (c.src_on && in_box(i, j, kk, c.slo, c.sdim)) {
@@ -526,6 +535,17 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
     }
     if (a.mode & CCPR_MODE_CORREL)
         c.grad[v] = g0 + ((double)nxv * Tox + (double)nyv * Toy + (double)nzv * Toz);
+    if constexpr (DFT) {
+        // x exp(-j phase) = x (cos - j sin)
+        const bool fwd = (a.mode & CCPR_MODE_DFT_T) != 0;
+        const float x0 = fwd ? Tx : nxv, x1 = fwd ? Ty : nyv, x2 = fwd ? Tz : nzv;
+        dacc[v] = fmaf(x0, a.phc, dq[0]);
+        dacc[c.nd + v] = fmaf(-x0, a.phs, dq[1]);
+        dacc[2 * c.nd + v] = fmaf(x1, a.phc, dq[2]);
+        dacc[3 * c.nd + v] = fmaf(-x1, a.phs, dq[3]);
+        dacc[4 * c.nd + v] = fmaf(x2, a.phc, dq[4]);
+        dacc[5 * c.nd + v] = fmaf(-x2, a.phs, dq[5]);
+    }
     if ((a.mode & CCPR_MODE_GAP) && in_box(i, j, kk, c.glo, c.gdim)) {
         float* g = c.gap + ((long long)(n + 1) * c.gncell + box_index(i, j, kk, c.glo, c.gdim)) * 3;
         g[0] = nxv;
@@ -666,6 +686,29 @@ __global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long l
     ps[sz + x] = p1;
     if (k != 0) stf(a.Eo, o + cs, ldf(a.Eo, o + cs) - a.S * fmaf(cf.z - 1.f, dHz, p0));
     if (j != 0) stf(a.Eo, o + 2 * cs, ldf(a.Eo, o + 2 * cs) + a.S * fmaf(cf.z - 1.f, dHy, p1));
+}
+
+// DFT-mode gradient of each design voxel (see ccpr_set_gradient_mode): the
+// adjoint amplitude A_k = a - j b solves the window's least-squares normal
+// equations [a; b] = inv [Re P_k; -Im P_k] (inverse i00 i01; i01 i11), and
+// grad = sum_k Re{A_k W T_hat_k}, all in FP64.
+__global__ void dft_grad_kernel(double* grad, const float* acc, long long nd, double i00, double i01, double i11,
+                                double wc, double ws)
+{
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nd;
+         v += (long long)gridDim.x * blockDim.x) {
+        double g = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double tr = acc[(2 * k) * nd + v], ti = acc[(2 * k + 1) * nd + v];
+            const double rc = acc[(6 + 2 * k) * nd + v], rs = -(double)acc[(7 + 2 * k) * nd + v];
+            const double ar = i00 * rc + i01 * rs, ab = i01 * rc + i11 * rs;  // A = ar - j ab
+            // A W = (ar wc + ab ws) + j (ar ws - ab wc)
+            const double awr = ar * wc + ab * ws, awi = ar * ws - ab * wc;
+            g += awr * tr - awi * ti;
+        }
+        grad[v] = g;
+    }
 }
 
 __global__ void fill_kernel(float* p, long long n, float v)
@@ -884,16 +927,16 @@ int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream)
     return (int)hipGetLastError();
 }
 
-template <bool NT>
+template <bool NT, bool DFT>
 void launch_aux_nt(const StepArgs& a, int maxpairs, dim3 ag, dim3 ab, hipStream_t s)
 {
-    if (maxpairs <= 0) hipLaunchKernelGGL((ccpr_aux_kernel<0, NT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 1) hipLaunchKernelGGL((ccpr_aux_kernel<1, NT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 2) hipLaunchKernelGGL((ccpr_aux_kernel<2, NT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 3) hipLaunchKernelGGL((ccpr_aux_kernel<3, NT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 4) hipLaunchKernelGGL((ccpr_aux_kernel<4, NT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 6) hipLaunchKernelGGL((ccpr_aux_kernel<6, NT>), ag, ab, 0, s, a);
-    else hipLaunchKernelGGL((ccpr_aux_kernel<8, NT>), ag, ab, 0, s, a);
+    if (maxpairs <= 0) hipLaunchKernelGGL((ccpr_aux_kernel<0, NT, DFT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 1) hipLaunchKernelGGL((ccpr_aux_kernel<1, NT, DFT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 2) hipLaunchKernelGGL((ccpr_aux_kernel<2, NT, DFT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 3) hipLaunchKernelGGL((ccpr_aux_kernel<3, NT, DFT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 4) hipLaunchKernelGGL((ccpr_aux_kernel<4, NT, DFT>), ag, ab, 0, s, a);
+    else if (maxpairs <= 6) hipLaunchKernelGGL((ccpr_aux_kernel<6, NT, DFT>), ag, ab, 0, s, a);
+    else hipLaunchKernelGGL((ccpr_aux_kernel<8, NT, DFT>), ag, ab, 0, s, a);
 }
 
 int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, void* stream)
@@ -901,8 +944,14 @@ int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, void* stream)
     if (nd <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
     dim3 ag((unsigned)((nd + 255) / 256)), ab(256);
-    if (a.stream_st) launch_aux_nt<true>(a, maxpairs, ag, ab, s);
-    else launch_aux_nt<false>(a, maxpairs, ag, ab, s);
+    const bool dft = (a.mode & (CCPR_MODE_DFT_T | CCPR_MODE_DFT_P)) != 0;
+    if (a.stream_st) {
+        if (dft) launch_aux_nt<true, true>(a, maxpairs, ag, ab, s);
+        else launch_aux_nt<true, false>(a, maxpairs, ag, ab, s);
+    } else {
+        if (dft) launch_aux_nt<false, true>(a, maxpairs, ag, ab, s);
+        else launch_aux_nt<false, false>(a, maxpairs, ag, ab, s);
+    }
     return (int)hipGetLastError();
 }
 
@@ -965,6 +1014,15 @@ int ccpr_launch_extract(float* d, const float* src, int comp, int nx, int ny, in
     const long long n = (long long)nx * ny * nz;
     hipLaunchKernelGGL(extract_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, d, src, comp,
                        nx, ny, nz, nxp, nyp, f);
+    return (int)hipGetLastError();
+}
+
+int ccpr_launch_dft_grad(double* grad, const float* acc, long long nd, double i00, double i01, double i11,
+                         double wc, double ws, void* stream)
+{
+    if (nd <= 0) return 0;
+    hipLaunchKernelGGL(dft_grad_kernel, dim3(grid_for(nd)), dim3(256), 0, (hipStream_t)stream, grad, acc, nd,
+                       i00, i01, i11, wc, ws);
     return (int)hipGetLastError();
 }
 

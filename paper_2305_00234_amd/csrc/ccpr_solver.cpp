@@ -87,6 +87,7 @@ struct ccpr_solver {
     int obj_kind = 1, glo[3]{}, gdim[3]{}, gncell = 0, nb = 0, ne = -1;
     double omega = 0;
     int ckpt_every = 0;
+    bool grad_dft = false;      // DFT-mode gradient estimator (CCPR_GRAD_DFT)
     // workspace
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
@@ -185,6 +186,18 @@ long long tf_count(const ccpr_solver* s)
     return 2 * (Lt + 1) * Lp + 2 * (Lt + 1) * Ld + 2 * (Lt + 1) * Lp + 2 * (Ld + 1) * Lp;
 }
 
+// DFT-mode fit window: the adjoint fields m in [M-L+1, M] with L the whole
+// periods of 2 pi/(omega dt) steps that fit in half the run, rounded to whole
+// steps (half the run when that is less than a period; 2 <= L <= M).
+int dft_window(int M, double omega, double dt)
+{
+    const double per = 2.0 * 3.14159265358979323846 / (omega * dt);
+    const int q = (int)std::floor(0.5 * M / per);
+    int L = q >= 1 ? (int)std::lround(q * per) : M / 2;
+    L = std::max(L, std::min(M, 2));
+    return std::min(L, M);
+}
+
 // Workspace layout for a solve of M steps (M = 0: stepping only).
 Layout make_layout(const ccpr_solver* s, int M, int K_req)
 {
@@ -238,10 +251,12 @@ Layout make_layout(const ccpr_solver* s, int M, int K_req)
     if (M > 0) {
         L.src_adj = take((size_t)M * std::max(s->gncell, 1) * 3 * 4);
         L.gap = take((size_t)(M + 1) * std::max(s->gncell, 1) * 3 * 4);
-        int K = K_req > 0 ? std::min(K_req, M) : M;
+        // DFT mode: one segment, no history; the T region holds the running
+        // transforms [12][nd] instead
+        int K = s->grad_dft ? M : K_req > 0 ? std::min(K_req, M) : M;
         L.K = K;
         L.S = (M + K - 1) / K;
-        L.T = take((size_t)K * 3 * nd * 4);
+        L.T = take(s->grad_dft ? 12 * nd * 4 : (size_t)K * 3 * nd * 4);
         L.ckpt_bytes = (6 * nc + 2 * (size_t)std::max(s->npairs_total, 1) * nd + 2 * psi) * 4 + 8 * 3 * 8;
         L.ckpt = take((size_t)(L.S - 1) * align256(L.ckpt_bytes));
     }
@@ -724,6 +739,8 @@ StepArgs hot_args(ccpr_solver* s, int st)
     A.S = (float)s->g.courant;
     A.psi_in = par;
     A.tslot = -1;
+    A.mode = 0;
+    A.phc = A.phs = 0.f;
     A.cold = wsp<StepCold>(s, L.cold[st]);
     A.zr = wsp<int2>(s, L.zr);
     A.tiles = wsp<int2>(s, L.tiles);
@@ -801,9 +818,62 @@ ccpr_status forward_step(ccpr_solver* s, int n, int tslot, bool gap)
 {
     StepArgs A = hot_args(s, 0);
     A.n = n;
-    A.tslot = tslot;
-    A.mode = (tslot >= 0 ? CCPR_MODE_RECORD : 0) | (gap && s->has_obj ? CCPR_MODE_GAP : 0);
+    A.mode = gap && s->has_obj ? CCPR_MODE_GAP : 0;
+    if (s->grad_dft) {
+        // DFT mode: T_hat += T^{n+1/2} exp(-j omega dt n) instead of the history
+        const double ph = s->omega * s->dt * n;
+        A.mode |= CCPR_MODE_DFT_T;
+        A.phc = (float)std::cos(ph);
+        A.phs = (float)std::sin(ph);
+    } else {
+        A.tslot = tslot;
+        if (tslot >= 0) A.mode |= CCPR_MODE_RECORD;
+    }
     return launch_step(s, A, 0);
+}
+
+// Adjoint step p = M-1-n (it pairs with forward step n of the segment that
+// starts at n0): time-exact correlation with history slot n-n0, or, in DFT
+// mode, the projection of the new adjoint field Et^{p+1} when it lies in the
+// fit window.
+ccpr_status adjoint_step(ccpr_solver* s, int n, int n0)
+{
+    StepArgs A = hot_args(s, 1);
+    const int p = s->M - 1 - n;
+    A.n = p;
+    if (s->grad_dft) {
+        const int m = p + 1;
+        if (m >= s->M - dft_window(s->M, s->omega, s->dt) + 1) {
+            const double ph = s->omega * s->dt * m;
+            A.mode = CCPR_MODE_DFT_P;
+            A.phc = (float)std::cos(ph);
+            A.phs = (float)std::sin(ph);
+        }
+    } else {
+        A.tslot = n - n0;
+        A.mode = CCPR_MODE_CORREL;
+    }
+    return launch_step(s, A, 1);
+}
+
+// DFT mode, after the adjoint run: the window's least-squares normal matrix
+// (host FP64) and the per-voxel gradient into the accumulator.
+ccpr_status dft_finish(ccpr_solver* s)
+{
+    const int M = s->M, Lw = dft_window(M, s->omega, s->dt);
+    const double th = s->omega * s->dt;
+    double scc = 0, sss = 0, scs = 0;
+    for (int m = M - Lw + 1; m <= M; ++m) {
+        const double c = std::cos(th * m), sn = std::sin(th * m);
+        scc += c * c;
+        sss += sn * sn;
+        scs += c * sn;
+    }
+    const double det = scc * sss - scs * scs;
+    if (!(det > 0)) return fail(s, CCPR_EINVAL, "DFT-mode fit window is degenerate (omega dt a multiple of pi?)");
+    HIPCHK(ccpr_launch_dft_grad(wsp<double>(s, s->lay.gradacc), wsp<float>(s, s->lay.T), s->nd, sss / det,
+                                -scs / det, scc / det, std::cos(th * M), std::sin(th * M), s->stream));
+    return CCPR_OK;
 }
 
 // add the recorded grid-kernel event triples to the statistics (the stream is
@@ -857,6 +927,8 @@ ccpr_status check_ready(ccpr_solver* s, bool need_obj)
     if (s->src_kind == 0) return fail(s, CCPR_ESTATE, "no source set");
     if (need_obj && !s->has_obj) return fail(s, CCPR_ESTATE, "no objective set");
     if (need_obj && !s->has_design) return fail(s, CCPR_ESTATE, "no design set");
+    if (need_obj && s->grad_dft && (s->obj_kind != CCPR_OBJ_DFT_E2 || !(s->omega > 0)))
+        return fail(s, CCPR_EINVAL, "the DFT gradient mode needs the DFT objective (omega > 0)");
     return CCPR_OK;
 }
 
@@ -1148,6 +1220,15 @@ ccpr_status ccpr_set_checkpointing(ccpr_solver* s, int every)
     return CCPR_OK;
 }
 
+ccpr_status ccpr_set_gradient_mode(ccpr_solver* s, int mode)
+{
+    if (!s) return CCPR_EINVAL;
+    if (mode != CCPR_GRAD_TIME_EXACT && mode != CCPR_GRAD_DFT) return fail(s, CCPR_EINVAL, "unknown gradient mode");
+    s->grad_dft = mode == CCPR_GRAD_DFT;
+    s->have_forward = s->have_adjoint = false;
+    return CCPR_OK;
+}
+
 ccpr_status ccpr_workspace_size(const ccpr_solver* s, int nsteps, uint64_t* bytes)
 {
     if (!s || !bytes || nsteps < 0) return CCPR_EINVAL;
@@ -1257,6 +1338,7 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
     st = upload_cold(s, 0);
     if (st) return st;
     HIPCHK(ccpr_launch_fill(wsp<float>(s, L.gap), (long long)s->gncell * 3, 0.f, s->stream));
+    if (s->grad_dft) HIPCHK(ccpr_launch_fill(wsp<float>(s, L.T), 12 * std::max(s->nd, 1LL), 0.f, s->stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s->timing) {
         HIPCHK(hipEventCreate(&e0));
@@ -1315,6 +1397,7 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
     st = upload_cold(s, 1);
     if (st) return st;
     HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), ndm, 0.0, s->stream));
+    if (s->grad_dft) HIPCHK(ccpr_launch_fill(wsp<float>(s, L.T) + 6 * ndm, 6 * ndm, 0.f, s->stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms_total = 0;
     s->timed_loop = s->timing;
@@ -1336,12 +1419,7 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
             HIPCHK(hipEventRecord(e0, s->stream));
         }
         for (int n = n1 - 1; n >= n0; --n) {
-            const int p = M - 1 - n;  // adjoint step p pairs with forward step n
-            StepArgs A = hot_args(s, 1);
-            A.n = p;
-            A.tslot = n - n0;
-            A.mode = CCPR_MODE_CORREL;
-            st = launch_step(s, A, 1);
+            st = adjoint_step(s, n, n0);
             if (st) return st;
         }
         if (s->timing) {
@@ -1360,6 +1438,10 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
     if (s->timing) {
         s->stat_ms += ms_total;
         s->stat_launches += M;
+    }
+    if (s->grad_dft) {
+        st = dft_finish(s);
+        if (st) return st;
     }
     s->current_state = 1;
     s->have_adjoint = true;
@@ -1462,6 +1544,8 @@ ccpr_status ccpr_pipe_begin(ccpr_solver* s, int nsteps)
     st = upload_cold(s, 1);
     if (st) return st;
     HIPCHK(ccpr_launch_fill(wsp<float>(s, s->lay.gap), (long long)s->gncell * 3, 0.f, s->stream));
+    if (s->grad_dft)
+        HIPCHK(ccpr_launch_fill(wsp<float>(s, s->lay.T), 12 * std::max(s->nd, 1LL), 0.f, s->stream));
     s->have_forward = s->have_adjoint = false;
     s->pipe_phase = 0;
     s->pipe_n = 0;
@@ -1496,6 +1580,10 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
             st = zero_state(s, 1);
             if (st) return st;
             HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), std::max(s->nd, 1LL), 0.0, s->stream));
+            if (s->grad_dft) {
+                const long long ndm = std::max(s->nd, 1LL);
+                HIPCHK(ccpr_launch_fill(wsp<float>(s, L.T) + 6 * ndm, 6 * ndm, 0.f, s->stream));
+            }
             s->pipe_phase = 2;
             s->pipe_seg = S - 1;
             s->pipe_sub = 1;  // the last segment's history is already written
@@ -1518,15 +1606,15 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
                 }
             } else {  // adjoint step p pairs with forward step n
                 const int n = n1 - 1 - s->pipe_k;
-                StepArgs A = hot_args(s, 1);
-                A.n = M - 1 - n;
-                A.tslot = n - n0;
-                A.mode = CCPR_MODE_CORREL;
-                st = launch_step(s, A, 1);
+                st = adjoint_step(s, n, n0);
                 if (st) return st;
                 ++done;
                 if (n == n0) {
                     if (--s->pipe_seg < 0) {
+                        if (s->grad_dft) {
+                            st = dft_finish(s);
+                            if (st) return st;
+                        }
                         s->pipe_phase = 3;
                         s->step_count = M;
                         s->current_state = 1;

@@ -148,6 +148,7 @@ class Workload:
     omega: float = 0.0
     window: Tuple[int, int] = (0, -1)        # time objective [n_begin, n_end); -1 = M+1
     checkpoint_every: int = 0                # 0 = let the library choose
+    gradient: str = "time"                   # "time" (exact) | "dft" (single-frequency estimator)
     pml_m: float = 3.0
     pml_kappa_max: float = 1.0
     pml_alpha_max: float = 0.05

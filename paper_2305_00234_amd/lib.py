@@ -27,7 +27,7 @@ EX, EY, EZ, HX, HY, HZ = range(6)
 EXPORTS = [
     "ccpr_create", "ccpr_destroy", "ccpr_last_error", "ccpr_set_material", "ccpr_set_design",
     "ccpr_set_source_dipole", "ccpr_set_source_planewave", "ccpr_set_objective",
-    "ccpr_set_checkpointing", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
+    "ccpr_set_checkpointing", "ccpr_set_gradient_mode", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
     "ccpr_adjoint", "ccpr_gradient", "ccpr_reset", "ccpr_step", "ccpr_get_field",
     "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_grid_timing", "ccpr_get_info",
     "ccpr_set_tile_planes", "ccpr_set_tile_rows",
@@ -35,6 +35,7 @@ EXPORTS = [
     "ccpr_engine_result", "ccpr_engine_release", "ccpr_engine_last_error", "ccpr_engine_destroy",
 ]
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+GRAD_TIME_EXACT, GRAD_DFT = 0, 1
 
 
 class CcprGrid(C.Structure):
@@ -78,6 +79,7 @@ def load():
         "ccpr_set_source_planewave": (_i, [_p, _i, _i, _i, _ip, _ip, _dp, _i]),
         "ccpr_set_objective": (_i, [_p, _i, _ip, _ip, _d, _i, _i]),
         "ccpr_set_checkpointing": (_i, [_p, _i]),
+        "ccpr_set_gradient_mode": (_i, [_p, _i]),
         "ccpr_workspace_size": (_i, [_p, _i, C.POINTER(C.c_uint64)]),
         "ccpr_bind_workspace": (_i, [_p, _p, C.c_uint64, _p]),
         "ccpr_forward": (_i, [_p, _i, _dp]),
@@ -198,6 +200,12 @@ class Solver:
 
     def set_checkpointing(self, every):
         self._chk(self._lib.ccpr_set_checkpointing(self._h, every), "ccpr_set_checkpointing")
+
+    def set_gradient_mode(self, mode):
+        """"time" (exact discrete gradient, default) or "dft" (single-frequency
+        estimator for the DFT objective)."""
+        code = {"time": GRAD_TIME_EXACT, "dft": GRAD_DFT}[mode]
+        self._chk(self._lib.ccpr_set_gradient_mode(self._h, code), "ccpr_set_gradient_mode")
 
     def workspace_size(self, nsteps):
         b = C.c_uint64(0)

@@ -26,6 +26,7 @@ def configure(w: Workload, s: Solver | None = None) -> Solver:
                     -1 if w.window[1] < 0 else w.window[1])
     if w.checkpoint_every:
         s.set_checkpointing(w.checkpoint_every)
+    s.set_gradient_mode(w.gradient)
     return s
 
 

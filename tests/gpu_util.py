@@ -93,6 +93,9 @@ def oracle_gradient(w: Workload):
     o.reset()
     o.run(w.steps)
     fwd = o.fields()
-    F, g = o.gradient(w.steps, kind, w.gap_lo, w.gap_dims, w.omega, w.window[0], w.window_end)
+    if w.gradient == "dft":
+        F, g = o.gradient_dft(w.steps, w.gap_lo, w.gap_dims, w.omega)
+    else:
+        F, g = o.gradient(w.steps, kind, w.gap_lo, w.gap_dims, w.omega, w.window[0], w.window_end)
     adj = o.fields()
     return F, g, fwd, adj

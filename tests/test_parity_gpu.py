@@ -191,7 +191,7 @@ def test_aniso_two_material_fields_objective_gradient():
 
 def test_full_size_320_fields_vs_oracle():
     """The 320^3 gold gap grid in the launch configuration of the benchmark
-    (2 rows per thread, nominal 8-plane z-chunks balanced over the XCDs,
+    (2 rows per thread, default 5-plane nominal z-chunks balanced over the XCDs,
     12-cell CPML, TF/SF box): all six field components after 60 steps of an
     early-starting pulse against the oracle on the full grid."""
     w = I.gold_gap_320(steps=60)

@@ -16,7 +16,9 @@ SPECS = [(40, 1, 300), (56, 3, 260), (48, 2, 340), (64, 3, 240), (44, 1, 280), (
 
 
 def _requests():
-    return [I.serving_workload(side, p, steps, seed=500 + k) for k, (side, p, steps) in enumerate(SPECS)]
+    ws = [I.serving_workload(side, p, steps, seed=500 + k) for k, (side, p, steps) in enumerate(SPECS)]
+    ws[2].gradient = "dft"  # one request with the DFT-mode gradient in the mix
+    return ws
 
 
 def _alone(w):
