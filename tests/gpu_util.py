@@ -44,12 +44,14 @@ def field_errors(gpu_fields, or_fields):
     return state, rel_l2(g[:3], o[:3]), rel_l2(g[3:], o[3:])
 
 
-def gpu_fields_after_steps(w: Workload, steps: int, tile_planes=None):
+def gpu_fields_after_steps(w: Workload, steps: int, tile_planes=None, tile_rows=None):
     from paper_2305_00234_amd.solver import configure
     torch = require_gpu()
     s = configure(w)
     if tile_planes:
         s.set_tile_planes(tile_planes)
+    if tile_rows:
+        s.set_tile_rows(tile_rows)
     s.bind_torch(0)
     s.reset()
     s.step(steps)

@@ -173,6 +173,58 @@ def test_tile_shape_invariance_bitwise():
         assert np.array_equal(x, y)
 
 
+def test_widest_workgroup_fields():
+    """nx = 1000: a 1024-lane workgroup (16 waves, the last one ragged) per
+    y-strip, the widest x extent one workgroup row takes; dispersive design,
+    CPML."""
+    w = _dipole_box(n=(1000, 20, 22), npml=4, steps=90,
+                    mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
+    w.design_lo = (480, 5, 6)
+    w.dipole_cell = (470, 8, 8)
+    w.gap_lo = (483, 8, 8)
+    say("widest workgroup", w.shape)
+    g = gpu_fields_after_steps(w, 90)
+    o = oracle_fields_after_steps(w, 90)
+    st, eE, eH = field_errors(g, o)
+    say("rel L2 state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+
+
+def test_four_rows_per_thread_variant():
+    """Four y rows per thread (register blocking limited to nx <= 512): the
+    same fields as two rows per thread, bit for bit, and the oracle's."""
+    w = _dipole_box(n=(70, 38, 33), npml=6, steps=120,
+                    mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
+    a = gpu_fields_after_steps(w, 120, tile_rows=4)
+    b = gpu_fields_after_steps(w, 120, tile_rows=2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    o = oracle_fields_after_steps(w, 120)
+    st, eE, eH = field_errors(a, o)
+    say("rows=4 rel L2 state", st)
+    assert st <= FIELD_TOL
+
+
+@pytest.mark.parametrize("kind", ["binary", "single_voxel"])
+def test_degenerate_designs_gradient(kind):
+    """Degenerate designs: densities exactly 0 or 1 (the end points of the
+    interpolation, where the conductivity damping term vanishes), and a
+    design box of one voxel."""
+    w = _dipole_box(n=(40, 30, 36), npml=5, steps=240,
+                    mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
+    if kind == "binary":
+        w.rho = (np.random.default_rng(21).random(w.rho.shape) > 0.5).astype(np.float32)
+    else:
+        w.rho = np.array([[[0.4]]], dtype=np.float32)
+        w.gap_lo = (w.design_lo[0] + 1, w.design_lo[1], w.design_lo[2])
+    say("degenerate design", kind, w.rho.shape)
+    Fg, gg, _, _, _ = gpu_gradient(w)
+    Fo, go, _, _ = oracle_gradient(w)
+    say("F", Fg, Fo, "grad rel L2", rel_l2(gg, go), "grad", gg.ravel()[:3], go.ravel()[:3])
+    assert abs(Fg - Fo) <= FIELD_TOL * abs(Fo)
+    assert rel_l2(gg, go) <= GRAD_TOL
+
+
 def test_aniso_two_material_fields_objective_gradient():
     """Diagonal anisotropy with two dispersive materials: rho=0 a Lorentz
     dielectric, rho=1 a metal whose pole set differs per axis (4 pairs per
