@@ -180,6 +180,10 @@ int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* strea
 // after the aux kernel: x-CPML of E^{n+1} (nxs x-layer cells) and the
 // nmisc = nextra + tf_nE source / gap cells and TF/SF E words
 int ccpr_launch_post(const StepArgs& a, long long nxs, long long nmisc, void* stream);
+// after the aux kernel when the next step follows at once: the post work of
+// step n and the pre work of step n+1 (ntfh TF/SF H words) in one launch
+// (2 npml <= 256)
+int ccpr_launch_post_fused(const StepArgs& a, long long nmisc, long long ntfh, void* stream);
 int ccpr_launch_fill(float* p, long long n, float v, void* stream);
 int ccpr_launch_fill_d(double* p, long long n, double v, void* stream);
 int ccpr_launch_copy(float* dst, const float* src, long long n, void* stream);

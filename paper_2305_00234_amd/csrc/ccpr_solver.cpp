@@ -96,6 +96,11 @@ struct ccpr_solver {
     int tz = 5;                 // nominal planes per z-chunk of the step kernel
     // run state
     int parity[2] = {0, 0};
+    // pre_done[st]: the last step's post launch also applied the next step's
+    // pre-corrections (H^{n+1/2} is no longer the plain state until that step
+    // runs); fuse_ok[st]: that fusion is safe for this configuration
+    bool pre_done[2] = {false, false};
+    bool fuse_ok[2] = {false, false};
     int step_count = 0;
     int src_table_steps = -1;   // steps covered by the uploaded forward source table
     Layout lay{};
@@ -376,6 +381,7 @@ ccpr_status zero_state(ccpr_solver* s, int st)
     HIPCHK(ccpr_launch_fill(wsp<float>(s, L.psiH[st][1]), psi, 0.f, s->stream));
     HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.ssh[st]), (long long)std::max(s->gncell, 1) * 3, 0.0, s->stream));
     s->parity[st] = 0;
+    s->pre_done[st] = false;
     return CCPR_OK;
 }
 
@@ -702,6 +708,12 @@ ccpr_status upload_cold(ccpr_solver* s, int st)
     fill_cold(s, st, s->cold_host[st]);
     fill_classes(s, s->cold_host[st], s->rowf_host[st], s->lanef_host[st]);
     fill_extra(s->cold_host[st], s->extra_host[st]);
+    // the fused post launch reads E^{n+1} of the first cell past the low x
+    // layer while its other blocks finish the source cells: no source cell
+    // may sit there
+    s->fuse_ok[st] = 2 * s->g.npml <= 256;
+    for (const int4& e : s->extra_host[st])
+        if (e.w == CCPR_EXTRA_SOURCE && s->g.npml > 0 && e.x == s->g.npml) s->fuse_ok[st] = false;
     if (!s->extra_host[st].empty())
         HIPCHK(hipMemcpyAsync(s->ws + s->lay.extra[st], s->extra_host[st].data(),
                               s->extra_host[st].size() * sizeof(int4), hipMemcpyHostToDevice, s->stream));
@@ -749,13 +761,17 @@ StepArgs hot_args(ccpr_solver* s, int st)
     return A;
 }
 
-ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st)
+// One leapfrog step of state st.  fuse: the next step of this state follows
+// at once (no checkpoint or field read in between), so the post launch also
+// applies its pre-corrections.
+ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
 {
     const StepCold& C = s->cold_host[st];
     const long long nxs = s->g.npml > 0 ? 2LL * s->g.npml * s->g.ny * s->g.nz : 0;
     const long long ndes = s->has_design ? s->nd : 0;
     const long long nmisc = A.nextra + (C.pw_on ? C.tf_nE : 0);
-    int e = ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, s->stream);
+    int e = s->pre_done[st] ? 0 : ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, s->stream);
+    s->pre_done[st] = false;
     const bool tm = s->timing && s->timed_loop;
     if (tm) {
         while (s->tev.size() < s->tev_used + 3) {
@@ -806,15 +822,29 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st)
     // aux and post touch disjoint cells but share the device better in
     // sequence than side by side (measured)
     if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, ndes, s->stream);
-    if (e == 0) e = ccpr_launch_post(A, nxs, nmisc, s->stream);
+    fuse = fuse && s->fuse_ok[st];
+    if (e == 0)
+        e = fuse ? ccpr_launch_post_fused(A, nmisc, C.pw_on ? C.tf_nH : 0, s->stream)
+                 : ccpr_launch_post(A, nxs, nmisc, s->stream);
     if (e != 0) return fail(s, CCPR_EDEVICE, "step kernel launch: %s", hipGetErrorString((hipError_t)e));
+    s->pre_done[st] = fuse;
     s->parity[st] ^= 1;
     return CCPR_OK;
 }
 
+// Whether forward step m of a full run follows its predecessor at once: not
+// past the end and not after a checkpoint save (which must see the plain state).
+bool fuse_forward(const ccpr_solver* s, int m)
+{
+    const int K = s->lay.K, S = s->lay.S;
+    if (m >= s->M) return false;
+    const int seg = K > 0 ? m / K : 0;
+    return !(K > 0 && m % K == 0 && seg >= 1 && seg < S);
+}
+
 // One forward step n of the forward state; tslot >= 0 records the gradient
 // factor of this step into that history slot.
-ccpr_status forward_step(ccpr_solver* s, int n, int tslot, bool gap)
+ccpr_status forward_step(ccpr_solver* s, int n, int tslot, bool gap, bool fuse)
 {
     StepArgs A = hot_args(s, 0);
     A.n = n;
@@ -829,14 +859,14 @@ ccpr_status forward_step(ccpr_solver* s, int n, int tslot, bool gap)
         A.tslot = tslot;
         if (tslot >= 0) A.mode |= CCPR_MODE_RECORD;
     }
-    return launch_step(s, A, 0);
+    return launch_step(s, A, 0, fuse);
 }
 
 // Adjoint step p = M-1-n (it pairs with forward step n of the segment that
 // starts at n0): time-exact correlation with history slot n-n0, or, in DFT
 // mode, the projection of the new adjoint field Et^{p+1} when it lies in the
 // fit window.
-ccpr_status adjoint_step(ccpr_solver* s, int n, int n0)
+ccpr_status adjoint_step(ccpr_solver* s, int n, int n0, bool fuse)
 {
     StepArgs A = hot_args(s, 1);
     const int p = s->M - 1 - n;
@@ -853,7 +883,7 @@ ccpr_status adjoint_step(ccpr_solver* s, int n, int n0)
         A.tslot = n - n0;
         A.mode = CCPR_MODE_CORREL;
     }
-    return launch_step(s, A, 1);
+    return launch_step(s, A, 1, fuse);
 }
 
 // DFT mode, after the adjoint run: the window's least-squares normal matrix
@@ -894,6 +924,9 @@ ccpr_status harvest_grid_events(ccpr_solver* s)
 // copy the forward state (current parity) to / from checkpoint slot c
 ccpr_status checkpoint(ccpr_solver* s, int slot, bool save)
 {
+    // a checkpoint holds the plain state between two steps
+    if (save && s->pre_done[0]) return fail(s, CCPR_EDEVICE, "internal: checkpoint of a pre-corrected state");
+    if (!save) s->pre_done[0] = false;
     const Layout& L = s->lay;
     float* ck = wsp<float>(s, L.ckpt + (size_t)slot * align256(L.ckpt_bytes));
     const int par = save ? s->parity[0] : 0;
@@ -1284,7 +1317,7 @@ ccpr_status ccpr_step(ccpr_solver* s, int n)
     if (st) return st;
     s->current_state = 0;
     for (int q = 0; q < n; ++q) {
-        st = forward_step(s, s->step_count, -1, false);
+        st = forward_step(s, s->step_count, -1, false, q + 1 < n);
         if (st) return st;
         s->step_count++;
     }
@@ -1352,7 +1385,7 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
             st = checkpoint(s, seg - 1, true);
             if (st) return st;
         }
-        st = forward_step(s, n, seg == S - 1 ? n - seg * K : -1, true);
+        st = forward_step(s, n, seg == S - 1 ? n - seg * K : -1, true, fuse_forward(s, n + 1));
         if (st) return st;
     }
     if (s->timing) {
@@ -1409,7 +1442,7 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
             else st = checkpoint(s, seg - 1, false);
             if (st) return st;
             for (int n = n0; n < n1; ++n) {
-                st = forward_step(s, n, n - n0, false);
+                st = forward_step(s, n, n - n0, false, n + 1 < n1);
                 if (st) return st;
             }
         }
@@ -1419,7 +1452,7 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
             HIPCHK(hipEventRecord(e0, s->stream));
         }
         for (int n = n1 - 1; n >= n0; --n) {
-            st = adjoint_step(s, n, n0);
+            st = adjoint_step(s, n, n0, n > 0);
             if (st) return st;
         }
         if (s->timing) {
@@ -1570,7 +1603,7 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
                 st = checkpoint(s, seg - 1, true);
                 if (st) return st;
             }
-            st = forward_step(s, n, seg == S - 1 ? n - seg * K : -1, true);
+            st = forward_step(s, n, seg == S - 1 ? n - seg * K : -1, true, fuse_forward(s, n + 1));
             if (st) return st;
             ++s->pipe_n;
             ++done;
@@ -1597,7 +1630,7 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
                     if (st) return st;
                 }
                 const int n = n0 + s->pipe_k;
-                st = forward_step(s, n, n - n0, false);
+                st = forward_step(s, n, n - n0, false, n + 1 < n1);
                 if (st) return st;
                 ++done;
                 if (++s->pipe_k == n1 - n0) {
@@ -1606,7 +1639,7 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
                 }
             } else {  // adjoint step p pairs with forward step n
                 const int n = n1 - 1 - s->pipe_k;
-                st = adjoint_step(s, n, n0);
+                st = adjoint_step(s, n, n0, n > 0);
                 if (st) return st;
                 ++done;
                 if (n == n0) {
