@@ -118,7 +118,10 @@ struct ccpr_solver {
     int ntiles_int = 0, ntiles_pml = 0;
     hipStream_t stream2 = nullptr;  // second stream: CPML tiles run beside the interior ones
     bool own_stream2 = false;
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr, pdone_ev = nullptr;
+    // split passes alternate the two streams' roles: lead2 = the step sequence
+    // currently continues on stream2 (join_lead() returns it to 'stream')
+    bool lead2 = false;
     int tf_nE = 0, tf_nH = 0;
     long long fixed_key[4] = {-1, -1, -1, -1};
     // diagnostics
@@ -366,8 +369,23 @@ ccpr_status upload_rho(ccpr_solver* s)
     return CCPR_OK;
 }
 
+// Make the solver's stream wait for a step sequence that ended on stream2
+// (every launch outside the step loop goes to the solver's stream).
+ccpr_status join_lead(ccpr_solver* s)
+{
+    if (!s->lead2) return CCPR_OK;
+    HIPCHK(hipEventRecord(s->join_ev, s->stream2));
+    HIPCHK(hipStreamWaitEvent(s->stream, s->join_ev, 0));
+    s->lead2 = false;
+    return CCPR_OK;
+}
+
 ccpr_status zero_state(ccpr_solver* s, int st)
 {
+    {
+        ccpr_status j = join_lead(s);
+        if (j) return j;
+    }
     const Layout& L = s->lay;
     const long long psi = psi_total(s);
     HIPCHK(ccpr_launch_fill(wsp<float>(s, L.Eb[st][0]), 3 * s->npad, 0.f, s->stream));
@@ -685,6 +703,7 @@ ccpr_status upload_cold(ccpr_solver* s, int st)
     if (s->stream2 && !s->fork_ev) {
         HIPCHK(hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&s->pdone_ev, hipEventDisableTiming));
     }
     // source and gap cells are finished by the aux kernel before the x-CPML
     // pass of E: they must lie outside the x layers
@@ -770,7 +789,13 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
     const long long nxs = s->g.npml > 0 ? 2LL * s->g.npml * s->g.ny * s->g.nz : 0;
     const long long ndes = s->has_design ? s->nd : 0;
     const long long nmisc = A.nextra + (C.pw_on ? C.tf_nE : 0);
-    int e = s->pre_done[st] ? 0 : ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, s->stream);
+    // Ls leads this step (its previous work is the last step's post); with a
+    // split pass the other stream Fs runs the interior tiles, aux and post
+    // and leads the next step, so the only wait that is not already
+    // satisfied (Fs on the fork event) overlaps the CPML-tile launch.
+    hipStream_t Ls = s->lead2 ? s->stream2 : s->stream;
+    hipStream_t Fs = s->lead2 ? s->stream : s->stream2;
+    int e = s->pre_done[st] ? 0 : ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, Ls);
     s->pre_done[st] = false;
     const bool tm = s->timing && s->timed_loop;
     if (tm) {
@@ -779,53 +804,57 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
             HIPCHK(hipEventCreate(&ev));
             s->tev.push_back(ev);
         }
-        HIPCHK(hipEventRecord(s->tev[s->tev_used], s->stream));
+        HIPCHK(hipEventRecord(s->tev[s->tev_used], Ls));
     }
     // grid kernel: CPML tiles and interior tiles as two concurrent launches
     // (both read step-n state only and write disjoint cells)
     StepArgs Ap = A;
     Ap.tiles = A.tiles + s->ntiles_int;
     Ap.nblk = s->ntiles_pml;
-    // the split pays for its fork/join only with enough tiles on both sides
+    // the split pays for its fork only with enough tiles on both sides
     const bool split = s->stream2 && s->ntiles_int >= 1024 && s->ntiles_pml >= 128;
     bool two = false;
+    hipStream_t As = Ls;  // stream of aux and post
     if (e == 0) {
         if (s->ntiles_int == 0 || (!split && s->ntiles_pml > 0)) {
             Ap.tiles = A.tiles;  // one launch over all tiles
             Ap.nblk = s->ntiles_int + s->ntiles_pml;
-            e = ccpr_launch_grid(Ap, true, s->stream);
+            e = ccpr_launch_grid(Ap, true, Ls);
         } else if (s->ntiles_pml == 0) {
-            e = ccpr_launch_grid(A, false, s->stream);
+            e = ccpr_launch_grid(A, false, Ls);
         } else {
-            // the slower CPML tiles go first, on the solver's stream; the
-            // interior tiles fill the device around them
-            HIPCHK(hipEventRecord(s->fork_ev, s->stream));
-            e = ccpr_launch_grid(Ap, true, s->stream);
-            if (tm) HIPCHK(hipEventRecord(s->tev[s->tev_used + 1], s->stream));
-            HIPCHK(hipStreamWaitEvent(s->stream2, s->fork_ev, 0));
-            if (e == 0) e = ccpr_launch_grid(A, false, s->stream2);
-            if (tm) HIPCHK(hipEventRecord(s->tev[s->tev_used + 2], s->stream2));
-            HIPCHK(hipEventRecord(s->join_ev, s->stream2));
-            HIPCHK(hipStreamWaitEvent(s->stream, s->join_ev, 0));
+            // the slower CPML tiles go first; the interior tiles fill the
+            // device around them; aux waits for the CPML launch too (normally
+            // long finished by then)
+            HIPCHK(hipEventRecord(s->fork_ev, Ls));
+            e = ccpr_launch_grid(Ap, true, Ls);
+            if (tm) HIPCHK(hipEventRecord(s->tev[s->tev_used + 1], Ls));
+            HIPCHK(hipEventRecord(s->pdone_ev, Ls));
+            HIPCHK(hipStreamWaitEvent(Fs, s->fork_ev, 0));
+            if (e == 0) e = ccpr_launch_grid(A, false, Fs);
+            if (tm) HIPCHK(hipEventRecord(s->tev[s->tev_used + 2], Fs));
+            HIPCHK(hipStreamWaitEvent(Fs, s->pdone_ev, 0));
+            As = Fs;
+            s->lead2 = !s->lead2;
             two = true;
         }
     }
-    // timed pass: start on the solver's stream, end with the later of the two
-    // launches (the solver stream's wait on the second stream is not part of it)
+    // timed pass: start before the first launch, end with the later of the
+    // two launches
     if (tm) {
         if (!two) {
-            HIPCHK(hipEventRecord(s->tev[s->tev_used + 1], s->stream));
-            HIPCHK(hipEventRecord(s->tev[s->tev_used + 2], s->stream));
+            HIPCHK(hipEventRecord(s->tev[s->tev_used + 1], Ls));
+            HIPCHK(hipEventRecord(s->tev[s->tev_used + 2], Ls));
         }
         s->tev_used += 3;
     }
     // aux and post touch disjoint cells but share the device better in
     // sequence than side by side (measured)
-    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, ndes, s->stream);
+    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, ndes, As);
     fuse = fuse && s->fuse_ok[st];
     if (e == 0)
-        e = fuse ? ccpr_launch_post_fused(A, nmisc, C.pw_on ? C.tf_nH : 0, s->stream)
-                 : ccpr_launch_post(A, nxs, nmisc, s->stream);
+        e = fuse ? ccpr_launch_post_fused(A, nmisc, C.pw_on ? C.tf_nH : 0, As)
+                 : ccpr_launch_post(A, nxs, nmisc, As);
     if (e != 0) return fail(s, CCPR_EDEVICE, "step kernel launch: %s", hipGetErrorString((hipError_t)e));
     s->pre_done[st] = fuse;
     s->parity[st] ^= 1;
@@ -890,6 +919,10 @@ ccpr_status adjoint_step(ccpr_solver* s, int n, int n0, bool fuse)
 // (host FP64) and the per-voxel gradient into the accumulator.
 ccpr_status dft_finish(ccpr_solver* s)
 {
+    {
+        ccpr_status j = join_lead(s);
+        if (j) return j;
+    }
     const int M = s->M, Lw = dft_window(M, s->omega, s->dt);
     const double th = s->omega * s->dt;
     double scc = 0, sss = 0, scs = 0;
@@ -924,6 +957,10 @@ ccpr_status harvest_grid_events(ccpr_solver* s)
 // copy the forward state (current parity) to / from checkpoint slot c
 ccpr_status checkpoint(ccpr_solver* s, int slot, bool save)
 {
+    {
+        ccpr_status j = join_lead(s);
+        if (j) return j;
+    }
     // a checkpoint holds the plain state between two steps
     if (save && s->pre_done[0]) return fail(s, CCPR_EDEVICE, "internal: checkpoint of a pre-corrected state");
     if (!save) s->pre_done[0] = false;
@@ -1030,6 +1067,10 @@ ccpr_status adopt_layout(ccpr_solver* s, int M)
 // table) and its SI values on the device (scal[4..6]).
 ccpr_status launch_objective(ccpr_solver* s)
 {
+    {
+        ccpr_status j = join_lead(s);
+        if (j) return j;
+    }
     const Layout& L = s->lay;
     const int M = s->M;
     const int ne = s->gncell * 3;
@@ -1100,6 +1141,7 @@ void ccpr_destroy(ccpr_solver* s)
     if (s->stream2) (void)hipStreamSynchronize(s->stream2);
     if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
     if (s->join_ev) (void)hipEventDestroy(s->join_ev);
+    if (s->pdone_ev) (void)hipEventDestroy(s->pdone_ev);
     if (s->stream2 && s->own_stream2) (void)hipStreamDestroy(s->stream2);
     delete s;
 }
@@ -1321,7 +1363,7 @@ ccpr_status ccpr_step(ccpr_solver* s, int n)
         if (st) return st;
         s->step_count++;
     }
-    return CCPR_OK;
+    return join_lead(s);
 }
 
 int ccpr_step_count(const ccpr_solver* s) { return s ? s->step_count : -1; }
@@ -1388,6 +1430,8 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
         st = forward_step(s, n, seg == S - 1 ? n - seg * K : -1, true, fuse_forward(s, n + 1));
         if (st) return st;
     }
+    st = join_lead(s);
+    if (st) return st;
     if (s->timing) {
         HIPCHK(hipEventRecord(e1, s->stream));
         HIPCHK(hipEventSynchronize(e1));
@@ -1445,6 +1489,8 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
                 st = forward_step(s, n, n - n0, false, n + 1 < n1);
                 if (st) return st;
             }
+            st = join_lead(s);
+            if (st) return st;
         }
         if (s->timing) {
             HIPCHK(hipEventCreate(&e0));
@@ -1455,6 +1501,8 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
             st = adjoint_step(s, n, n0, n > 0);
             if (st) return st;
         }
+        st = join_lead(s);
+        if (st) return st;
         if (s->timing) {
             HIPCHK(hipEventRecord(e1, s->stream));
             HIPCHK(hipEventSynchronize(e1));
@@ -1661,6 +1709,8 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
             }
         }
     }
+    st = join_lead(s);
+    if (st) return st;
     return done;
 }
 
@@ -1688,6 +1738,10 @@ long long ccpr_pipe_design_voxels(const ccpr_solver* s) { return s->has_design ?
 
 ccpr_status ccpr_pipe_set_stream2(ccpr_solver* s, void* stream2)
 {
+    {
+        ccpr_status j = join_lead(s);
+        if (j) return j;
+    }
     if (s->stream2 && s->own_stream2) {
         HIPCHK(hipStreamSynchronize(s->stream2));
         HIPCHK(hipStreamDestroy(s->stream2));

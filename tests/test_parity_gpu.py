@@ -103,6 +103,38 @@ def test_tfsf_planewave_fields(prop, sign, pol):
     assert st <= FIELD_TOL
 
 
+def test_tfsf_planewave_pec_walls_fields():
+    """TF/SF plane wave with no CPML (PEC walls): the fused post/pre launch
+    then carries only the misc cells and the next step's TF/SF H words."""
+    w = I.gold_gap(n=(40, 34, 38), design=(12, 10, 8), gap=2, npml=0, steps=120, seed=8,
+                   name="tfsf_pec", tfsf_margin=3)
+    _short_pulse(w)
+    g = gpu_fields_after_steps(w, 120)
+    o = oracle_fields_after_steps(w, 120)
+    st, eE, eH = field_errors(g, o)
+    say("tfsf PEC rel L2 state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+
+
+def test_sources_next_to_the_low_x_layer_gradient():
+    """Dipole cell and gap box (the adjoint's source cells) on the first cell
+    past the low x CPML layer: the post and pre launches then stay separate
+    (the fused launch would read that E word while another block writes it);
+    fields, objective and gradient against the oracle."""
+    w = _dipole_box(n=(40, 30, 36), npml=6, steps=220,
+                    mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
+    w.dipole_cell = (6, 12, 14)
+    w.gap_lo = (6, 14, 15)
+    say("sources at x = npml", w.dipole_cell, w.gap_lo, w.design_lo)
+    Fg, gg, fg, _, _ = gpu_gradient(w)
+    Fo, go, fo, _ = oracle_gradient(w)
+    st, eE, eH = field_errors(fg, fo)
+    say("forward state", st, "F", Fg, Fo, "grad rel L2", rel_l2(gg, go))
+    assert st <= FIELD_TOL
+    assert abs(Fg - Fo) <= FIELD_TOL * abs(Fo)
+    assert rel_l2(gg, go) <= GRAD_TOL
+
+
 def test_drude_dipole_32_fields_400_steps():
     """The CPU-sized workload: 32^3, 8-cell CPML, Drude design, 400 steps."""
     w = I.drude_dipole_32()
