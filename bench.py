@@ -83,10 +83,10 @@ def step_bytes(w):
     return algorithmic_bytes(w) + design + xpml + record
 
 
-def traffic_from_profile(kernel_src_hash):
+def traffic_from_profile(kernel_src_hash, workload):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_hbm_traffic_gold_gap_320.json")
+    were taken on the current kernel source and this workload; else None."""
+    path = os.path.join(ROOT, "profiles", f"step_kernel_hbm_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -301,7 +301,7 @@ def main():
     alg = algorithmic_bytes(w)
     achieved = alg / avg_launch_s / 1e9
     sb = step_bytes(w)
-    traffic = traffic_from_profile(kernel_hash())
+    traffic = traffic_from_profile(kernel_hash(), w.name)
 
     out = {
         "metric": METRIC,

@@ -216,12 +216,18 @@ class Solver:
         self._chk(self._lib.ccpr_bind_workspace(self._h, C.c_void_p(ptr), nbytes, C.c_void_p(stream)),
                   "ccpr_bind_workspace")
 
-    def bind_torch(self, nsteps: int, device=None, extra: int = 0):
+    def bind_torch(self, nsteps: int, device=None, extra: int = 0, reserve: int = 4 << 30):
         """Allocate the workspace as a torch uint8 CUDA tensor and bind it with
-        torch's current stream on that device."""
+        torch's current stream on that device.  When the full gradient history
+        does not fit in the device's free memory (less 'reserve' bytes), the
+        workspace takes what is free and the library splits the run into
+        checkpointed segments (ccpr_set_checkpointing(0), the default)."""
         import torch
         dev = torch.device(device or "cuda")
         nbytes = self.workspace_size(nsteps) + extra
+        free, _ = torch.cuda.mem_get_info(dev)
+        if nbytes > free - reserve:
+            nbytes = max(free - reserve, 1 << 20)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         stream = torch.cuda.current_stream(dev).cuda_stream
         self.bind_workspace(ws.data_ptr(), nbytes, stream)
