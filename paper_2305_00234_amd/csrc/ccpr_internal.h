@@ -132,7 +132,7 @@ struct StepArgs {
     const unsigned* rowf;       // row classes [k*ny + j]
     const unsigned* lanef;      // lane classes [nxp]
     float* drive;               // S curl H' of design voxels [3][nd], then source cells [sncell][3]
-    const int4* extra;          // non-design cells finished by the aux kernel: (i, j, k, kind)
+    const int4* extra;          // non-design cells finished by the post kernel: (i, j, k, kind)
     long long nextra;
     unsigned cstride;           // bytes between field components (npad*4)
     int stream_st;              // 1: write the streamed state with nontemporal stores
@@ -175,7 +175,7 @@ int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream);
 // aux kernel over the nd design voxels
 int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, void* stream);
 // before a step: x-CPML and TF/SF corrections of H^{n-1/2} (nxs x-layer cells,
-// ntf TF/SF H words); after it: x-CPML of E^{n+1}
+// ntf TF/SF H words)
 int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* stream);
 // after the aux kernel: x-CPML of E^{n+1} (nxs x-layer cells) and the
 // nmisc = nextra + tf_nE source / gap cells and TF/SF E words

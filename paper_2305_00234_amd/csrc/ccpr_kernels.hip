@@ -3,32 +3,39 @@
 // One leapfrog step -- H^{n-1/2} -> H^{n+1/2} (Faraday, supplement
 // Eq. Maxwells2 c) and E^n -> E^{n+1} with the CCPR pole-pair currents
 // (Eqs. Maxwells2 a, b; interpolation Eqs. eps_mixed, sigma_mixed,
-// Poles_mixed) -- is two launches:
+// Poles_mixed) -- is a short sequence of launches:
+//  - ccpr_pre_kernel: the x-CPML and TF/SF corrections of H^{n-1/2} (only
+//    when the previous step's post launch did not already apply them);
 //  - ccpr_step_kernel streams the whole grid once (every E and H word read
-//    once and written once: 48 bytes per cell) and applies the vacuum update,
-//    the CPML memories and the TF/SF face corrections.  For design and source
-//    cells it also stores the E drive S curl H';
-//  - ccpr_aux_kernel, one thread per design voxel (plus the few source and gap
-//    cells outside the design), redoes those cells' E update from E^n and the
-//    drive: CCPR pole-pair currents, source current, the forward gradient
-//    record and the adjoint gradient correlation (Eq. Gradient_FDTD), and the
-//    gap monitor.
-// Keeping the dispersive work out of the grid kernel keeps the grid kernel's
-// loop at the register and instruction budget of a plain Yee update.
+//    once and written once: 48 bytes per cell) with the vacuum update and the
+//    y/z CPML memories, as two concurrent launches (tiles that touch a y or z
+//    CPML layer, interior tiles).  For design and source cells it also stores
+//    the E drive S curl H';
+//  - ccpr_aux_kernel, one thread per design voxel, redoes those cells' E
+//    update from E^n and the drive: CCPR pole-pair currents, source current,
+//    the forward gradient record and the adjoint gradient correlation (Eq.
+//    Gradient_FDTD, or the running transforms of the DFT-mode estimator), and
+//    the gap monitor;
+//  - ccpr_post_kernel: the x-CPML correction of E^{n+1}, the source and gap
+//    cells outside the design and the TF/SF E faces; ccpr_post_fused_kernel
+//    does the same and also the next step's pre work when that step follows
+//    at once.
+// Keeping the dispersive work and the x layers out of the grid kernel keeps
+// its loop at the register and instruction budget of a plain Yee update.
 //
 // Grid kernel decomposition (memory-bound stencil, no MFMA):
 //  - a workgroup spans the whole x extent (blockDim = nx rounded up to 64),
 //    so x-neighbours come from DPP wave shifts plus one LDS word per wave seam;
 //  - each thread owns R consecutive y rows (register blocking) and the
-//    workgroup marches over a chunk of tz z-planes, keeping the previous
-//    plane's new H and the next plane's old E in registers;
+//    workgroup marches over a chunk of z-planes, keeping the previous plane's
+//    new H and the next plane's old E in registers;
 //  - H^{n+1/2} is recomputed on one halo row (y = j0-1) and one halo plane
 //    (z = k0-1) so the E update never waits on another workgroup.  E, H and
 //    the H-side CPML memories are therefore double-buffered (read old, write
 //    new); pole currents and E-side CPML memories are touched only by their
 //    owner and are updated in place;
 //  - workgroups are numbered so that each XCD gets a contiguous run of
-//    y-strips: neighbouring strips share their halo rows in the same L2.
+//    tiles: neighbouring y-strips share their halo rows in the same L2.
 #include <hip/hip_runtime.h>
 
 #include "ccpr_internal.h"

@@ -47,7 +47,7 @@ struct Layout {
     size_t extra[2];             // [state] aux-kernel cell list
     size_t zr;                   // z-chunk plane ranges of the step kernel
     size_t tiles;                // tile lists of the step kernel (interior, then CPML)
-    size_t drive;                // S curl H' of the aux kernel's cells (scratch of one step)
+    size_t drive;                // S curl H' of design and source cells (scratch of one step)
     size_t rho, pmlE, pmlH, scal, gradacc, work;
     size_t fixed_end;
     // variable part
@@ -610,7 +610,7 @@ void fill_classes(const ccpr_solver* s, const StepCold& C, std::vector<unsigned>
     }
 }
 
-// Cells outside the design box that the aux kernel finishes: source cells
+// Cells outside the design box that the post kernel finishes: source cells
 // (E update from the stored drive minus the source current) and gap-monitor
 // cells outside both boxes (monitor only).
 void fill_extra(const StepCold& C, std::vector<int4>& ex)
@@ -705,8 +705,8 @@ ccpr_status upload_cold(ccpr_solver* s, int st)
         HIPCHK(hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&s->pdone_ev, hipEventDisableTiming));
     }
-    // source and gap cells are finished by the aux kernel before the x-CPML
-    // pass of E: they must lie outside the x layers
+    // source and gap cells outside the design are finished in the same post
+    // launch as the x-CPML pass of E, so they must lie outside the x layers
     if (s->g.npml > 0) {
         auto off_x_layers = [&](const int* lo, const int* dim) {
             return lo[0] >= s->g.npml && lo[0] + dim[0] <= s->g.nx - s->g.npml;
