@@ -643,11 +643,12 @@ int or_objective(or_sim* s, int nsteps, int obj_kind, const int* gap_lo, const i
  * exactly like J_src, and the forward sources are off.  After adjoint step p
  * visit(s, p, ctx) sees the adjoint fields Et^{p+1}.  The forward sources are
  * restored afterwards; the simulation is left holding the adjoint fields. */
-static void adjoint_run(or_sim* s, int M, const int* gap_lo, const int* gap_dims,
-                        const double* dFdE, void (*visit)(or_sim*, int, void*), void* ctx)
+static int adjoint_run(or_sim* s, int M, const int* gap_lo, const int* gap_dims,
+                       const double* dFdE, void (*visit)(or_sim*, int, void*), void* ctx)
 {
     int ncell = gap_dims[0] * gap_dims[1] * gap_dims[2];
-    double* adj = malloc((size_t)M * ncell * 3 * sizeof(double));
+    double* adj = calloc((size_t)M * ncell * 3, sizeof(double));
+    if (!adj) return -1;
     for (int p = 0; p < M; ++p)
         for (int e = 0; e < ncell * 3; ++e)
             adj[(size_t)p * ncell * 3 + e] = dFdE[(size_t)(M - p) * ncell * 3 + e] / s->dt;
@@ -677,6 +678,7 @@ static void adjoint_run(or_sim* s, int M, const int* gap_lo, const int* gap_dims
     s->dip_on = dip_on;
     s->pw_on = pw_on;
     free(adj);
+    return 0;
 }
 
 /* adjoint E of the three edges of design voxel v */
@@ -726,9 +728,9 @@ int or_gradient(or_sim* s, int nsteps, int obj_kind, const int* gap_lo, const in
     if (gap_hist_out) memcpy(gap_hist_out, hist, ne * sizeof(double));
     for (int v = 0; v < nd; ++v) grad_out[v] = 0.0;
     exact_ctx c = {M, T_hist, grad_out};
-    adjoint_run(s, M, gap_lo, gap_dims, dFdE, exact_visit, &c);
+    int rc = adjoint_run(s, M, gap_lo, gap_dims, dFdE, exact_visit, &c);
     free(hist); free(dFdE); free(T_hist);
-    return 0;
+    return rc;
 }
 
 int or_dft_window(int nsteps, double omega, double dt)
@@ -795,7 +797,10 @@ int or_gradient_dft(or_sim* s, int nsteps, const int* gap_lo, const int* gap_dim
                           hist, dFdE);
     const int L = or_dft_window(M, omega, s->dt);
     dft_ctx c = {M - L + 1, omega * s->dt, P, 0.0, 0.0, 0.0};
-    adjoint_run(s, M, gap_lo, gap_dims, dFdE, dft_visit, &c);
+    if (adjoint_run(s, M, gap_lo, gap_dims, dFdE, dft_visit, &c)) {
+        free(hist); free(dFdE); free(T_hat); free(P);
+        return -1;
+    }
     /* [scc scs; scs sss] [a; b] = [sum Et cos; sum Et sin] = [Re P; -Im P] */
     const double det = c.scc * c.sss - c.scs * c.scs;
     const cplx W = cexp(I * omega * s->dt * M);
