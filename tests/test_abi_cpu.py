@@ -128,3 +128,21 @@ def test_bind_rejects_misaligned_or_small(built):
         s.bind_workspace(0x100000, 16)
     assert e.value.status == L.ENOMEM
     s.close()
+
+
+def test_gradient_mode_selection_and_workspace(built):
+    """ccpr_set_gradient_mode: unknown modes are rejected; the DFT mode keeps
+    12 floats per design voxel instead of 3 per voxel and step."""
+    s = L.Solver(32, 32, 32, 10e-9, npml=8)
+    s.set_design((12, 12, 12), np.full((4, 4, 4), 0.5, np.float32))
+    s.set_source_dipole((10, 16, 16), 0, np.ones(400))
+    s.set_objective(L.OBJ_DFT_E2, (15, 15, 15), (2, 2, 2), 3e15)
+    assert s._lib.ccpr_set_gradient_mode(s._h, 7) == L.EINVAL
+    b_time = s.workspace_size(400)
+    s.set_gradient_mode("dft")
+    b_dft = s.workspace_size(400)
+    nd = 4 * 4 * 4
+    assert b_time - b_dft == 400 * 3 * nd * 4 - 12 * nd * 4
+    s.set_gradient_mode("time")
+    assert s.workspace_size(400) == b_time
+    s.close()
