@@ -278,22 +278,26 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
     for (int r = 0; r <= R; ++r) { hxm[r] = 0.f; hym[r] = 0.f; }
 
     for (int kk = k0 - 1; kk < k1; ++kk) {
-        // ---- loads: E^n of plane kk+1, H^{n-1/2} of plane kk (unconditional;
-        // ghost rows and planes are zero)
+        // ---- loads: E^n of plane kk+1, H^{n-1/2} of plane kk (ghost rows and
+        // planes are zero).  Two words of the z halo are never used and not
+        // read: Ez of plane k1 (the last H update takes only the z-differences
+        // of Ex and Ey) and Hz of the halo plane k0-1 (the first E update
+        // takes only Hx and Hy from below).
         float hxo[R + 1], hyo[R + 1], hzo[R + 1];
+        const bool zlast = kk + 1 >= k1, zhalo = kk < k0;  // uniform
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) {
             const unsigned o = poff(kk + 1, r);
             nex[r] = ldf(a.Ei, o);
             ney[r] = ldf(a.Ei, o + cs);
-            nez[r] = ldf(a.Ei, o + 2 * cs);
+            nez[r] = zlast ? 0.f : ldf(a.Ei, o + 2 * cs);
         }
 #pragma unroll
         for (int r = 0; r <= R; ++r) {
             const unsigned o = poff(kk, r);
             hxo[r] = ldf(a.Hi, o);
             hyo[r] = ldf(a.Hi, o + cs);
-            hzo[r] = ldf(a.Hi, o + 2 * cs);
+            hzo[r] = zhalo ? 0.f : ldf(a.Hi, o + 2 * cs);
         }
 
         // ---- row classes of this plane.  Row r is H row j0-1+r; E rows are r = 1..R.
