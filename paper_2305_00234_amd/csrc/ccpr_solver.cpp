@@ -1759,5 +1759,7 @@ void ccpr_pipe_unbind(ccpr_solver* s)
     if (!s->own_stream2) s->stream2 = nullptr;  // the engine's stream goes back to its pool
     s->have_forward = s->have_adjoint = false;
     s->rho_uploaded = false;
+    s->lead2 = false;  // (the engine unbinds after the solve's work completed)
+    s->pre_done[0] = s->pre_done[1] = false;
     std::memset(s->fixed_key, 0xff, sizeof s->fixed_key);
 }
