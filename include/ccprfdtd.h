@@ -273,6 +273,39 @@ typedef struct ccpr_engine ccpr_engine;
 
 enum { CCPR_JOB_QUEUED = 0, CCPR_JOB_RUNNING = 1, CCPR_JOB_DONE = 2, CCPR_JOB_FAILED = 3 };
 
+/* Design filtering and projection (Sec. Filtering and projection), on the
+ * per-voxel density grid of the design box: dims = (nx, ny, nz), arrays of
+ * nx*ny*nz values, x fastest, distances in voxels.  All pointers are device
+ * memory owned by the caller; the calls are stream-ordered on hip_stream
+ * (hipStream_t, may be NULL) and do not synchronise.  They take no solver:
+ * CCPR_EINVAL for bad arguments, CCPR_EDEVICE when the launch fails (no
+ * message is kept).
+ *
+ * ccpr_filter_project: Eq. FilterFunction, the cone filter
+ *   rho_filtered[n] = sum_m w(n,m) rho[m] / sum_m w(n,m),  w = R - |r_m - r_n|,
+ * over the design voxels m with |r_m - r_n| < R (1 <= radius <= 17), writing
+ * the weight sum weight_sum[n] = sum_m w(n,m) for the backward pass; then Eq.
+ * Projection, the smoothed Heaviside
+ *   rho_projected = (tanh(beta eta) + tanh(beta (rho_filtered - eta)))
+ *                   / (tanh(beta eta) + tanh(beta (1 - eta))),
+ * beta > 0, 0 <= eta <= 1.  FP32. */
+ccpr_status ccpr_filter_project(const float* rho, float* rho_filtered, float* rho_projected, float* weight_sum,
+                                const int dims[3], double radius, double beta, double eta, void* hip_stream);
+
+/* Eq. GradientsFiltered, the chain rule of ccpr_filter_project:
+ *   dF_drho[n] = sum_m dF_dprojected[m] * drho_projected/drho_filtered[m]
+ *                * w(m,n) / weight_sum[m],
+ * from that call's rho_filtered and weight_sum (same dims, radius, beta,
+ * eta).  FP64 in and out. */
+ccpr_status ccpr_filter_project_grad(const double* dF_dprojected, const float* rho_filtered, const float* weight_sum,
+                                     double* dF_drho, const int dims[3], double radius, double beta, double eta,
+                                     void* hip_stream);
+
+/* Eq. MeasureOfNon-discretness: *out = sum 4 rho (1 - rho) / n x 100 (per
+ * cent) over n projected densities, FP64, written to device memory; the
+ * summation order is fixed (bitwise reproducible). */
+ccpr_status ccpr_nondiscreteness(const float* rho_projected, long long n, double* out, void* hip_stream);
+
 /* arena: device memory the engine sub-allocates for the solves' workspaces
  * (256-byte aligned, caller-owned, valid until ccpr_engine_destroy returns);
  * max_active: solves on the device at once (1..64); chunk_steps: leapfrog

@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import torch
 
-from .lib import Solver
+from .lib import Solver, filter_project, filter_project_grad
 
 
 class CCPRObjective(torch.autograd.Function):
@@ -54,3 +54,37 @@ class CCPRObjective(torch.autograd.Function):
 def objective(rho, solver: Solver, nsteps: int, design_lo, gamma: float = 0.0):
     """Functional form of CCPRObjective.apply."""
     return CCPRObjective.apply(rho, solver, nsteps, design_lo, gamma)
+
+
+class FilterProject(torch.autograd.Function):
+    """rho_projected = FilterProject.apply(rho, radius, beta, eta): the cone
+    filter (Eq. FilterFunction) and the smoothed Heaviside projection (Eq.
+    Projection) of a CUDA density tensor (dz, dy, dx), computed by the
+    library's kernels in FP32; the backward is the chain rule of Eq.
+    GradientsFiltered, in FP64, returned in rho's dtype."""
+
+    @staticmethod
+    def forward(ctx, rho, radius: float, beta: float, eta: float):
+        if not rho.is_cuda:
+            raise ValueError("rho must be a CUDA tensor")
+        r32 = rho.detach().to(torch.float32).contiguous()
+        rt, rb, ws = filter_project(r32, radius, beta, eta)
+        ctx.save_for_backward(rt, ws)
+        ctx.params = (radius, beta, eta)
+        ctx.rho_dtype = rho.dtype
+        return rb.to(rho.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        rt, ws = ctx.saved_tensors
+        radius, beta, eta = ctx.params
+        g = filter_project_grad(grad_out.detach().to(torch.float64).contiguous(), rt, ws, radius, beta, eta)
+        return g.to(ctx.rho_dtype), None, None, None
+
+
+def filtered_objective(rho, solver: Solver, nsteps: int, design_lo, gamma: float, radius: float,
+                       beta: float, eta: float = 0.5):
+    """F(project(filter(rho))): the density the solver sees is the filtered and
+    projected one; autograd chains Eq. GradientsFiltered after the adjoint
+    gradient."""
+    return CCPRObjective.apply(FilterProject.apply(rho, radius, beta, eta), solver, nsteps, design_lo, gamma)

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libccprfdtd.so")
 ARCH = os.environ.get("CCPR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["ccpr_kernels.hip", "ccpr_solver.cpp", "ccpr_engine.cpp"]
+SOURCES = ["ccpr_kernels.hip", "ccpr_solver.cpp", "ccpr_engine.cpp", "ccpr_filter.hip"]
 
 # -packed-fp32-ops: no v_pk_*_f32 from the compiler (they are avoided on this
 # hardware); -ffp-contract=fast lets hipcc fuse a*b+c into FMA.

@@ -1,0 +1,192 @@
+// gfx950 kernels of the design filtering and projection (Sec. "Filtering and
+// projection"): the cone filter of Eq. FilterFunction, the smoothed Heaviside
+// of Eq. Projection, their chain rule (Eq. GradientsFiltered) and the measure
+// of non-discreteness (Eq. MeasureOfNon-discretness), on the per-voxel density
+// grid of the design box ([nz][ny][nx], x fastest; distances in voxels).
+//
+// The filter is a 3-D stencil over the sphere |d| < R (R <= 17 voxels).  A
+// workgroup owns a 16 x 16 tile of one output plane; for every z offset it
+// stages the input plane's tile plus an R-wide halo in LDS as (value, inside)
+// pairs and each lane sums the disk of that offset straight from LDS, so
+// every input word is read from HBM once per (output plane, offset) workgroup
+// and the taps cost LDS reads only.  Loop bounds are uniform per workgroup.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "../../include/ccprfdtd.h"
+
+namespace {
+
+constexpr int kFT = 16;                   // output tile edge (x and y)
+constexpr int kMaxRi = 16;                // largest integer offset (radius <= 17)
+constexpr int kTW = kFT + 2 * kMaxRi;     // staged tile edge
+
+// Eq. FilterFunction and Eq. Projection: rho -> rho_t (filtered), rho_b
+// (projected) and W (cone-weight sum of the design voxels in the sphere).
+__global__ __launch_bounds__(256) void filter_project_kernel(const float* __restrict__ rho, float* rho_t,
+                                                             float* rho_b, float* wsum, int nx, int ny, int nz,
+                                                             float R, int Ri, float beta, float eta, float tbe,
+                                                             float inv_den)
+{
+    __shared__ float2 tile[kTW * kTW];  // (density, 1) inside the box, (0, 0) outside
+    const int tx = threadIdx.x % kFT, ty = threadIdx.x / kFT;
+    const int i = blockIdx.x * kFT + tx, j = blockIdx.y * kFT + ty, k = blockIdx.z;
+    const int W = kFT + 2 * Ri;
+    const int gx0 = blockIdx.x * kFT - Ri, gy0 = blockIdx.y * kFT - Ri;
+    float num = 0.f, den = 0.f;
+    for (int dz = -Ri; dz <= Ri; ++dz) {
+        const int kk = k + dz;
+        const float rz2 = R * R - (float)(dz * dz);
+        if (kk < 0 || kk >= nz || rz2 <= 0.f) continue;  // uniform
+        __syncthreads();
+        for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
+            const int ly = t / W, lx = t - ly * W;
+            const int gx = gx0 + lx, gy = gy0 + ly;
+            const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            tile[t] = in ? make_float2(rho[((long long)kk * ny + gy) * nx + gx], 1.f) : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        for (int dy = -Ri; dy <= Ri; ++dy) {
+            const float ry2 = rz2 - (float)(dy * dy);
+            if (ry2 <= 0.f) continue;  // uniform
+            const int dxm = (int)ceilf(sqrtf(ry2)) - 1;  // dx^2 < ry2
+            const int d2yz = dy * dy + dz * dz;
+            const float2* row = tile + (ty + Ri + dy) * W + (tx + Ri);
+            for (int dx = -dxm; dx <= dxm; ++dx) {
+                const float w = R - sqrtf((float)(dx * dx + d2yz));
+                const float2 v = row[dx];
+                num = fmaf(w, v.x, num);
+                den = fmaf(w, v.y, den);
+            }
+        }
+    }
+    if (i < nx && j < ny) {
+        const long long n = ((long long)k * ny + j) * nx + i;
+        const float rt = num / den;
+        rho_t[n] = rt;
+        wsum[n] = den;
+        rho_b[n] = (tbe + tanhf(beta * (rt - eta))) * inv_den;
+    }
+}
+
+// Eq. GradientsFiltered: dF/drho[n] = sum_m w(m,n) v[m] over the design
+// voxels m of the sphere around n, v = dF/drho_b * d rho_b/d rho_t / W,
+// all in FP64 (the staged tile holds v, zero outside the box).
+__global__ __launch_bounds__(256) void filter_project_grad_kernel(const double* __restrict__ g_b,
+                                                                  const float* __restrict__ rho_t,
+                                                                  const float* __restrict__ wsum, double* g,
+                                                                  int nx, int ny, int nz, float R, int Ri,
+                                                                  double beta, double eta, double inv_den)
+{
+    __shared__ double tile[kTW * kTW];
+    const int tx = threadIdx.x % kFT, ty = threadIdx.x / kFT;
+    const int i = blockIdx.x * kFT + tx, j = blockIdx.y * kFT + ty, k = blockIdx.z;
+    const int W = kFT + 2 * Ri;
+    const int gx0 = blockIdx.x * kFT - Ri, gy0 = blockIdx.y * kFT - Ri;
+    double acc = 0.0;
+    for (int dz = -Ri; dz <= Ri; ++dz) {
+        const int kk = k + dz;
+        const float rz2 = R * R - (float)(dz * dz);
+        if (kk < 0 || kk >= nz || rz2 <= 0.f) continue;  // uniform
+        __syncthreads();
+        for (int t = threadIdx.x; t < W * W; t += blockDim.x) {
+            const int ly = t / W, lx = t - ly * W;
+            const int gx = gx0 + lx, gy = gy0 + ly;
+            double v = 0.0;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                const long long m = ((long long)kk * ny + gy) * nx + gx;
+                const double th = tanh(beta * ((double)rho_t[m] - eta));
+                v = g_b[m] * (beta * (1.0 - th * th) * inv_den) / (double)wsum[m];
+            }
+            tile[t] = v;
+        }
+        __syncthreads();
+        for (int dy = -Ri; dy <= Ri; ++dy) {
+            const float ry2 = rz2 - (float)(dy * dy);
+            if (ry2 <= 0.f) continue;  // uniform
+            const int dxm = (int)ceilf(sqrtf(ry2)) - 1;
+            const int d2yz = dy * dy + dz * dz;
+            const double* row = tile + (ty + Ri + dy) * W + (tx + Ri);
+            for (int dx = -dxm; dx <= dxm; ++dx) {
+                const float w = R - sqrtf((float)(dx * dx + d2yz));
+                acc = fma((double)w, row[dx], acc);
+            }
+        }
+    }
+    if (i < nx && j < ny) g[((long long)k * ny + j) * nx + i] = acc;
+}
+
+// Eq. MeasureOfNon-discretness: one workgroup, fixed summation order (wave
+// shuffles, then LDS), so the result does not depend on the launch.
+__global__ __launch_bounds__(1024) void nondiscreteness_kernel(const float* __restrict__ rb, long long n, double* out)
+{
+    __shared__ double part[16];
+    double s = 0.0;
+    for (long long t = threadIdx.x; t < n; t += blockDim.x) {
+        const double r = rb[t];
+        s += 4.0 * r * (1.0 - r);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += part[w];
+        out[0] = tot / (double)n * 100.0;
+    }
+}
+
+bool dims_ok(const int* d)
+{
+    return d && d[0] >= 1 && d[1] >= 1 && d[2] >= 1 && d[2] <= 65535;
+}
+
+int radius_to_offsets(double R)
+{
+    // largest integer offset with |d| < R
+    return (int)std::ceil(R) - 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+ccpr_status ccpr_filter_project(const float* rho, float* rho_filtered, float* rho_projected, float* weight_sum,
+                                const int dims[3], double radius, double beta, double eta, void* hip_stream)
+{
+    if (!rho || !rho_filtered || !rho_projected || !weight_sum || !dims_ok(dims)) return CCPR_EINVAL;
+    if (!(radius >= 1.0 && radius <= 17.0) || !(beta > 0) || !(eta >= 0 && eta <= 1)) return CCPR_EINVAL;
+    const int Ri = radius_to_offsets(radius);
+    const double den = std::tanh(beta * eta) + std::tanh(beta * (1.0 - eta));
+    dim3 grid((unsigned)((dims[0] + kFT - 1) / kFT), (unsigned)((dims[1] + kFT - 1) / kFT), (unsigned)dims[2]);
+    hipLaunchKernelGGL(filter_project_kernel, grid, dim3(kFT * kFT), 0, (hipStream_t)hip_stream, rho, rho_filtered,
+                       rho_projected, weight_sum, dims[0], dims[1], dims[2], (float)radius, Ri, (float)beta,
+                       (float)eta, (float)std::tanh(beta * eta), (float)(1.0 / den));
+    return hipGetLastError() == hipSuccess ? CCPR_OK : CCPR_EDEVICE;
+}
+
+ccpr_status ccpr_filter_project_grad(const double* dF_dprojected, const float* rho_filtered, const float* weight_sum,
+                                     double* dF_drho, const int dims[3], double radius, double beta, double eta,
+                                     void* hip_stream)
+{
+    if (!dF_dprojected || !rho_filtered || !weight_sum || !dF_drho || !dims_ok(dims)) return CCPR_EINVAL;
+    if (!(radius >= 1.0 && radius <= 17.0) || !(beta > 0) || !(eta >= 0 && eta <= 1)) return CCPR_EINVAL;
+    const int Ri = radius_to_offsets(radius);
+    const double den = std::tanh(beta * eta) + std::tanh(beta * (1.0 - eta));
+    dim3 grid((unsigned)((dims[0] + kFT - 1) / kFT), (unsigned)((dims[1] + kFT - 1) / kFT), (unsigned)dims[2]);
+    hipLaunchKernelGGL(filter_project_grad_kernel, grid, dim3(kFT * kFT), 0, (hipStream_t)hip_stream, dF_dprojected,
+                       rho_filtered, weight_sum, dF_drho, dims[0], dims[1], dims[2], (float)radius, Ri, beta, eta,
+                       1.0 / den);
+    return hipGetLastError() == hipSuccess ? CCPR_OK : CCPR_EDEVICE;
+}
+
+ccpr_status ccpr_nondiscreteness(const float* rho_projected, long long n, double* out, void* hip_stream)
+{
+    if (!rho_projected || !out || n < 1) return CCPR_EINVAL;
+    hipLaunchKernelGGL(nondiscreteness_kernel, dim3(1), dim3(1024), 0, (hipStream_t)hip_stream, rho_projected, n,
+                       out);
+    return hipGetLastError() == hipSuccess ? CCPR_OK : CCPR_EDEVICE;
+}
+
+}  // extern "C"

@@ -33,6 +33,7 @@ EXPORTS = [
     "ccpr_set_tile_planes", "ccpr_set_tile_rows",
     "ccpr_engine_create", "ccpr_engine_submit", "ccpr_engine_poll", "ccpr_engine_wait",
     "ccpr_engine_result", "ccpr_engine_release", "ccpr_engine_last_error", "ccpr_engine_destroy",
+    "ccpr_filter_project", "ccpr_filter_project_grad", "ccpr_nondiscreteness",
 ]
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 GRAD_TIME_EXACT, GRAD_DFT = 0, 1
@@ -103,6 +104,9 @@ def load():
         "ccpr_engine_release": (_i, [_p, C.c_uint64]),
         "ccpr_engine_last_error": (C.c_char_p, [_p]),
         "ccpr_engine_destroy": (None, [_p]),
+        "ccpr_filter_project": (_i, [_p, _p, _p, _p, _ip, _d, _d, _d, _p]),
+        "ccpr_filter_project_grad": (_i, [_p, _p, _p, _p, _ip, _d, _d, _d, _p]),
+        "ccpr_nondiscreteness": (_i, [_p, C.c_longlong, _p, _p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -119,6 +123,63 @@ def _i3(v: Sequence[int]):
 def _f64(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data_as(_dp)
+
+
+def _check_free(st, what):
+    if st != OK:
+        raise CcprError(st, what, "")
+
+
+def _cuda_tensor(t, dtype, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+            and t.dim() == 3):
+        raise ValueError(f"{name} must be a contiguous 3-D CUDA {dtype} tensor (dz, dy, dx)")
+    return t
+
+
+def filter_project(rho, radius: float, beta: float, eta: float):
+    """ccpr_filter_project on a float32 CUDA density tensor (dz, dy, dx), on
+    torch's current stream: returns (rho_filtered, rho_projected, weight_sum)."""
+    import torch
+    _cuda_tensor(rho, torch.float32, "rho")
+    rt, rb, ws = torch.empty_like(rho), torch.empty_like(rho), torch.empty_like(rho)
+    dims = _i3((rho.shape[2], rho.shape[1], rho.shape[0]))
+    st = load().ccpr_filter_project(C.c_void_p(rho.data_ptr()), C.c_void_p(rt.data_ptr()),
+                                    C.c_void_p(rb.data_ptr()), C.c_void_p(ws.data_ptr()), dims, radius,
+                                    beta, eta, C.c_void_p(torch.cuda.current_stream(rho.device).cuda_stream))
+    _check_free(st, "ccpr_filter_project")
+    return rt, rb, ws
+
+
+def filter_project_grad(dF_dprojected, rho_filtered, weight_sum, radius: float, beta: float, eta: float):
+    """ccpr_filter_project_grad: dF/drho (float64) from dF/drho_projected
+    (float64) and the forward call's rho_filtered and weight_sum."""
+    import torch
+    _cuda_tensor(dF_dprojected, torch.float64, "dF_dprojected")
+    _cuda_tensor(rho_filtered, torch.float32, "rho_filtered")
+    _cuda_tensor(weight_sum, torch.float32, "weight_sum")
+    g = torch.empty_like(dF_dprojected)
+    dims = _i3((g.shape[2], g.shape[1], g.shape[0]))
+    st = load().ccpr_filter_project_grad(C.c_void_p(dF_dprojected.data_ptr()),
+                                         C.c_void_p(rho_filtered.data_ptr()), C.c_void_p(weight_sum.data_ptr()),
+                                         C.c_void_p(g.data_ptr()), dims, radius, beta, eta,
+                                         C.c_void_p(torch.cuda.current_stream(g.device).cuda_stream))
+    _check_free(st, "ccpr_filter_project_grad")
+    return g
+
+
+def nondiscreteness(rho_projected) -> float:
+    """ccpr_nondiscreteness (per cent); synchronises to return the value."""
+    import torch
+    if not (rho_projected.is_cuda and rho_projected.dtype == torch.float32 and rho_projected.is_contiguous()):
+        raise ValueError("rho_projected must be a contiguous float32 CUDA tensor")
+    out = torch.empty(1, dtype=torch.float64, device=rho_projected.device)
+    st = load().ccpr_nondiscreteness(C.c_void_p(rho_projected.data_ptr()), rho_projected.numel(),
+                                     C.c_void_p(out.data_ptr()),
+                                     C.c_void_p(torch.cuda.current_stream(out.device).cuda_stream))
+    _check_free(st, "ccpr_nondiscreteness")
+    return float(out.item())
 
 
 class Solver:

@@ -146,3 +146,19 @@ def test_gradient_mode_selection_and_workspace(built):
     s.set_gradient_mode("time")
     assert s.workspace_size(400) == b_time
     s.close()
+
+
+def test_filter_calls_validate_arguments(built):
+    """The stateless filter / projection calls reject bad arguments before
+    touching the device."""
+    lib = L.load()
+    dims = L._i3((8, 8, 8))
+    p = C.c_void_p(0x1000)
+    assert lib.ccpr_filter_project(None, p, p, p, dims, 2.0, 8.0, 0.5, None) == L.EINVAL
+    assert lib.ccpr_filter_project(p, p, p, p, dims, 0.5, 8.0, 0.5, None) == L.EINVAL    # radius < 1
+    assert lib.ccpr_filter_project(p, p, p, p, dims, 18.0, 8.0, 0.5, None) == L.EINVAL   # radius > 17
+    assert lib.ccpr_filter_project(p, p, p, p, dims, 2.0, 0.0, 0.5, None) == L.EINVAL    # beta <= 0
+    assert lib.ccpr_filter_project(p, p, p, p, dims, 2.0, 8.0, 1.5, None) == L.EINVAL    # eta > 1
+    assert lib.ccpr_filter_project(p, p, p, p, L._i3((0, 8, 8)), 2.0, 8.0, 0.5, None) == L.EINVAL
+    assert lib.ccpr_filter_project_grad(p, None, p, p, dims, 2.0, 8.0, 0.5, None) == L.EINVAL
+    assert lib.ccpr_nondiscreteness(p, 0, p, None) == L.EINVAL

@@ -1,0 +1,106 @@
+"""Design filtering and projection on the GPU (through the C-ABI) against the
+FP64 oracle (oracle/filters.py): the cone filter and projection (FP32 on the
+GPU: relative error 1e-5), the chain rule (FP64: 1e-5), the measure of
+non-discreteness, and the filtered objective end to end through autograd
+against the oracle's solver gradient chained through the oracle's filter."""
+import numpy as np
+import pytest
+
+from oracle import filters as OF
+from paper_2305_00234_amd import inputs as I
+from tests.gpu_util import oracle_gradient, rel_l2, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+FILT_TOL = 1e-5
+
+
+def _rho(shape, seed):
+    return np.random.default_rng(seed).random(shape).astype(np.float32)
+
+
+@pytest.mark.parametrize("shape,R,beta,eta", [
+    ((23, 29, 37), 3.5, 8.0, 0.45),   # ragged tiles, fractional radius
+    ((11, 17, 16), 1.0, 4.0, 0.5),    # radius 1: the filter is the identity
+    ((20, 30, 40), 12.3, 16.0, 0.5),  # a large sphere, most of it outside the box
+    ((9, 5, 7), 17.0, 2.0, 0.3),      # the largest radius on a box smaller than it
+])
+def test_filter_project_matches_oracle(shape, R, beta, eta):
+    torch = require_gpu()
+    from paper_2305_00234_amd.lib import filter_project
+    rho = _rho(shape, seed=int(R * 10))
+    rt, rb, ws = filter_project(torch.tensor(rho, device="cuda"), R, beta, eta)
+    torch.cuda.synchronize()
+    ot = OF.cone_filter(rho.astype(np.float64), R)
+    ob = OF.project(ot, beta, eta)
+    ow = OF.weight_sums(shape, R)
+    # each step against the oracle on its own: the projection's slope (up to
+    # beta/2 at eta) amplifies the filter's FP32 rounding, so the projected
+    # density is checked against the oracle's projection of the GPU's
+    # filtered values
+    rt_h = rt.cpu().numpy()
+    ob_gpu_in = OF.project(rt_h.astype(np.float64), beta, eta)
+    say("filter", shape, R, "rho_t", rel_l2(rt_h, ot), "rho_b", rel_l2(rb.cpu().numpy(), ob_gpu_in),
+        "rho_b end to end", rel_l2(rb.cpu().numpy(), ob), "W", rel_l2(ws.cpu().numpy(), ow))
+    assert rel_l2(rt_h, ot) <= FILT_TOL
+    assert rel_l2(rb.cpu().numpy(), ob_gpu_in) <= FILT_TOL
+    assert rel_l2(ws.cpu().numpy(), ow) <= FILT_TOL
+    if R == 1.0:
+        assert np.array_equal(rt.cpu().numpy(), rho)
+
+
+def test_filter_project_grad_matches_oracle():
+    torch = require_gpu()
+    from paper_2305_00234_amd.lib import filter_project, filter_project_grad
+    shape, R, beta, eta = (21, 26, 33), 4.2, 10.0, 0.5
+    rho = _rho(shape, seed=3)
+    g_b = np.random.default_rng(4).standard_normal(shape)
+    rt, _, ws = filter_project(torch.tensor(rho, device="cuda"), R, beta, eta)
+    g = filter_project_grad(torch.tensor(g_b, device="cuda"), rt, ws, R, beta, eta)
+    torch.cuda.synchronize()
+    og = OF.filter_project_grad(g_b, rho.astype(np.float64), R, beta, eta)
+    say("chain rule rel L2", rel_l2(g.cpu().numpy(), og))
+    assert rel_l2(g.cpu().numpy(), og) <= FILT_TOL
+
+
+def test_nondiscreteness_matches_oracle():
+    torch = require_gpu()
+    from paper_2305_00234_amd.lib import nondiscreteness
+    rb = _rho((50, 60, 70), seed=8)
+    m = nondiscreteness(torch.tensor(rb, device="cuda"))
+    assert m == pytest.approx(OF.nondiscreteness(rb.astype(np.float64)), rel=1e-12)
+    assert nondiscreteness(torch.tensor((rb > 0.5).astype(np.float32), device="cuda")) == 0.0
+
+
+def test_filtered_objective_autograd_matches_oracle_chain():
+    """rho -> filter -> projection -> FDTD objective, one backward: against the
+    oracle's adjoint gradient at the projected density, chained through the
+    oracle's filter (Eq. GradientsFiltered)."""
+    torch = require_gpu()
+    from paper_2305_00234_amd.autograd import filtered_objective
+    from paper_2305_00234_amd.solver import configure
+    R, beta, eta = 2.5, 6.0, 0.5
+    w = I.drude_dipole_32(steps=300, n=32, npml=6)
+    w.shape = (30, 27, 33)
+    w.mat2 = (I.GOLD_TABLE1,) * 3
+    w.design_lo = (10, 9, 11)
+    rho0 = np.random.default_rng(11).random((9, 8, 10)).astype(np.float32)
+    w.rho = rho0
+    w.dipole_cell = (7, 13, 15)
+    w.gap_lo, w.gap_dims = (14, 12, 15), (2, 2, 2)
+    s = configure(w)
+    s.bind_torch(w.steps)
+    rho = torch.tensor(rho0, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = filtered_objective(rho, s, w.steps, w.design_lo, w.gamma, R, beta, eta)
+    F.backward()
+    g = rho.grad.detach().cpu().numpy()
+    Fv = float(F.detach())
+    s.close()
+    # oracle: the same chain in FP64
+    rb = OF.project(OF.cone_filter(rho0.astype(np.float64), R), beta, eta)
+    w.rho = rb
+    Fo, gbo, _, _ = oracle_gradient(w)
+    go = OF.filter_project_grad(gbo, rho0.astype(np.float64), R, beta, eta)
+    say("filtered objective F", Fv, Fo, "grad rel L2", rel_l2(g, go))
+    assert abs(Fv - Fo) <= 1e-5 * abs(Fo)
+    assert rel_l2(g, go) <= 1e-3
