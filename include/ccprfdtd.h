@@ -192,6 +192,18 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out);
  * CCPR_ESTATE before a successful ccpr_forward. */
 ccpr_status ccpr_adjoint(ccpr_solver* s);
 
+/* Spectrum of the gap field recorded by the last ccpr_forward (the monitor of
+ * Eq. Objective_analyitically_enhancement read in the frequency domain, as
+ * the paper's averaged gap-enhancement spectra): for each of nf angular
+ * frequencies omega[f] [rad/s],
+ *   mean_E2[f] = (1/ne) sum_e |dt sum_{n=0..M} E_e^n exp(-j omega[f] n dt)|^2
+ * over the ne = 3 x (gap cells) edges, in (V s / m)^2.  Dividing by the same
+ * quantity of the incident field gives the averaged enhancement spectrum.
+ * Host arrays; synchronises.  CCPR_ESTATE before ccpr_forward; CCPR_EINVAL
+ * for more frequencies than the workspace's staging area holds (one per 16
+ * bytes of max(4 cells, 8 design voxels)). */
+ccpr_status ccpr_gap_spectrum(ccpr_solver* s, const double* omega, int nf, double* mean_E2);
+
 /* dF/drho per design voxel (FP64: in SI units the objective of a weak source
  * is far below the FP32 range), dims of the design box, x fastest, written to
  * host memory (synchronises) or device memory (stream-ordered).  Eq.

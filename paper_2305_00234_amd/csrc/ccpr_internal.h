@@ -196,6 +196,10 @@ int ccpr_launch_extract(float* dst, const float* src, int comp, int nx, int ny, 
 // W = (wc, ws)
 int ccpr_launch_dft_grad(double* grad, const float* acc, long long nd, double i00, double i01, double i11,
                          double wc, double ws, void* stream);
+// spectrum of the recorded gap field at nf angular frequencies (device
+// arrays omega[nf], out[nf])
+int ccpr_launch_gap_spectrum(const float* gap, int M, int ne, double dt, const double* omega, int nf, double scale,
+                             double* out, void* stream);
 int ccpr_launch_grad_out(double* dst, const double* acc, long long n, const double* scale, void* stream);
 // SI objective and scales of a forward run into scal[4..6] (kind 1: DFT, 0: time)
 int ccpr_launch_finish(double* scal, int kind, double a, double dt, double dx, double eps0, void* stream);

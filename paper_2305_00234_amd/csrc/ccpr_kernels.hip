@@ -935,6 +935,35 @@ __global__ void incident_line_kernel(const double* wave, int nw, int M, int L, d
 //  TIME: F' = sum_{n in window} sum_e (E_e^n)^2; scale = max |E| over the window;
 //        adjoint drive r_{p,e} = E_e^{M-p} (M-p in the window).
 // adj[p*ne + e] = r / scale; scal[0] = F', scal[1] = scale.
+// Spectrum of the recorded gap field: block f takes angular frequency
+// omega[f]; out[f] = mean over the ne edges of |scale * sum_{n=0..M} E_e^n
+// exp(-j omega[f] dt n)|^2 (FP64 sums, fixed order).
+__global__ __launch_bounds__(256) void gap_spectrum_kernel(const float* gap, int M, int ne, double dt,
+                                                           const double* omega, double scale, double* out)
+{
+    __shared__ double part[256];
+    const double wdt = omega[blockIdx.x] * dt;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int n = 0; n <= M; ++n) {
+            double sn, cn;
+            sincos(wdt * n, &sn, &cn);
+            const double v = gap[(long long)n * ne + e];
+            re += v * cn;
+            im -= v * sn;
+        }
+        acc += (re * re + im * im) * scale * scale;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0] / (double)ne;
+}
+
 __global__ void objective_kernel(const float* gap, int M, int ne, int kind, double wdt, int nb,
                                  int nend, double* scal, double* work, float* adj)
 {
@@ -1175,6 +1204,15 @@ int ccpr_launch_objective(const float* gap, int M, int ne, int kind, double omeg
 {
     hipLaunchKernelGGL(objective_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, gap, M, ne,
                        kind, omega_dt, nb, nend, scal, work, adj);
+    return (int)hipGetLastError();
+}
+
+int ccpr_launch_gap_spectrum(const float* gap, int M, int ne, double dt, const double* omega, int nf, double scale,
+                             double* out, void* stream)
+{
+    if (nf <= 0 || ne <= 0) return 0;
+    hipLaunchKernelGGL(gap_spectrum_kernel, dim3((unsigned)nf), dim3(256), 0, (hipStream_t)stream, gap, M, ne, dt,
+                       omega, scale, out);
     return (int)hipGetLastError();
 }
 

@@ -1546,6 +1546,28 @@ ccpr_status ccpr_gradient(ccpr_solver* s, double* grad, int mem)
     return CCPR_OK;
 }
 
+ccpr_status ccpr_gap_spectrum(ccpr_solver* s, const double* omega, int nf, double* mean_E2)
+{
+    if (!s) return CCPR_EINVAL;
+    if (!omega || !mean_E2 || nf < 1) return fail(s, CCPR_EINVAL, "bad gap-spectrum arguments");
+    if (!s->have_forward) return fail(s, CCPR_ESTATE, "the gap spectrum needs a completed forward run");
+    const Layout& L = s->lay;
+    const size_t stage_bytes = std::max((size_t)s->ncell * 4, (size_t)std::max(s->nd, 1LL) * 8);
+    if ((size_t)nf * 16 > stage_bytes) return fail(s, CCPR_EINVAL, "too many frequencies (at most %zu)", stage_bytes / 16);
+    for (int f = 0; f < nf; ++f)
+        if (!std::isfinite(omega[f])) return fail(s, CCPR_EINVAL, "non-finite frequency");
+    ccpr_status st = join_lead(s);
+    if (st) return st;
+    double* dev = wsp<double>(s, L.stage);
+    HIPCHK(hipMemcpyAsync(dev, omega, nf * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    // recorded E' = alpha E: the SI transform is dt / alpha times the sum
+    HIPCHK(ccpr_launch_gap_spectrum(wsp<float>(s, L.gap), s->M, s->gncell * 3, s->dt, dev, nf, s->dt / s->alpha,
+                                    dev + nf, s->stream));
+    HIPCHK(hipMemcpyAsync(mean_E2, dev + nf, nf * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CCPR_OK;
+}
+
 // ---- diagnostics (declared in ccprfdtd.h)
 ccpr_status ccpr_set_timing(ccpr_solver* s, int enable)
 {

@@ -28,7 +28,7 @@ EXPORTS = [
     "ccpr_create", "ccpr_destroy", "ccpr_last_error", "ccpr_set_material", "ccpr_set_design",
     "ccpr_set_source_dipole", "ccpr_set_source_planewave", "ccpr_set_objective",
     "ccpr_set_checkpointing", "ccpr_set_gradient_mode", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
-    "ccpr_adjoint", "ccpr_gradient", "ccpr_reset", "ccpr_step", "ccpr_get_field",
+    "ccpr_adjoint", "ccpr_gradient", "ccpr_gap_spectrum", "ccpr_reset", "ccpr_step", "ccpr_get_field",
     "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_grid_timing", "ccpr_get_info",
     "ccpr_set_tile_planes", "ccpr_set_tile_rows",
     "ccpr_engine_create", "ccpr_engine_submit", "ccpr_engine_poll", "ccpr_engine_wait",
@@ -86,6 +86,7 @@ def load():
         "ccpr_forward": (_i, [_p, _i, _dp]),
         "ccpr_adjoint": (_i, [_p]),
         "ccpr_gradient": (_i, [_p, _p, _i]),
+        "ccpr_gap_spectrum": (_i, [_p, _dp, _i, _dp]),
         "ccpr_reset": (_i, [_p]),
         "ccpr_step": (_i, [_p, _i]),
         "ccpr_get_field": (_i, [_p, _i, _p, _i]),
@@ -303,6 +304,15 @@ class Solver:
 
     def adjoint(self):
         self._chk(self._lib.ccpr_adjoint(self._h), "ccpr_adjoint")
+
+    def gap_spectrum(self, omegas):
+        """Mean |E_hat(omega)|^2 over the gap edges of the last forward run, for
+        each angular frequency in omegas (numpy float64)."""
+        w, wp = _f64(np.atleast_1d(omegas))
+        out = np.zeros(w.size, dtype=np.float64)
+        self._chk(self._lib.ccpr_gap_spectrum(self._h, wp, w.size, out.ctypes.data_as(_dp)),
+                  "ccpr_gap_spectrum")
+        return out
 
     def gradient(self, out=None):
         """Host numpy (dz,dy,dx) float64 by default; pass a torch float64 CUDA

@@ -1,0 +1,37 @@
+"""Gap-field spectrum (multi-frequency DFT of the gap monitor) on the GPU
+against the FP64 oracle's gap history, and against the objective at the
+objective's own frequency."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.oracle import OBJ_DFT
+from paper_2305_00234_amd import inputs as I
+from tests.gpu_util import rel_l2, require_gpu, say
+from tests.oracle_setup import oracle_from_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def test_gap_spectrum_matches_oracle_and_objective():
+    torch = require_gpu()
+    from paper_2305_00234_amd.solver import configure
+    w = I.drude_dipole_32()
+    lam = np.linspace(350e-9, 1000e-9, 40)
+    omegas = np.concatenate([2 * math.pi * I.C0 / lam, [w.omega]])
+    s = configure(w)
+    s.bind_torch(w.steps)
+    F = s.forward(w.steps)
+    spec = s.gap_spectrum(omegas)
+    torch.cuda.synchronize()
+    s.close()
+    o = oracle_from_workload(w)
+    _, _, hist = o.gradient(w.steps, OBJ_DFT, w.gap_lo, w.gap_dims, w.omega, want_hist=True)
+    h = hist.reshape(w.steps + 1, -1)
+    n = np.arange(w.steps + 1)
+    spec_o = np.array([np.mean(np.abs(w.dt * (np.exp(-1j * om * n * w.dt) @ h)) ** 2) for om in omegas])
+    ne = h.shape[1]
+    say("spectrum rel L2", rel_l2(spec, spec_o), "at omega0", spec[-1] * ne, F)
+    assert rel_l2(spec, spec_o) <= 1e-5
+    assert spec[-1] * ne == pytest.approx(F, rel=1e-9)
