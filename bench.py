@@ -37,6 +37,7 @@ def workload_by_name(name, solve_steps=None):
         "drude_dipole_32": lambda m: I.drude_dipole_32(steps=m or 400),
         "gold_gap_td_512x512x256": lambda m: I.gold_gap_timedomain_512(steps=m or 8000),
         "aniso_two_material_384": lambda m: I.aniso_two_material_384(steps=m or 8000),
+        "paper_broadband_gold": lambda m: I.paper_broadband("gold", steps=m or 18000),
     }
     return table[name](solve_steps)
 

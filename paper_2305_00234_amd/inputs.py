@@ -86,6 +86,22 @@ def gaussian_sine(t: np.ndarray, lambda0: float, fwhm: float, t0: float, amp: fl
     return amp * np.exp(-4 * math.log(2) * (t - t0) ** 2 / fwhm ** 2) * np.sin(w0 * (t - t0))
 
 
+def sinc_hanning(t: np.ndarray, f0: float, rel_bandwidth: float = 0.5, lobes: int = 3,
+                 amp: float = 1.0) -> np.ndarray:
+    """Broadband excitation of the paper's optimisation runs (Sec. "Topology
+    Optimization Setup"): a sinc truncated to 'lobes' lobes on each side of
+    its peak, modulating a carrier of frequency f0, times a Hanning window
+    over the truncation.  The sinc's width gives a rectangular band of
+    rel_bandwidth * f0 around f0 (the paper quotes ~50 % at half maximum and
+    does not give the lobe count: 3 is this package's reading).  Zero outside
+    the window [0, 2 lobes / B]."""
+    B = rel_bandwidth * f0
+    Tw = 2.0 * lobes / B
+    tc = t - Tw / 2.0
+    win = np.where((t >= 0) & (t <= Tw), 0.5 * (1.0 - np.cos(2 * math.pi * t / Tw)), 0.0)
+    return amp * np.sinc(B * tc) * np.cos(2 * math.pi * f0 * tc) * win
+
+
 def dt_of(dx: float, courant: float) -> float:
     return courant * dx / C0
 
@@ -233,6 +249,36 @@ def gold_gap(n: Tuple[int, int, int] = (320, 320, 320), design: Tuple[int, int, 
                     tfsf_lo=(m, m, m), tfsf_hi=(nx - m, ny - m, nz - m),
                     objective=objective, gap_lo=gap_lo, gap_dims=gap_dims,
                     omega=2 * math.pi * C0 / 800e-9)
+
+
+def paper_broadband(material: str = "gold", steps: int = 18000, seed: int = 6) -> Workload:
+    """The paper's optimisation problem for the metals (Sec. "Technical details
+    of the optimization"): a 100 x 25 x 100 cell design region (200 x 50 x 200
+    nm at dx = 2 nm) with a 6 x 25 x 6 air gap at its centre, a z-polarised
+    plane wave travelling along +y (sinc x Hanning pulse on a 576.5 THz
+    carrier), 18000 steps at Courant 0.5 (dt = 3.34e-3 fs, 60.1 fs), the
+    time-domain objective (Eq. 2) over the whole run, gamma = 5e4, a 20-cell
+    CPML.  The paper does not give the vacuum margins: here 10 cells between
+    the design and the TF/SF box and 5 between the box and the CPML.  rho is
+    seeded U[0,1], smoothed, zero in the gap."""
+    mat = {"gold": GOLD_TABLE1, "aluminium": ALUMINIUM_TABLE1}[material]
+    design, npml, inner, outer = (100, 25, 100), 20, 10, 5
+    m = npml + outer
+    n = tuple(d + 2 * (m + inner) for d in design)
+    lo = tuple(m + inner for _ in range(3))
+    gap_dims = (6, 25, 6)
+    gap_lo = (lo[0] + (design[0] - 6) // 2, lo[1], lo[2] + (design[2] - 6) // 2)
+    rho = smooth3(uniform_density((design[2], design[1], design[0]), seed))
+    rho = _gap_zero(rho, lo, gap_lo, gap_dims)
+    dx, S = 2e-9, 0.5
+    t = np.arange(steps + 1) * dt_of(dx, S)
+    wave = sinc_hanning(t, 576.5e12, 0.5, 3)
+    w = Workload(f"paper_broadband_{material}", n, dx, S, npml, steps, _iso(VACUUM), _iso(mat), lo, rho, 5e4,
+                 "planewave", wave, pw_prop_axis=1, pw_sign=1, pw_pol_axis=2,
+                 tfsf_lo=(m, m, m), tfsf_hi=(n[0] - m, n[1] - m, n[2] - m),
+                 objective="time", gap_lo=gap_lo, gap_dims=gap_dims,
+                 omega=2 * math.pi * 576.5e12)
+    return w
 
 
 def gold_gap_320(steps: int = 6000) -> Workload:
