@@ -119,7 +119,9 @@ ccpr_status ccpr_set_design(ccpr_solver* s, const int lo[3], const int dims[3], 
 
 /* Point current source (host data): J_src [A/m^2] on the 'axis' edge of
  * 'cell', wave[n] being its value at t = (n+1/2) dt for n in [0,nsteps); zero
- * afterwards.  Replaces any previous source. */
+ * afterwards.  Replaces any previous source.  The cell must lie outside the x
+ * CPML layers (CCPR_ENOTSUP at the next run otherwise): source cells are
+ * finished in the same launch as the x-CPML pass of E. */
 ccpr_status ccpr_set_source_dipole(ccpr_solver* s, const int cell[3], int axis,
                                    const double* wave, int nsteps);
 
@@ -139,7 +141,9 @@ ccpr_status ccpr_set_source_planewave(ccpr_solver* s, int prop_axis, int sign, i
  *   CCPR_OBJ_TIME_E2: F = eps0/2 dx^3 dt sum_{n in [n_begin,n_end)} sum E^2
  *                     (Eq. 2, rectangle rule, air in the gap);
  *   CCPR_OBJ_DFT_E2:  F = sum |dt sum_{n=0..M} E^n exp(-j omega n dt)|^2.
- * n_end < 0 means "through the last step". */
+ * n_end < 0 means "through the last step".  The gap box must lie outside the
+ * x CPML layers (CCPR_ENOTSUP at the next run otherwise: its cells are the
+ * adjoint run's source cells). */
 ccpr_status ccpr_set_objective(ccpr_solver* s, int kind, const int lo[3], const int dims[3],
                                double omega, int n_begin, int n_end);
 
