@@ -40,7 +40,7 @@ def _autograd_grad(w, rho_dtype, scale=1.0):
     F = objective(rho, s, w.steps, w.design_lo, w.gamma)
     (scale * F).backward()
     g = rho.grad.detach().double().cpu().numpy()
-    Fv = float(F)
+    Fv = float(F.detach())
     s.close()
     return Fv, g
 
