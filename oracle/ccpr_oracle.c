@@ -67,11 +67,19 @@ struct or_sim {
     double* psiE[3][3];            /* [component][derivative axis]             */
     double* psiH[3][3];
     or_mat mat[2][3];
-    /* design */
-    int dlo[3], ddim[3], nd;
+    /* design: one density per design edge (Sec. "FDTD implementation and
+     * design export").  The edges of component c form the box
+     * [dlo, dlo + edim[c]); edge e of c is eoff[c] + its index in that box
+     * (x fastest).  A per-voxel design gives each component the voxel box
+     * and copies the voxel's density to its three edges; a per-edge design
+     * of N cells gives component c the extents N_l + 1 - delta(c,l). */
+    int dlo[3], ddim[3], nd;     /* cell box; nd = its cell count          */
+    int per_edge;
+    int edim[3][3];
+    size_t eoff[4];              /* eoff[3]: number of design edges        */
     double gamma;
-    double* rho;
-    cplx* J; /* [nd][3][2*OR_MAX_PAIRS] */
+    double* rho;                 /* [eoff[3]]                              */
+    cplx* J;                     /* [eoff[3]][2*OR_MAX_PAIRS]              */
     /* dipole */
     int dip_on, dip_cell[3], dip_axis, dip_nw;
     double* dip_wave;
@@ -197,20 +205,47 @@ int or_set_material(or_sim* s, int slot, int axis, double eps_inf, double sigma,
     return 0;
 }
 
-int or_set_design(or_sim* s, const int* lo, const int* dims, double gamma, const double* rho)
+static int set_design_boxes(or_sim* s, const int* lo, const int* dims, int per_edge, double gamma)
 {
-    for (int a = 0; a < 3; ++a)
-        if (lo[a] < 0 || dims[a] < 1 || lo[a] + dims[a] > s->n[a]) return -1;
+    for (int a = 0; a < 3; ++a) {
+        if (lo[a] < 0 || dims[a] < 1) return -1;
+        if (lo[a] + dims[a] + (per_edge ? 1 : 0) > s->n[a]) return -1;
+    }
     memcpy(s->dlo, lo, sizeof(s->dlo));
     memcpy(s->ddim, dims, sizeof(s->ddim));
     s->nd = dims[0] * dims[1] * dims[2];
+    s->per_edge = per_edge;
     s->gamma = gamma;
+    s->eoff[0] = 0;
+    for (int c = 0; c < 3; ++c) {
+        size_t n = 1;
+        for (int l = 0; l < 3; ++l) {
+            s->edim[c][l] = dims[l] + ((per_edge && l != c) ? 1 : 0);
+            n *= (size_t)s->edim[c][l];
+        }
+        s->eoff[c + 1] = s->eoff[c] + n;
+    }
     free(s->rho); free(s->J);
-    s->rho = malloc(s->nd * sizeof(double));
-    memcpy(s->rho, rho, s->nd * sizeof(double));
-    s->J = calloc((size_t)s->nd * 3 * 2 * OR_MAX_PAIRS, sizeof(cplx));
+    s->rho = malloc(s->eoff[3] * sizeof(double));
+    s->J = calloc(s->eoff[3] * 2 * OR_MAX_PAIRS, sizeof(cplx));
+    return (s->rho && s->J) ? 0 : -1;
+}
+
+int or_set_design(or_sim* s, const int* lo, const int* dims, double gamma, const double* rho)
+{
+    if (set_design_boxes(s, lo, dims, 0, gamma)) return -1;
+    for (int c = 0; c < 3; ++c) memcpy(s->rho + s->eoff[c], rho, (size_t)s->nd * sizeof(double));
     return 0;
 }
+
+int or_set_design_edges(or_sim* s, const int* lo, const int* dims, double gamma, const double* rho)
+{
+    if (set_design_boxes(s, lo, dims, 1, gamma)) return -1;
+    memcpy(s->rho, rho, s->eoff[3] * sizeof(double));
+    return 0;
+}
+
+long long or_design_outputs(const or_sim* s) { return s->per_edge ? (long long)s->eoff[3] : (long long)s->nd; }
 
 int or_set_dipole(or_sim* s, const int* cell, int axis, const double* wave, int nw)
 {
@@ -289,7 +324,7 @@ void or_reset(or_sim* s)
             if (s->psiE[c][d]) memset(s->psiE[c][d], 0, nc * sizeof(double));
             if (s->psiH[c][d]) memset(s->psiH[c][d], 0, nc * sizeof(double));
         }
-    if (s->J) memset(s->J, 0, (size_t)s->nd * 3 * 2 * OR_MAX_PAIRS * sizeof(cplx));
+    if (s->J) memset(s->J, 0, s->eoff[3] * 2 * OR_MAX_PAIRS * sizeof(cplx));
     if (s->pw_E) {
         memset(s->pw_E, 0, (s->pw_L + 1) * sizeof(double));
         memset(s->pw_H, 0, (s->pw_L + 1) * sizeof(double));
@@ -437,6 +472,15 @@ static int in_box(const int* lo, const int* dim, int i, int j, int k)
            k >= lo[2] && k < lo[2] + dim[2];
 }
 
+/* Design edge of component c at cell (i,j,k), or -1. */
+static long long design_edge(const or_sim* s, int c, int i, int j, int k)
+{
+    if (s->eoff[3] == 0 || !in_box(s->dlo, s->edim[c], i, j, k)) return -1;
+    const int* d = s->edim[c];
+    return (long long)s->eoff[c] +
+           ((long long)(k - s->dlo[2]) * d[1] + (j - s->dlo[1])) * d[0] + (i - s->dlo[0]);
+}
+
 /* H^{n+1/2} = H^{n-1/2} - (dt/mu0) curl E^n (supplement Eq. Maxwells2 c). */
 static void update_H(or_sim* s)
 {
@@ -476,8 +520,8 @@ static void update_H(or_sim* s)
 }
 
 /* E^{n+1} from Ampere's law with the CCPR currents (supplement Eq. Maxwells2
- * a, b).  If T is not NULL, T[v*3+axis] receives the gradient factor of each
- * design edge. */
+ * a, b).  If T is not NULL, T[e] receives the gradient factor of design
+ * edge e. */
 static void update_E(or_sim* s, double* T)
 {
     const double dx = s->dx;
@@ -528,12 +572,11 @@ static void update_E(or_sim* s, double* T)
                     edge_coef ec;
                     cplx* J = NULL;
                     double* Tp = NULL;
-                    if (s->nd > 0 && in_box(s->dlo, s->ddim, i, j, k)) {
-                        int v = ((k - s->dlo[2]) * s->ddim[1] + (j - s->dlo[1])) * s->ddim[0] +
-                                (i - s->dlo[0]);
-                        edge_coef_at(s, c, s->rho[v], s->gamma, &ec);
-                        J = &s->J[((size_t)v * 3 + c) * 2 * OR_MAX_PAIRS];
-                        if (T) Tp = &T[(size_t)v * 3 + c];
+                    const long long e = design_edge(s, c, i, j, k);
+                    if (e >= 0) {
+                        edge_coef_at(s, c, s->rho[e], s->gamma, &ec);
+                        J = &s->J[(size_t)e * 2 * OR_MAX_PAIRS];
+                        if (T) Tp = &T[e];
                     } else {
                         vacuum_coef(s, &ec);
                     }
@@ -573,25 +616,27 @@ static void record_gap(const or_sim* s, const int* lo, const int* dims, double* 
 }
 
 /* Forward run with gap recording, then the objective and its derivative
- * dF/dE^n at every gap edge.  Gradient factors: with T_hist the whole history
- * T^{n+1/2} is kept; with T_hat (and T_hist NULL) only its transform at omega,
- * T_hat[v*3+k] = sum_{n=0}^{M-1} T_k^{n+1/2}(v) exp(-j omega n dt). */
+ * dF/dE^n at every gap edge.  Gradient factors (one per design edge e): with
+ * T_hist the whole history T^{n+1/2} is kept; with T_hat (and T_hist NULL)
+ * only its transform at omega, T_hat[e] = sum_{n=0}^{M-1} T_e^{n+1/2}
+ * exp(-j omega n dt). */
 static int forward_and_objective(or_sim* s, int M, int kind, const int* glo, const int* gdim,
                                  double omega, int nb, int ne, double* T_hist, cplx* T_hat,
                                  double* F_out, double* hist, double* dFdE)
 {
     int ncell = gdim[0] * gdim[1] * gdim[2];
-    double* T_step = (!T_hist && T_hat) ? malloc((size_t)s->nd * 3 * sizeof(double)) : NULL;
-    if (T_hat) memset(T_hat, 0, (size_t)s->nd * 3 * sizeof(cplx));
+    const size_t nE = s->eoff[3];
+    double* T_step = (!T_hist && T_hat) ? malloc(nE * sizeof(double)) : NULL;
+    if (T_hat) memset(T_hat, 0, nE * sizeof(cplx));
     or_reset(s);
     record_gap(s, glo, gdim, hist);
     for (int n = 0; n < M; ++n) {
-        double* T = T_hist ? T_hist + (size_t)n * s->nd * 3 : T_step;
+        double* T = T_hist ? T_hist + (size_t)n * nE : T_step;
         step_once(s, T);
         record_gap(s, glo, gdim, hist + (size_t)(n + 1) * ncell * 3);
         if (T_hat) {
             cplx ph = cexp(-I * omega * n * s->dt);
-            for (size_t q = 0; q < (size_t)s->nd * 3; ++q) T_hat[q] += T[q] * ph;
+            for (size_t q = 0; q < nE; ++q) T_hat[q] += T[q] * ph;
         }
     }
     free(T_step);
@@ -681,55 +726,70 @@ static int adjoint_run(or_sim* s, int M, const int* gap_lo, const int* gap_dims,
     return 0;
 }
 
-/* adjoint E of the three edges of design voxel v */
-static void design_E(const or_sim* s, int v, double* e3)
+/* Field of design edge e (component c of its cell). */
+static double design_edge_E(const or_sim* s, size_t e)
 {
-    int i = v % s->ddim[0], j = (v / s->ddim[0]) % s->ddim[1], k = v / (s->ddim[0] * s->ddim[1]);
-    size_t id = idx3(s, s->dlo[0] + i, s->dlo[1] + j, s->dlo[2] + k);
-    for (int a = 0; a < 3; ++a) e3[a] = s->F[a][id];
+    int c = 0;
+    while (e >= s->eoff[c + 1]) ++c;
+    const int* d = s->edim[c];
+    const size_t q = e - s->eoff[c];
+    const int i = (int)(q % d[0]), j = (int)((q / d[0]) % d[1]), k = (int)(q / ((size_t)d[0] * d[1]));
+    return s->F[c][idx3(s, s->dlo[0] + i, s->dlo[1] + j, s->dlo[2] + k)];
+}
+
+/* Gradient read-out: per-edge designs return the edge values; per-voxel
+ * designs sum the three edges of each voxel (the voxel's density drives all
+ * three). */
+static void gradient_out(const or_sim* s, const double* ge, double* out)
+{
+    if (s->per_edge) {
+        memcpy(out, ge, s->eoff[3] * sizeof(double));
+        return;
+    }
+    for (int v = 0; v < s->nd; ++v) out[v] = ge[v] + ge[s->eoff[1] + v] + ge[s->eoff[2] + v];
 }
 
 typedef struct {
     int M;
     const double* T_hist;
-    double* grad;
+    double* grad;           /* per design edge */
 } exact_ctx;
 
 static void exact_visit(or_sim* s, int p, void* vctx)
 {
     exact_ctx* c = (exact_ctx*)vctx;
-    const double* T = c->T_hist + (size_t)(c->M - 1 - p) * s->nd * 3;
-    for (int v = 0; v < s->nd; ++v) {
-        double e3[3];
-        design_E(s, v, e3);
-        for (int a = 0; a < 3; ++a) c->grad[v] += e3[a] * T[(size_t)v * 3 + a];
-    }
+    const size_t nE = s->eoff[3];
+    const double* T = c->T_hist + (size_t)(c->M - 1 - p) * nE;
+    for (size_t e = 0; e < nE; ++e) c->grad[e] += design_edge_E(s, e) * T[e];
 }
 
 /* Time-exact discrete gradient.  Writing Et^m for the adjoint E after m
  * adjoint steps, the gradient (Eq. Gradient_FDTD with the index pairing of
- * the exact discrete adjoint) is
- *   dF/drho_v = sum_k sum_{n=0}^{M-1} Et_k^{M-n}(v) T_k^{n+1/2}(v),
- * where T is the per-edge factor recorded by edge_update. */
+ * the exact discrete adjoint) with respect to the density of design edge e is
+ *   dF/drho_e = sum_{n=0}^{M-1} Et_e^{M-n} T_e^{n+1/2},
+ * where T is the per-edge factor recorded by edge_update; a voxel's density
+ * collects the sum over its three edges. */
 int or_gradient(or_sim* s, int nsteps, int obj_kind, const int* gap_lo, const int* gap_dims,
                 double omega, int n_begin, int n_end, double* F_out, double* grad_out,
                 double* gap_hist_out)
 {
-    if (nsteps < 1 || s->nd < 1 || !gap_ok(s, gap_lo, gap_dims)) return -1;
-    const int M = nsteps, nd = s->nd;
+    if (nsteps < 1 || s->eoff[3] < 1 || !gap_ok(s, gap_lo, gap_dims)) return -1;
+    const int M = nsteps;
+    const size_t nE = s->eoff[3];
     int ncell = gap_dims[0] * gap_dims[1] * gap_dims[2];
     size_t ne = (size_t)(M + 1) * ncell * 3;
     double* hist = malloc(ne * sizeof(double));
     double* dFdE = malloc(ne * sizeof(double));
-    double* T_hist = malloc((size_t)M * nd * 3 * sizeof(double));
-    if (!hist || !dFdE || !T_hist) { free(hist); free(dFdE); free(T_hist); return -1; }
+    double* T_hist = malloc((size_t)M * nE * sizeof(double));
+    double* ge = calloc(nE, sizeof(double));
+    if (!hist || !dFdE || !T_hist || !ge) { free(hist); free(dFdE); free(T_hist); free(ge); return -1; }
     forward_and_objective(s, M, obj_kind, gap_lo, gap_dims, omega, n_begin, n_end, T_hist, NULL,
                           F_out, hist, dFdE);
     if (gap_hist_out) memcpy(gap_hist_out, hist, ne * sizeof(double));
-    for (int v = 0; v < nd; ++v) grad_out[v] = 0.0;
-    exact_ctx c = {M, T_hist, grad_out};
+    exact_ctx c = {M, T_hist, ge};
     int rc = adjoint_run(s, M, gap_lo, gap_dims, dFdE, exact_visit, &c);
-    free(hist); free(dFdE); free(T_hist);
+    if (rc == 0) gradient_out(s, ge, grad_out);
+    free(hist); free(dFdE); free(T_hist); free(ge);
     return rc;
 }
 
@@ -746,7 +806,7 @@ int or_dft_window(int nsteps, double omega, double dt)
 typedef struct {
     int m0;                 /* first adjoint field index of the window */
     double theta;           /* omega dt */
-    cplx* P;                /* [nd*3]: sum over the window of Et^m exp(-j theta m) */
+    cplx* P;                /* per design edge: sum over the window of Et^m exp(-j theta m) */
     double scc, sss, scs;   /* the window's normal matrix */
 } dft_ctx;
 
@@ -760,11 +820,7 @@ static void dft_visit(or_sim* s, int p, void* vctx)
     c->sss += sn * sn;
     c->scs += cs * sn;
     const cplx ph = cexp(-I * c->theta * m);
-    for (int v = 0; v < s->nd; ++v) {
-        double e3[3];
-        design_E(s, v, e3);
-        for (int a = 0; a < 3; ++a) c->P[(size_t)v * 3 + a] += e3[a] * ph;
-    }
+    for (size_t e = 0; e < s->eoff[3]; ++e) c->P[e] += design_edge_E(s, e) * ph;
 }
 
 /* Single-frequency (DFT-mode) gradient estimator for OR_OBJ_DFT.  The adjoint
@@ -772,8 +828,8 @@ static void dft_visit(or_sim* s, int p, void* vctx)
  * transient has died out the adjoint field is Et^m = Re{A exp(j theta m)},
  * theta = omega dt, with one complex amplitude A per design edge.  Put into
  * the time-exact sum above this gives
- *   dF/drho_v ~ sum_k Re{ A_k(v) exp(j theta M) T_hat_k(v) },
- *   T_hat_k(v) = sum_{n=0}^{M-1} T_k^{n+1/2}(v) exp(-j theta n),
+ *   dF/drho_e ~ Re{ A_e exp(j theta M) T_hat_e },
+ *   T_hat_e = sum_{n=0}^{M-1} T_e^{n+1/2} exp(-j theta n),
  * so the forward run keeps only T_hat and the adjoint run only a projection.
  * A is the least-squares fit of a cos(theta m) + b sin(theta m) (A = a - j b)
  * to Et^m over the window of the last L adjoint fields, m in [M-L+1, M], with
@@ -784,38 +840,39 @@ static void dft_visit(or_sim* s, int p, void* vctx)
 int or_gradient_dft(or_sim* s, int nsteps, const int* gap_lo, const int* gap_dims, double omega,
                     double* F_out, double* grad_out)
 {
-    if (nsteps < 2 || s->nd < 1 || !(omega > 0) || !gap_ok(s, gap_lo, gap_dims)) return -1;
-    const int M = nsteps, nd = s->nd;
+    if (nsteps < 2 || s->eoff[3] < 1 || !(omega > 0) || !gap_ok(s, gap_lo, gap_dims)) return -1;
+    const int M = nsteps;
+    const size_t nE = s->eoff[3];
     int ncell = gap_dims[0] * gap_dims[1] * gap_dims[2];
     size_t ne = (size_t)(M + 1) * ncell * 3;
     double* hist = malloc(ne * sizeof(double));
     double* dFdE = malloc(ne * sizeof(double));
-    cplx* T_hat = malloc((size_t)nd * 3 * sizeof(cplx));
-    cplx* P = calloc((size_t)nd * 3, sizeof(cplx));
-    if (!hist || !dFdE || !T_hat || !P) { free(hist); free(dFdE); free(T_hat); free(P); return -1; }
+    cplx* T_hat = malloc(nE * sizeof(cplx));
+    cplx* P = calloc(nE, sizeof(cplx));
+    double* ge = malloc(nE * sizeof(double));
+    if (!hist || !dFdE || !T_hat || !P || !ge) {
+        free(hist); free(dFdE); free(T_hat); free(P); free(ge);
+        return -1;
+    }
     forward_and_objective(s, M, OR_OBJ_DFT, gap_lo, gap_dims, omega, 0, -1, NULL, T_hat, F_out,
                           hist, dFdE);
     const int L = or_dft_window(M, omega, s->dt);
     dft_ctx c = {M - L + 1, omega * s->dt, P, 0.0, 0.0, 0.0};
     if (adjoint_run(s, M, gap_lo, gap_dims, dFdE, dft_visit, &c)) {
-        free(hist); free(dFdE); free(T_hat); free(P);
+        free(hist); free(dFdE); free(T_hat); free(P); free(ge);
         return -1;
     }
     /* [scc scs; scs sss] [a; b] = [sum Et cos; sum Et sin] = [Re P; -Im P] */
     const double det = c.scc * c.sss - c.scs * c.scs;
     const cplx W = cexp(I * omega * s->dt * M);
-    for (int v = 0; v < nd; ++v) {
-        double g = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            const cplx Pk = P[(size_t)v * 3 + k];
-            const double rc = creal(Pk), rs = -cimag(Pk);
-            const double a = (c.sss * rc - c.scs * rs) / det;
-            const double b = (c.scc * rs - c.scs * rc) / det;
-            g += creal((a - I * b) * W * T_hat[(size_t)v * 3 + k]);
-        }
-        grad_out[v] = g;
+    for (size_t e = 0; e < nE; ++e) {
+        const double rc = creal(P[e]), rs = -cimag(P[e]);
+        const double a = (c.sss * rc - c.scs * rs) / det;
+        const double b = (c.scc * rs - c.scs * rc) / det;
+        ge[e] = creal((a - I * b) * W * T_hat[e]);
     }
-    free(hist); free(dFdE); free(T_hat); free(P);
+    gradient_out(s, ge, grad_out);
+    free(hist); free(dFdE); free(T_hat); free(P); free(ge);
     return 0;
 }
 

@@ -53,6 +53,19 @@ int or_set_material(or_sim* s, int slot, int axis, double eps_inf, double sigma,
 int or_set_design(or_sim* s, const int* lo, const int* dims, double gamma,
                   const double* rho);
 
+/* Design of dims = N cells at lo with one density per E edge (Sec. "FDTD
+ * implementation and design export"): component c has the edges of the box
+ * [lo, lo + N + 1 - e_c) (N_l + 1 - delta(c,l) along axis l), so the box's
+ * boundary edges are design variables too.  rho holds the x edges, then the
+ * y edges, then the z edges, each x fastest.  The gradient then has one
+ * value per edge in the same order (or_design_outputs values). */
+int or_set_design_edges(or_sim* s, const int* lo, const int* dims, double gamma,
+                        const double* rho);
+
+/* Number of gradient values: voxels (or_set_design) or edges
+ * (or_set_design_edges). */
+long long or_design_outputs(const or_sim* s);
+
 /* Point current J_src [A/m^2] on the 'axis' edge of 'cell'; wave[n] is the
  * value at t=(n+1/2)dt for n in [0,nw). */
 int or_set_dipole(or_sim* s, const int* cell, int axis, const double* wave, int nw);

@@ -39,6 +39,9 @@ def _lib():
         lib.or_dt.argtypes = [_p]
         lib.or_set_material.argtypes = [_p, _i, _i, _d, _d, _i, _dp, _dp]
         lib.or_set_design.argtypes = [_p, _ip, _ip, _d, _dp]
+        lib.or_set_design_edges.argtypes = [_p, _ip, _ip, _d, _dp]
+        lib.or_design_outputs.argtypes = [_p]
+        lib.or_design_outputs.restype = C.c_longlong
         lib.or_set_dipole.argtypes = [_p, _ip, _i, _dp, _i]
         lib.or_set_planewave.argtypes = [_p, _i, _i, _i, _ip, _ip, _dp, _i]
         lib.or_set_box_source.argtypes = [_p, _ip, _ip, _dp, _i]
@@ -71,6 +74,13 @@ def _dv(a):
     return a, a.ctypes.data_as(_dp)
 
 
+def edge_shape(dims, c):
+    """(z, y, x) shape of the component-c design edges of a design of
+    dims = (Nx, Ny, Nz) cells: N_l + 1 along the two axes other than c."""
+    e = [dims[l] + (0 if l == c else 1) for l in range(3)]
+    return (e[2], e[1], e[0])
+
+
 def num_threads() -> int:
     return _lib().or_num_threads()
 
@@ -88,6 +98,7 @@ class OracleSim:
         self.dt = _lib().or_dt(self._h)
         self.dx = dx
         self.design_dims = None
+        self.per_edge = False
 
     def close(self):
         if self._h:
@@ -124,7 +135,35 @@ class OracleSim:
         r, rp = _dv(rho.ravel())
         self._rho_keep = r
         self.design_dims = dims
+        self.per_edge = False
         self._chk(_lib().or_set_design(self._h, _iv(lo), _iv(dims), gamma, rp), "design")
+
+    def set_design_edges(self, lo, dims, rho_edges, gamma=0.0):
+        """One density per E edge of a design of dims = (Nx, Ny, Nz) cells:
+        rho_edges = (rho_x, rho_y, rho_z), rho_c shaped edge_shape(dims, c)."""
+        parts = []
+        for c in range(3):
+            r = np.asarray(rho_edges[c], dtype=np.float64)
+            assert r.shape == edge_shape(dims, c), (r.shape, edge_shape(dims, c))
+            parts.append(r.ravel())
+        r, rp = _dv(np.concatenate(parts))
+        self._rho_keep = r
+        self.design_dims = tuple(dims)
+        self.per_edge = True
+        self._chk(_lib().or_set_design_edges(self._h, _iv(lo), _iv(dims), gamma, rp), "edge design")
+
+    def _grad_shape(self, g):
+        """Flat gradient -> (dz, dy, dx) per voxel, or the three per-edge arrays."""
+        d = self.design_dims
+        if not self.per_edge:
+            return g.reshape(d[2], d[1], d[0])
+        out, o = [], 0
+        for c in range(3):
+            shp = edge_shape(d, c)
+            n = int(np.prod(shp))
+            out.append(g[o:o + n].reshape(shp))
+            o += n
+        return tuple(out)
 
     def set_dipole(self, cell, axis, wave):
         w, wp = _dv(wave)
@@ -171,7 +210,7 @@ class OracleSim:
                  want_hist=False):
         if n_end is None:
             n_end = nsteps + 1
-        nd = int(np.prod(self.design_dims))
+        nd = int(_lib().or_design_outputs(self._h))
         F = C.c_double(0.0)
         g = np.zeros(nd, dtype=np.float64)
         ncell = int(np.prod(gap_dims))
@@ -180,19 +219,17 @@ class OracleSim:
         self._chk(_lib().or_gradient(self._h, nsteps, kind, _iv(gap_lo), _iv(gap_dims), omega,
                                      n_begin, n_end, C.byref(F), g.ctypes.data_as(_dp), hp),
                   "gradient")
-        d = self.design_dims
-        g = g.reshape(d[2], d[1], d[0])
+        g = self._grad_shape(g)
         return (F.value, g, hist) if want_hist else (F.value, g)
 
     def gradient_dft(self, nsteps, gap_lo, gap_dims, omega):
         """DFT-mode gradient estimator of the DFT objective (or_gradient_dft)."""
-        nd = int(np.prod(self.design_dims))
+        nd = int(_lib().or_design_outputs(self._h))
         F = C.c_double(0.0)
         g = np.zeros(nd, dtype=np.float64)
         self._chk(_lib().or_gradient_dft(self._h, nsteps, _iv(gap_lo), _iv(gap_dims), omega,
                                          C.byref(F), g.ctypes.data_as(_dp)), "DFT-mode gradient")
-        d = self.design_dims
-        return F.value, g.reshape(d[2], d[1], d[0])
+        return F.value, self._grad_shape(g)
 
     def objective(self, nsteps, kind, gap_lo, gap_dims, omega=0.0, n_begin=0, n_end=None):
         if n_end is None:

@@ -169,6 +169,10 @@ class Workload:
     pml_kappa_max: float = 1.0
     pml_alpha_max: float = 0.05
     pml_sigma_scale: float = 1.0
+    # per-edge design (one density per E edge, Sec. "FDTD implementation and
+    # design export"): (rho_x, rho_y, rho_z), rho_c shaped edge_shape(N, c)
+    # for a design of N cells; None = one density per voxel (rho)
+    rho_edges: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
 
     @property
     def dt(self) -> float:
@@ -180,6 +184,9 @@ class Workload:
 
     @property
     def design_dims(self) -> Tuple[int, int, int]:
+        if self.rho_edges is not None:
+            z = self.rho_edges[2].shape  # (Nz, Ny + 1, Nx + 1)
+            return (z[2] - 1, z[1] - 1, z[0])
         return (self.rho.shape[2], self.rho.shape[1], self.rho.shape[0])
 
     @property
@@ -188,6 +195,32 @@ class Workload:
 
     def max_pairs(self) -> int:
         return max(self.mat1[a].npairs + self.mat2[a].npairs for a in range(3))
+
+
+def edge_shape(dims: Tuple[int, int, int], c: int) -> Tuple[int, int, int]:
+    """(z, y, x) shape of the component-c edges of a per-edge design of
+    dims = (Nx, Ny, Nz) cells: N_l + 1 along the two axes other than c."""
+    e = [dims[l] + (0 if l == c else 1) for l in range(3)]
+    return (e[2], e[1], e[0])
+
+
+def random_edge_densities(dims: Tuple[int, int, int], seed: int):
+    """Per-edge densities ~ U[0,1) (FP64 draws cast to FP32), x, y, z edges."""
+    rng = np.random.default_rng(seed)
+    return tuple(rng.random(edge_shape(dims, c)).astype(np.float32) for c in range(3))
+
+
+def voxel_edge_densities(rho: np.ndarray, fill: float = 0.0):
+    """Per-edge densities equal to a per-voxel design on the edges the voxels
+    own (edge (i,j,k) of each component belongs to voxel (i,j,k)); the extra
+    edges on the far faces of the box get 'fill'."""
+    nz, ny, nx = rho.shape
+    out = []
+    for c in range(3):
+        e = np.full(edge_shape((nx, ny, nz), c), fill, dtype=np.float32)
+        e[:nz, :ny, :nx] = rho
+        out.append(e)
+    return tuple(out)
 
 
 def _iso(m: CCPRMaterial):

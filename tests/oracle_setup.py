@@ -14,7 +14,11 @@ def oracle_from_workload(w: Workload, with_source: bool = True) -> OracleSim:
     for ax in range(3):
         for slot, m in ((1, w.mat1[ax]), (2, w.mat2[ax])):
             s.set_material(slot, ax, m.eps_inf, m.sigma, m.a, m.c)
-    s.set_design(w.design_lo, w.rho.astype(np.float64), w.gamma)
+    if w.rho_edges is not None:
+        s.set_design_edges(w.design_lo, w.design_dims, [r.astype(np.float64) for r in w.rho_edges],
+                           w.gamma)
+    else:
+        s.set_design(w.design_lo, w.rho.astype(np.float64), w.gamma)
     if with_source:
         if w.source == "dipole":
             s.set_dipole(w.dipole_cell, w.dipole_axis, w.wave)

@@ -388,3 +388,115 @@ def test_p13_dft_window_whole_periods():
     assert OracleSim.dft_window(1099, w, dt) == 500
     assert OracleSim.dft_window(1250, w, dt) == 600
     assert OracleSim.dft_window(150, w, dt) == 75   # under one period: half the run
+
+
+# ------------------------------------------------ per-edge design variables
+def _edge_fd_check(w, kind, edges, h=1e-4):
+    """Adjoint gradient of a per-edge design against central differences at
+    the given (component, z, y, x) edges."""
+    s = oracle_from_workload(w)
+    F, g = s.gradient(w.steps, kind, w.gap_lo, w.gap_dims, w.omega, w.window[0], w.window_end)
+    base = [r.astype(np.float64) for r in w.rho_edges]
+    fd = []
+    for (c, z, y, x) in edges:
+        vals = []
+        for sgn in (+1, -1):
+            r = [b.copy() for b in base]
+            r[c][z, y, x] += sgn * h
+            s2 = oracle_from_workload(w)
+            s2.set_design_edges(w.design_lo, w.design_dims, r, w.gamma)
+            vals.append(s2.objective(w.steps, kind, w.gap_lo, w.gap_dims, w.omega, w.window[0],
+                                     w.window_end))
+        fd.append((vals[0] - vals[1]) / (2 * h))
+    return F, np.array([g[c][z, y, x] for (c, z, y, x) in edges]), np.array(fd)
+
+
+@pytest.mark.parametrize("objective", ["dft", "time"])
+def test_p8_edge_gradient_matches_central_fd_pec(objective):
+    """Brute force for one density per E edge (Sec. "FDTD implementation and
+    design export"): the adjoint gradient equals central differences, also on
+    the extra edges of the box's far faces (N_l + 1 along the transverse
+    axes), which a per-voxel layout does not have."""
+    w = _small_pec(objective)
+    dims = w.design_dims
+    w.rho_edges = I.random_edge_densities(dims, seed=21)
+    for r in w.rho_edges:   # the gap cells stay air
+        r[2:4, 2:4, 2:4] = 0.0
+    nx, ny, nz = dims
+    edges = [(0, nz, ny, 1), (0, 0, ny, 3), (0, nz, 2, 4),      # x edges on the far y / z faces
+             (1, nz, 3, nx), (1, 2, 0, nx),                      # y edges on the far x / z faces
+             (2, 1, ny, nx), (2, 4, ny, 0),                      # z edges on the far x / y faces
+             (0, 1, 1, 1), (1, 3, 2, 2), (2, 2, 4, 3)]           # interior edges
+    F, ad, fd = _edge_fd_check(w, OBJ_DFT if objective == "dft" else OBJ_TIME, edges)
+    assert F > 0
+    err = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
+    assert err < 1e-6, (err, ad, fd)
+
+
+def test_edge_design_reduces_to_voxel_design():
+    """Per-edge densities equal to a per-voxel design on the edges each voxel
+    owns, and 0 on the far-face edges with a vacuum rho=0 material, give the
+    same fields: the objective agrees and each voxel's gradient is the sum of
+    its three edges' gradients (the voxel density drives all three)."""
+    w = _small_pec("dft")
+    w.mat1 = (I.CCPRMaterial(1.0),) * 3
+    s = oracle_from_workload(w)
+    F_v, g_v = s.gradient(w.steps, OBJ_DFT, w.gap_lo, w.gap_dims, w.omega)
+    w.rho_edges = I.voxel_edge_densities(w.rho, fill=0.0)
+    s = oracle_from_workload(w)
+    F_e, g_e = s.gradient(w.steps, OBJ_DFT, w.gap_lo, w.gap_dims, w.omega)
+    nz, ny, nx = w.rho.shape
+    summed = sum(g[:nz, :ny, :nx] for g in g_e)
+    assert F_e == pytest.approx(F_v, rel=1e-13)
+    assert np.max(np.abs(summed - g_v)) <= 1e-12 * np.max(np.abs(g_v))
+
+
+# --------------------------------------------------------------------- P10
+def _diag_symmetric_case(per_edge, objective):
+    """Problem invariant under the mirror x <-> y (the plane x = y): square
+    grid and CPML, design and gap boxes on the diagonal, identical x and y
+    materials (z differs), a z dipole on the diagonal.  The mirror maps the
+    Yee lattice onto itself, E_x edges onto E_y edges and E_z onto E_z."""
+    w = I.drude_dipole_32(steps=150, n=16, npml=3, gamma=5e4)
+    w.shape = (16, 16, 14)
+    diel = I.lorentz(2.0, 1.2, 2 * math.pi * C0 / 250e-9, 2e14)
+    w.mat1 = (diel, diel, diel)
+    w.mat2 = (I.GOLD_TABLE1, I.GOLD_TABLE1, I.ALUMINIUM_TABLE1)
+    w.design_lo = (5, 5, 4)
+    dims = (6, 6, 5)
+    rng = np.random.default_rng(31)
+    a = rng.random((dims[2], dims[1], dims[0]))
+    w.rho = (0.5 * (a + a.transpose(0, 2, 1))).astype(np.float32)
+    w.gap_lo, w.gap_dims = (7, 7, 5), (2, 2, 2)
+    w.dipole_cell, w.dipole_axis = (3, 3, 6), 2
+    if per_edge:
+        ex, _, ez = I.random_edge_densities(dims, seed=32)
+        ey = np.ascontiguousarray(ex.transpose(0, 2, 1))
+        ez = (0.5 * (ez + ez.transpose(0, 2, 1))).astype(np.float32)
+        w.rho_edges = (ex, ey, ez)
+    w.objective = objective
+    if objective == "time":
+        w.window = (10, 140)
+    return w
+
+
+@pytest.mark.parametrize("per_edge", [False, True])
+@pytest.mark.parametrize("objective", ["dft", "time"])
+def test_p10_mirror_symmetric_problem_has_mirror_symmetric_gradient(per_edge, objective):
+    """Invariant: with a design, sources, gap and materials symmetric under
+    x <-> y, the objective is symmetric, so its gradient is too: per voxel
+    g(k, j, i) = g(k, i, j); per edge g_x(k, j, i) = g_y(k, i, j) and g_z
+    symmetric.  An index or sign slip on one transverse axis (a curl term, a
+    CPML coefficient, an edge box extent) breaks it."""
+    w = _diag_symmetric_case(per_edge, objective)
+    s = oracle_from_workload(w)
+    kind = OBJ_DFT if objective == "dft" else OBJ_TIME
+    F, g = s.gradient(w.steps, kind, w.gap_lo, w.gap_dims, w.omega, w.window[0], w.window_end)
+    assert F > 0
+    if per_edge:
+        gx, gy, gz = g
+        scale = max(np.max(np.abs(x)) for x in g)
+        assert np.max(np.abs(gx - gy.transpose(0, 2, 1))) <= 1e-10 * scale
+        assert np.max(np.abs(gz - gz.transpose(0, 2, 1))) <= 1e-10 * scale
+    else:
+        assert np.max(np.abs(g - g.transpose(0, 2, 1))) <= 1e-10 * np.max(np.abs(g))
