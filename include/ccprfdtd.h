@@ -117,6 +117,22 @@ ccpr_status ccpr_set_material(ccpr_solver* s, int slot, int axis, double eps_inf
 ccpr_status ccpr_set_design(ccpr_solver* s, const int lo[3], const int dims[3], double gamma,
                             const float* rho, int mem);
 
+/* Design of dims = (Nx, Ny, Nz) cells at lo with one density per E edge
+ * (Sec. "FDTD implementation and design export": the density rho_{k,n} sits
+ * at each E_k position, N~_k = prod_l (N_l + 1 - delta_kl) of them, so the
+ * edges on the box's far faces are design variables too).  Component k's
+ * edges are those of cells [lo, lo + N + 1 - e_k) (e_k the unit vector of
+ * axis k); rho holds the x edges, then the y edges, then the z edges, each
+ * block x fastest in its own extents (N~_x + N~_y + N~_z floats).  Each edge's
+ * density sets its own material (Eqs. eps_mixed, sigma_mixed, Poles_mixed);
+ * the far-face edges along their own axis (E_k at index lo_k + N_k) are not
+ * design edges and stay vacuum.  The cells [lo, lo + N + 1) must lie inside
+ * the grid, off the walls and outside the CPML.  Checks, memory kinds and
+ * ownership as ccpr_set_design.  ccpr_gradient then returns one value per
+ * edge in the same order and layout. */
+ccpr_status ccpr_set_design_edges(ccpr_solver* s, const int lo[3], const int dims[3], double gamma,
+                                  const float* rho, int mem);
+
 /* Point current source (host data): J_src [A/m^2] on the 'axis' edge of
  * 'cell', wave[n] being its value at t = (n+1/2) dt for n in [0,nsteps); zero
  * afterwards.  Replaces any previous source.  The cell must lie outside the x
@@ -205,13 +221,16 @@ ccpr_status ccpr_adjoint(ccpr_solver* s);
  * quantity of the incident field gives the averaged enhancement spectrum.
  * Host arrays; synchronises.  CCPR_ESTATE before ccpr_forward; CCPR_EINVAL
  * for more frequencies than the workspace's staging area holds (one per 16
- * bytes of max(4 cells, 8 design voxels)). */
+ * bytes of max(4 cells, 8 density values)). */
 ccpr_status ccpr_gap_spectrum(ccpr_solver* s, const double* omega, int nf, double* mean_E2);
 
 /* dF/drho per design voxel (FP64: in SI units the objective of a weak source
  * is far below the FP32 range), dims of the design box, x fastest, written to
- * host memory (synchronises) or device memory (stream-ordered).  Eq.
- * Gradient_FDTD in the exact discrete pairing:
+ * host memory (synchronises) or device memory (stream-ordered); after
+ * ccpr_set_design_edges, one value per design edge in the layout of its
+ * densities.  Eq. Gradient_FDTD in the exact discrete pairing, per edge e
+ *   dF/drho_e = sum_{n=0}^{M-1} Et_e^{M-n} T_e^{n+1/2}
+ * and per voxel the sum over its three edges:
  *   dF/drho_v = sum_k sum_{n=0}^{M-1} Et_k^{M-n}(v) T_k^{n+1/2}(v),
  *   T = eps0 deps_k (E^{n+1}-E^n) + dsig_k,eff dt (E^{n+1}+E^n)/2
  *       + dt sum_p dkappa_p Re{J_p^{n+1}+J_p^n},

@@ -62,17 +62,30 @@ struct AxisMat {
     int jofs;           // first flat pair index of this axis in the J arrays
 };
 
+// Per-edge design (one density per E edge): the kernels run over the box of
+// N + 1 cells per axis that holds every design edge of an N-cell design, and
+// component c has design edges on the sub-box of extents N_l + 1 - delta(c,l)
+// (its far face along its own axis has none: those edges are vacuum).
+// Densities and gradients are held per component, x edges then y then z, each
+// x fastest in its own sub-box.
+struct EdgeMap {
+    int on;                     // 1: per-edge design; 0: one density per voxel
+    int ebox[3][3];             // [component][axis] extents of the component's edges
+    long long eoff[3];          // first density / gradient index of each component
+};
+
 // Step data the kernel needs only inside rare branches (design voxels, CPML
 // layers, sources, TF/SF faces, the gap monitor, the gradient history).  It
 // lives in device memory (one block per state), so the hot loop keeps its
 // scalar registers for the field bases.
 struct StepCold {
-    // design box
+    // design box (per-edge designs: the box of N + 1 cells per axis)
     int dlo[3], ddim[3];
     long long nd;
-    const float* rho;
+    const float* rho;           // per voxel [nd], or per edge (see EdgeMap)
     float* J;                   // [(2*q + {0:re,1:im}) * nd + v]
     AxisMat mat[3];
+    EdgeMap em;
 
     // CPML: per axis, (b, a, 1/kappa, 0) at integer (E) and half-integer (H)
     // positions; psi memories per derivative axis, two components each
@@ -109,7 +122,7 @@ struct StepCold {
     float* T;                   // time-exact mode: gradient history [slot][3][nd];
                                 // DFT mode: [12][nd], the forward transform of T
                                 // (re, im of x, y, z) then the adjoint projection
-    double* grad;               // adjoint: per-voxel accumulator
+    double* grad;               // adjoint: accumulator per voxel, or per edge (EdgeMap)
 };
 
 // Row classes (one word per (j,k), per state) and lane classes (one word per
@@ -172,8 +185,8 @@ __host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, in
 // Launchers (ccpr_kernels.hip)
 // fused grid step over the tiles of a.tiles (pml: the CPML variant)
 int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream);
-// aux kernel over the nd design voxels
-int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, void* stream);
+// aux kernel over the nd cells of the design box (edge: per-edge design)
+int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, bool edge, void* stream);
 // before a step: x-CPML and TF/SF corrections of H^{n-1/2} (nxs x-layer cells,
 // ntf TF/SF H words)
 int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* stream);
@@ -194,8 +207,8 @@ int ccpr_launch_extract(float* dst, const float* src, int comp, int nx, int ny, 
 // DFT-mode gradient: grad[v] = sum_k Re{A_k W T_hat_k} with A_k from the
 // adjoint projection P_k and the inverse window normal matrix (i00, i01, i11),
 // W = (wc, ws)
-int ccpr_launch_dft_grad(double* grad, const float* acc, long long nd, double i00, double i01, double i11,
-                         double wc, double ws, void* stream);
+int ccpr_launch_dft_grad(double* grad, const float* acc, long long nd, const int ddim[3], const EdgeMap& em,
+                         double i00, double i01, double i11, double wc, double ws, void* stream);
 // spectrum of the recorded gap field at nf angular frequencies (device
 // arrays omega[nf], out[nf])
 int ccpr_launch_gap_spectrum(const float* gap, int M, int ne, double dt, const double* omega, int nf, double scale,

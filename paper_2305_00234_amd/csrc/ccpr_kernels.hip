@@ -119,16 +119,17 @@ __device__ __forceinline__ void st_stream(float* p, float v)
     else *p = v;
 }
 
-// Pole currents of component C at voxel v: load / store (pairs p < np).
+// Pole currents of component C at voxel v: load / store (pairs p < np;
+// on = false: the edge has no currents, all zero).
 template <int C, int PMAX>
-__device__ __forceinline__ void j_load(const StepCold& c, long long v, float* jr, float* ji)
+__device__ __forceinline__ void j_load(const StepCold& c, long long v, float* jr, float* ji, bool on = true)
 {
     const AxisMat& m = c.mat[C];
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
         jr[p] = 0.f;
         ji[p] = 0.f;
-        if (p < m.np) {
+        if (on && p < m.np) {
             const long long q = m.jofs + p;
             jr[p] = c.J[(2 * q) * c.nd + v];
             ji[p] = c.J[(2 * q + 1) * c.nd + v];
@@ -470,7 +471,28 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
 // these cells is written over the fused kernel's vacuum value.
 // Design voxels, one thread per voxel in box order (x fastest).  NT:
 // nontemporal stores of the currents, fields and history (large states).
-template <int PMAX, bool NT, bool DFT>
+// E update of an edge of the kernel box that is not a design edge (the far
+// face of a per-edge design along the edge's own axis): vacuum, E += drive.
+__device__ __forceinline__ float e_vac(float E, float drive, const double* sh, double* shn)
+{
+    if (sh) {
+        *shn = *sh + (double)drive;
+        return (float)*shn;
+    }
+    return E + drive;
+}
+
+// Density / gradient index of component C at box cell (xi, yi, zi) of a
+// per-edge design, or -1 where C has no design edge.
+template <int C>
+__device__ __forceinline__ long long edge_index(const EdgeMap& m, int xi, int yi, int zi)
+{
+    const int* b = m.ebox[C];
+    if (xi >= b[0] || yi >= b[1] || zi >= b[2]) return -1;
+    return m.eoff[C] + ((long long)zi * b[1] + yi) * b[0] + xi;
+}
+
+template <int PMAX, bool NT, bool DFT, bool EDGE>
 __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
 {
     const StepCold& c = *a.cold;
@@ -487,21 +509,45 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
     const unsigned o = (((unsigned)(kk + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
     // every load first (the current stores alias the later loads otherwise)
     constexpr int PN = PMAX > 0 ? PMAX : 1;
+    // design edges of this cell: per voxel all three share the voxel's
+    // density and gradient; per edge each has its own index (-1: not a
+    // design edge)
+    long long gx = v, gy = v, gz = v;
+    if constexpr (EDGE) {
+        const int xi = i - c.dlo[0], yi = j - c.dlo[1], zi = kk - c.dlo[2];
+        gx = edge_index<0>(c.em, xi, yi, zi);
+        gy = edge_index<1>(c.em, xi, yi, zi);
+        gz = edge_index<2>(c.em, xi, yi, zi);
+    }
+    const bool onx = !EDGE || gx >= 0, ony = !EDGE || gy >= 0, onz = !EDGE || gz >= 0;
     float jrx[PN], jix[PN], jry[PN], jiy[PN], jrz[PN], jiz[PN];
-    j_load<0, PMAX>(c, v, jrx, jix);
-    j_load<1, PMAX>(c, v, jry, jiy);
-    j_load<2, PMAX>(c, v, jrz, jiz);
+    j_load<0, PMAX>(c, v, jrx, jix, onx);
+    j_load<1, PMAX>(c, v, jry, jiy, ony);
+    j_load<2, PMAX>(c, v, jrz, jiz, onz);
     const float e0x = ldf(a.Ei, o), e0y = ldf(a.Ei, o + cs), e0z = ldf(a.Ei, o + 2 * cs);
     float dx_ = a.drive[v], dy_ = a.drive[c.nd + v], dz_ = a.drive[2 * c.nd + v];
-    const float rho = c.rho[v];
+    float rhox, rhoy, rhoz;
+    if constexpr (EDGE) {
+        rhox = onx ? c.rho[gx] : 0.f;
+        rhoy = ony ? c.rho[gy] : 0.f;
+        rhoz = onz ? c.rho[gz] : 0.f;
+    } else {
+        rhox = rhoy = rhoz = c.rho[v];
+    }
     float Tox = 0.f, Toy = 0.f, Toz = 0.f;
-    double g0 = 0.0;
+    double g0 = 0.0, g0y = 0.0, g0z = 0.0;
     float* Tslot = c.T + (long long)a.tslot * 3 * c.nd;
     if (a.mode & CCPR_MODE_CORREL) {
         Tox = Tslot[v];
         Toy = Tslot[c.nd + v];
         Toz = Tslot[2 * c.nd + v];
-        g0 = c.grad[v];
+        if constexpr (EDGE) {
+            if (onx) g0 = c.grad[gx];
+            if (ony) g0y = c.grad[gy];
+            if (onz) g0z = c.grad[gz];
+        } else {
+            g0 = c.grad[v];
+        }
     }
     // DFT mode (DFT: the launch carries CCPR_MODE_DFT_T or _P): running
     // transforms (re, im per component) of T (forward) or of the adjoint E
@@ -523,19 +569,23 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
         }
         if (c.ssh) sh = c.ssh + (long long)ci * 3;
     }
-    float Tx, Ty, Tz;
+    float Tx = 0.f, Ty = 0.f, Tz = 0.f;
     double shn[3];
-    const float nxv = e_disp<0, PMAX>(c, e0x, dx_, rho, jrx, jix, &Tx, sh, &shn[0]);
-    const float nyv = e_disp<1, PMAX>(c, e0y, dy_, rho, jry, jiy, &Ty, sh ? sh + 1 : nullptr, &shn[1]);
-    const float nzv = e_disp<2, PMAX>(c, e0z, dz_, rho, jrz, jiz, &Tz, sh ? sh + 2 : nullptr, &shn[2]);
+    float nxv, nyv, nzv;
+    if (!EDGE || onx) nxv = e_disp<0, PMAX>(c, e0x, dx_, rhox, jrx, jix, &Tx, sh, &shn[0]);
+    else nxv = e_vac(e0x, dx_, sh, &shn[0]);
+    if (!EDGE || ony) nyv = e_disp<1, PMAX>(c, e0y, dy_, rhoy, jry, jiy, &Ty, sh ? sh + 1 : nullptr, &shn[1]);
+    else nyv = e_vac(e0y, dy_, sh ? sh + 1 : nullptr, &shn[1]);
+    if (!EDGE || onz) nzv = e_disp<2, PMAX>(c, e0z, dz_, rhoz, jrz, jiz, &Tz, sh ? sh + 2 : nullptr, &shn[2]);
+    else nzv = e_vac(e0z, dz_, sh ? sh + 2 : nullptr, &shn[2]);
     if (sh) {
         sh[0] = shn[0];
         sh[1] = shn[1];
         sh[2] = shn[2];
     }
-    j_store<0, PMAX, NT>(c, v, jrx, jix);
-    j_store<1, PMAX, NT>(c, v, jry, jiy);
-    j_store<2, PMAX, NT>(c, v, jrz, jiz);
+    if (!EDGE || onx) j_store<0, PMAX, NT>(c, v, jrx, jix);
+    if (!EDGE || ony) j_store<1, PMAX, NT>(c, v, jry, jiy);
+    if (!EDGE || onz) j_store<2, PMAX, NT>(c, v, jrz, jiz);
     stf_nt<NT>(a.Eo, o, nxv);
     stf_nt<NT>(a.Eo, o + cs, nyv);
     stf_nt<NT>(a.Eo, o + 2 * cs, nzv);
@@ -544,8 +594,15 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
         st_stream<NT>(&Tslot[c.nd + v], Ty);
         st_stream<NT>(&Tslot[2 * c.nd + v], Tz);
     }
-    if (a.mode & CCPR_MODE_CORREL)
-        c.grad[v] = g0 + ((double)nxv * Tox + (double)nyv * Toy + (double)nzv * Toz);
+    if (a.mode & CCPR_MODE_CORREL) {
+        if constexpr (EDGE) {
+            if (onx) c.grad[gx] = g0 + (double)nxv * Tox;
+            if (ony) c.grad[gy] = g0y + (double)nyv * Toy;
+            if (onz) c.grad[gz] = g0z + (double)nzv * Toz;
+        } else {
+            c.grad[v] = g0 + ((double)nxv * Tox + (double)nyv * Toy + (double)nzv * Toz);
+        }
+    }
     if constexpr (DFT) {
         // x exp(-j phase) = x (cos - j sin)
         const bool fwd = (a.mode & CCPR_MODE_DFT_T) != 0;
@@ -795,12 +852,14 @@ __global__ __launch_bounds__(256) void ccpr_post_fused_kernel(const StepArgs a, 
 // adjoint amplitude A_k = a - j b solves the window's least-squares normal
 // equations [a; b] = inv [Re P_k; -Im P_k] (inverse i00 i01; i01 i11), and
 // grad = sum_k Re{A_k W T_hat_k}, all in FP64.
-__global__ void dft_grad_kernel(double* grad, const float* acc, long long nd, double i00, double i01, double i11,
-                                double wc, double ws)
+// per voxel: grad[v] = sum over the three edges; per edge (em.on): each
+// design edge's own term at its index
+__global__ void dft_grad_kernel(double* grad, const float* acc, long long nd, int dx, int dy, const EdgeMap em,
+                                double i00, double i01, double i11, double wc, double ws)
 {
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nd;
          v += (long long)gridDim.x * blockDim.x) {
-        double g = 0.0;
+        double gk[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double tr = acc[(2 * k) * nd + v], ti = acc[(2 * k + 1) * nd + v];
@@ -808,9 +867,18 @@ __global__ void dft_grad_kernel(double* grad, const float* acc, long long nd, do
             const double ar = i00 * rc + i01 * rs, ab = i01 * rc + i11 * rs;  // A = ar - j ab
             // A W = (ar wc + ab ws) + j (ar ws - ab wc)
             const double awr = ar * wc + ab * ws, awi = ar * ws - ab * wc;
-            g += awr * tr - awi * ti;
+            gk[k] = awr * tr - awi * ti;
         }
-        grad[v] = g;
+        if (em.on) {
+            const int xi = (int)(v % dx), yi = (int)((v / dx) % dy), zi = (int)(v / ((long long)dx * dy));
+            const long long e0 = edge_index<0>(em, xi, yi, zi), e1 = edge_index<1>(em, xi, yi, zi),
+                            e2 = edge_index<2>(em, xi, yi, zi);
+            if (e0 >= 0) grad[e0] = gk[0];
+            if (e1 >= 0) grad[e1] = gk[1];
+            if (e2 >= 0) grad[e2] = gk[2];
+        } else {
+            grad[v] = gk[0] + gk[1] + gk[2];
+        }
     }
 }
 
@@ -1059,31 +1127,38 @@ int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream)
     return (int)hipGetLastError();
 }
 
-template <bool NT, bool DFT>
+template <bool NT, bool DFT, bool EDGE>
 void launch_aux_nt(const StepArgs& a, int maxpairs, dim3 ag, dim3 ab, hipStream_t s)
 {
-    if (maxpairs <= 0) hipLaunchKernelGGL((ccpr_aux_kernel<0, NT, DFT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 1) hipLaunchKernelGGL((ccpr_aux_kernel<1, NT, DFT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 2) hipLaunchKernelGGL((ccpr_aux_kernel<2, NT, DFT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 3) hipLaunchKernelGGL((ccpr_aux_kernel<3, NT, DFT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 4) hipLaunchKernelGGL((ccpr_aux_kernel<4, NT, DFT>), ag, ab, 0, s, a);
-    else if (maxpairs <= 6) hipLaunchKernelGGL((ccpr_aux_kernel<6, NT, DFT>), ag, ab, 0, s, a);
-    else hipLaunchKernelGGL((ccpr_aux_kernel<8, NT, DFT>), ag, ab, 0, s, a);
+    if (maxpairs <= 0) hipLaunchKernelGGL((ccpr_aux_kernel<0, NT, DFT, EDGE>), ag, ab, 0, s, a);
+    else if (maxpairs <= 1) hipLaunchKernelGGL((ccpr_aux_kernel<1, NT, DFT, EDGE>), ag, ab, 0, s, a);
+    else if (maxpairs <= 2) hipLaunchKernelGGL((ccpr_aux_kernel<2, NT, DFT, EDGE>), ag, ab, 0, s, a);
+    else if (maxpairs <= 3) hipLaunchKernelGGL((ccpr_aux_kernel<3, NT, DFT, EDGE>), ag, ab, 0, s, a);
+    else if (maxpairs <= 4) hipLaunchKernelGGL((ccpr_aux_kernel<4, NT, DFT, EDGE>), ag, ab, 0, s, a);
+    else if (maxpairs <= 6) hipLaunchKernelGGL((ccpr_aux_kernel<6, NT, DFT, EDGE>), ag, ab, 0, s, a);
+    else hipLaunchKernelGGL((ccpr_aux_kernel<8, NT, DFT, EDGE>), ag, ab, 0, s, a);
 }
 
-int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, void* stream)
+template <bool EDGE>
+void launch_aux_mode(const StepArgs& a, int maxpairs, dim3 ag, dim3 ab, hipStream_t s)
+{
+    const bool dft = (a.mode & (CCPR_MODE_DFT_T | CCPR_MODE_DFT_P)) != 0;
+    if (a.stream_st) {
+        if (dft) launch_aux_nt<true, true, EDGE>(a, maxpairs, ag, ab, s);
+        else launch_aux_nt<true, false, EDGE>(a, maxpairs, ag, ab, s);
+    } else {
+        if (dft) launch_aux_nt<false, true, EDGE>(a, maxpairs, ag, ab, s);
+        else launch_aux_nt<false, false, EDGE>(a, maxpairs, ag, ab, s);
+    }
+}
+
+int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, bool edge, void* stream)
 {
     if (nd <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
     dim3 ag((unsigned)((nd + 255) / 256)), ab(256);
-    const bool dft = (a.mode & (CCPR_MODE_DFT_T | CCPR_MODE_DFT_P)) != 0;
-    if (a.stream_st) {
-        if (dft) launch_aux_nt<true, true>(a, maxpairs, ag, ab, s);
-        else launch_aux_nt<true, false>(a, maxpairs, ag, ab, s);
-    } else {
-        if (dft) launch_aux_nt<false, true>(a, maxpairs, ag, ab, s);
-        else launch_aux_nt<false, false>(a, maxpairs, ag, ab, s);
-    }
+    if (edge) launch_aux_mode<true>(a, maxpairs, ag, ab, s);
+    else launch_aux_mode<false>(a, maxpairs, ag, ab, s);
     return (int)hipGetLastError();
 }
 
@@ -1167,12 +1242,12 @@ int ccpr_launch_extract(float* d, const float* src, int comp, int nx, int ny, in
     return (int)hipGetLastError();
 }
 
-int ccpr_launch_dft_grad(double* grad, const float* acc, long long nd, double i00, double i01, double i11,
-                         double wc, double ws, void* stream)
+int ccpr_launch_dft_grad(double* grad, const float* acc, long long nd, const int ddim[3], const EdgeMap& em,
+                         double i00, double i01, double i11, double wc, double ws, void* stream)
 {
     if (nd <= 0) return 0;
     hipLaunchKernelGGL(dft_grad_kernel, dim3(grid_for(nd)), dim3(256), 0, (hipStream_t)stream, grad, acc, nd,
-                       i00, i01, i11, wc, ws);
+                       ddim[0], ddim[1], em, i00, i01, i11, wc, ws);
     return (int)hipGetLastError();
 }
 

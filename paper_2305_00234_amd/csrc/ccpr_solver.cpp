@@ -69,10 +69,15 @@ struct ccpr_solver {
     int rows = 2;               // y rows per thread of the step kernel
     std::string err;
     MatHost mat[2][3];
-    // design
+    // design: the box [dlo, dlo + ddim) of nd cells the kernels run over.
+    // Per-edge designs (edge) have ncl cells and one density per E edge; their
+    // box holds ncl + 1 cells per axis, and nrho is the number of edges.
     bool has_design = false;
     int dlo[3]{}, ddim[3]{};
     long long nd = 0;
+    bool edge = false;
+    int ncl[3]{};
+    long long nrho = 0;
     double gamma = 0;
     std::vector<float> rho_host;
     bool rho_on_host = false, rho_uploaded = false;
@@ -207,6 +212,33 @@ int dft_window(int M, double omega, double dt)
 }
 
 // Workspace layout for a solve of M steps (M = 0: stepping only).
+// density values and gradient values: one per voxel, or one per design edge
+long long n_rho(const ccpr_solver* s) { return s->edge ? s->nrho : s->nd; }
+
+// edge map of a per-edge design (EdgeMap::on = 0 for per-voxel designs)
+EdgeMap edge_map(const ccpr_solver* s)
+{
+    EdgeMap m{};
+    if (!s->edge) return m;
+    m.on = 1;
+    long long o = 0;
+    for (int c = 0; c < 3; ++c) {
+        long long n = 1;
+        for (int l = 0; l < 3; ++l) {
+            m.ebox[c][l] = s->ncl[l] + (l == c ? 0 : 1);
+            n *= m.ebox[c][l];
+        }
+        m.eoff[c] = o;
+        o += n;
+    }
+    return m;
+}
+
+size_t stage_bytes(const ccpr_solver* s)
+{
+    return std::max((size_t)s->ncell * 4, (size_t)std::max(n_rho(s), 1LL) * 8);
+}
+
 Layout make_layout(const ccpr_solver* s, int M, int K_req)
 {
     Layout L{};
@@ -234,11 +266,11 @@ Layout make_layout(const ccpr_solver* s, int M, int K_req)
     L.drive = take((3 * nd + 3 * nsrc) * 4);
     L.zr = take((size_t)(s->g.nz + 1) * sizeof(int2));
     L.tiles = take((size_t)((s->g.ny + 1) / 2 + 1) * (s->g.nz + 1) * sizeof(int2));
-    L.rho = take(nd * 4);
+    L.rho = take((size_t)std::max(n_rho(s), 1LL) * 4);
     L.pmlE = take((size_t)(s->g.nx + s->g.ny + s->g.nz) * 16);
     L.pmlH = take((size_t)(s->g.nx + s->g.ny + s->g.nz) * 16);
     L.scal = take(16 * 8);
-    L.gradacc = take(nd * 8);
+    L.gradacc = take((size_t)std::max(n_rho(s), 1LL) * 8);
     L.work = take((size_t)std::max(s->gncell * 3, 1) * 16);
     L.fixed_end = o;
     // forward source tables cover the solve (or the waveform when stepping)
@@ -268,7 +300,7 @@ Layout make_layout(const ccpr_solver* s, int M, int K_req)
         L.ckpt_bytes = (6 * nc + 2 * (size_t)std::max(s->npairs_total, 1) * nd + 2 * psi) * 4 + 8 * 3 * 8;
         L.ckpt = take((size_t)(L.S - 1) * align256(L.ckpt_bytes));
     }
-    L.stage = take(std::max((size_t)s->ncell * 4, nd * 8));
+    L.stage = take(stage_bytes(s));
     L.total = o;
     return L;
 }
@@ -532,6 +564,7 @@ void fill_cold(ccpr_solver* s, int st, StepCold& C)
         C.rho = wsp<float>(s, L.rho);
         C.J = wsp<float>(s, L.Jb[st]);
         for (int ax = 0; ax < 3; ++ax) C.mat[ax] = s->mats[ax];
+        C.em = edge_map(s);
     }
     if (s->g.npml > 0) {
         const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
@@ -850,7 +883,7 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
     }
     // aux and post touch disjoint cells but share the device better in
     // sequence than side by side (measured)
-    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, ndes, As);
+    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, ndes, s->edge, As);
     fuse = fuse && s->fuse_ok[st];
     if (e == 0)
         e = fuse ? ccpr_launch_post_fused(A, nmisc, C.pw_on ? C.tf_nH : 0, As)
@@ -934,7 +967,8 @@ ccpr_status dft_finish(ccpr_solver* s)
     }
     const double det = scc * sss - scs * scs;
     if (!(det > 0)) return fail(s, CCPR_EINVAL, "DFT-mode fit window is degenerate (omega dt a multiple of pi?)");
-    HIPCHK(ccpr_launch_dft_grad(wsp<double>(s, s->lay.gradacc), wsp<float>(s, s->lay.T), s->nd, sss / det,
+    const EdgeMap em = edge_map(s);
+    HIPCHK(ccpr_launch_dft_grad(wsp<double>(s, s->lay.gradacc), wsp<float>(s, s->lay.T), s->nd, s->ddim, em, sss / det,
                                 -scs / det, scc / det, std::cos(th * M), std::sin(th * M), s->stream));
     return CCPR_OK;
 }
@@ -1096,6 +1130,70 @@ ccpr_status check_results(ccpr_solver* s, const double* scal)
     return CCPR_OK;
 }
 
+// Shared by ccpr_set_design (edge = false: one density per voxel of dims)
+// and ccpr_set_design_edges (edge = true: dims cells, one density per E edge,
+// kernel box of dims + 1 cells).
+ccpr_status set_design_common(ccpr_solver* s, const int lo[3], const int dims[3], double gamma, const float* rho,
+                              int mem, bool edge)
+{
+    if (!s) return CCPR_EINVAL;
+    if (!lo || !dims || !rho || (mem != CCPR_MEM_HOST && mem != CCPR_MEM_DEVICE))
+        return fail(s, CCPR_EINVAL, "bad design arguments");
+    const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
+    const int m = std::max(s->g.npml, 1);
+    int box[3];
+    for (int a = 0; a < 3; ++a) {
+        if (dims[a] < 1) return fail(s, CCPR_EINVAL, "design dimensions must be positive");
+        box[a] = dims[a] + (edge ? 1 : 0);
+        if (lo[a] < m || lo[a] + box[a] > n3[a] - s->g.npml)
+            return fail(s, CCPR_EINVAL, edge ? "design box (with the far-face edges) must lie inside the grid, "
+                                               "off the walls and outside the CPML"
+                                             : "design box must lie inside the grid, off the walls and outside the CPML");
+    }
+    if (!std::isfinite(gamma) || gamma < 0) return fail(s, CCPR_EINVAL, "gamma must be finite and >= 0");
+    const long long nd = (long long)box[0] * box[1] * box[2];
+    if (nd > 0x7fffffffLL) return fail(s, CCPR_ENOTSUP, "design box above 2^31 voxels");
+    long long nr = nd;
+    if (edge) {
+        nr = 0;
+        for (int c = 0; c < 3; ++c)
+            nr += (long long)(dims[0] + (c != 0)) * (dims[1] + (c != 1)) * (dims[2] + (c != 2));
+    }
+    if (mem == CCPR_MEM_HOST) {
+        for (long long v = 0; v < nr; ++v)
+            if (!(rho[v] >= 0.f && rho[v] <= 1.f))
+                return fail(s, CCPR_EINVAL, "density %lld is %g: must be finite and in [0,1]", v, (double)rho[v]);
+    } else if (!s->ws) {
+        return fail(s, CCPR_ESTATE, "device densities need a bound workspace");
+    }
+    for (int a = 0; a < 3; ++a) { s->dlo[a] = lo[a]; s->ddim[a] = box[a]; s->ncl[a] = dims[a]; }
+    s->nd = nd;
+    s->edge = edge;
+    s->nrho = nr;
+    s->gamma = gamma;
+    s->have_forward = s->have_adjoint = false;
+    if (mem == CCPR_MEM_HOST) {
+        s->rho_host.assign(rho, rho + nr);
+        s->rho_on_host = true;
+        s->rho_uploaded = false;
+        s->has_design = true;
+        ccpr_status st = refresh_fixed(s, false);
+        if (st) return st;
+        return upload_rho(s);
+    } else {
+        s->rho_on_host = false;
+        s->rho_host.clear();
+        s->has_design = true;
+        ccpr_status st = refresh_fixed(s, false);
+        if (st) return st;
+        s->has_design = true;
+        HIPCHK(hipMemcpyAsync(s->ws + s->lay.rho, rho, nr * 4, hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(ccpr_launch_fill_d(wsp<double>(s, s->lay.scal) + 2, 1, 0.0, s->stream));
+        HIPCHK(ccpr_launch_check_rho(wsp<float>(s, s->lay.rho), nr, wsp<double>(s, s->lay.scal) + 2, s->stream));
+    }
+    return CCPR_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -1179,48 +1277,13 @@ ccpr_status ccpr_set_material(ccpr_solver* s, int slot, int axis, double eps_inf
 ccpr_status ccpr_set_design(ccpr_solver* s, const int lo[3], const int dims[3], double gamma, const float* rho,
                             int mem)
 {
-    if (!s) return CCPR_EINVAL;
-    if (!lo || !dims || !rho || (mem != CCPR_MEM_HOST && mem != CCPR_MEM_DEVICE))
-        return fail(s, CCPR_EINVAL, "bad design arguments");
-    const int n3[3] = {s->g.nx, s->g.ny, s->g.nz};
-    const int m = std::max(s->g.npml, 1);
-    for (int a = 0; a < 3; ++a)
-        if (dims[a] < 1 || lo[a] < m || lo[a] + dims[a] > n3[a] - s->g.npml)
-            return fail(s, CCPR_EINVAL, "design box must lie inside the grid, off the walls and outside the CPML");
-    if (!std::isfinite(gamma) || gamma < 0) return fail(s, CCPR_EINVAL, "gamma must be finite and >= 0");
-    const long long nd = (long long)dims[0] * dims[1] * dims[2];
-    if (nd > 0x7fffffffLL) return fail(s, CCPR_ENOTSUP, "design box above 2^31 voxels");
-    if (mem == CCPR_MEM_HOST) {
-        for (long long v = 0; v < nd; ++v)
-            if (!(rho[v] >= 0.f && rho[v] <= 1.f))
-                return fail(s, CCPR_EINVAL, "density %lld is %g: must be finite and in [0,1]", v, (double)rho[v]);
-    } else if (!s->ws) {
-        return fail(s, CCPR_ESTATE, "device densities need a bound workspace");
-    }
-    for (int a = 0; a < 3; ++a) { s->dlo[a] = lo[a]; s->ddim[a] = dims[a]; }
-    s->nd = nd;
-    s->gamma = gamma;
-    s->have_forward = s->have_adjoint = false;
-    if (mem == CCPR_MEM_HOST) {
-        s->rho_host.assign(rho, rho + nd);
-        s->rho_on_host = true;
-        s->rho_uploaded = false;
-        s->has_design = true;
-        ccpr_status st = refresh_fixed(s, false);
-        if (st) return st;
-        return upload_rho(s);
-    } else {
-        s->rho_on_host = false;
-        s->rho_host.clear();
-        s->has_design = true;
-        ccpr_status st = refresh_fixed(s, false);
-        if (st) return st;
-        s->has_design = true;
-        HIPCHK(hipMemcpyAsync(s->ws + s->lay.rho, rho, nd * 4, hipMemcpyDeviceToDevice, s->stream));
-        HIPCHK(ccpr_launch_fill_d(wsp<double>(s, s->lay.scal) + 2, 1, 0.0, s->stream));
-        HIPCHK(ccpr_launch_check_rho(wsp<float>(s, s->lay.rho), nd, wsp<double>(s, s->lay.scal) + 2, s->stream));
-    }
-    return CCPR_OK;
+    return set_design_common(s, lo, dims, gamma, rho, mem, false);
+}
+
+ccpr_status ccpr_set_design_edges(ccpr_solver* s, const int lo[3], const int dims[3], double gamma,
+                                  const float* rho, int mem)
+{
+    return set_design_common(s, lo, dims, gamma, rho, mem, true);
 }
 
 ccpr_status ccpr_set_source_dipole(ccpr_solver* s, const int cell[3], int axis, const double* wave, int nsteps)
@@ -1473,7 +1536,7 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
     if (st) return st;
     st = upload_cold(s, 1);
     if (st) return st;
-    HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), ndm, 0.0, s->stream));
+    HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), std::max(n_rho(s), 1LL), 0.0, s->stream));
     if (s->grad_dft) HIPCHK(ccpr_launch_fill(wsp<float>(s, L.T) + 6 * ndm, 6 * ndm, 0.f, s->stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms_total = 0;
@@ -1536,11 +1599,11 @@ ccpr_status ccpr_gradient(ccpr_solver* s, double* grad, int mem)
     if (!s->have_adjoint) return fail(s, CCPR_ESTATE, "gradient needs a completed adjoint run");
     const double* f = wsp<double>(s, s->lay.scal) + 5;  // gradient scale, on the device
     if (mem == CCPR_MEM_DEVICE) {
-        HIPCHK(ccpr_launch_grad_out(grad, wsp<double>(s, s->lay.gradacc), s->nd, f, s->stream));
+        HIPCHK(ccpr_launch_grad_out(grad, wsp<double>(s, s->lay.gradacc), n_rho(s), f, s->stream));
     } else {
         double* stage = wsp<double>(s, s->lay.stage);
-        HIPCHK(ccpr_launch_grad_out(stage, wsp<double>(s, s->lay.gradacc), s->nd, f, s->stream));
-        HIPCHK(hipMemcpyAsync(grad, stage, s->nd * 8, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(ccpr_launch_grad_out(stage, wsp<double>(s, s->lay.gradacc), n_rho(s), f, s->stream));
+        HIPCHK(hipMemcpyAsync(grad, stage, n_rho(s) * 8, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
     return CCPR_OK;
@@ -1552,8 +1615,8 @@ ccpr_status ccpr_gap_spectrum(ccpr_solver* s, const double* omega, int nf, doubl
     if (!omega || !mean_E2 || nf < 1) return fail(s, CCPR_EINVAL, "bad gap-spectrum arguments");
     if (!s->have_forward) return fail(s, CCPR_ESTATE, "the gap spectrum needs a completed forward run");
     const Layout& L = s->lay;
-    const size_t stage_bytes = std::max((size_t)s->ncell * 4, (size_t)std::max(s->nd, 1LL) * 8);
-    if ((size_t)nf * 16 > stage_bytes) return fail(s, CCPR_EINVAL, "too many frequencies (at most %zu)", stage_bytes / 16);
+    const size_t sb = stage_bytes(s);
+    if ((size_t)nf * 16 > sb) return fail(s, CCPR_EINVAL, "too many frequencies (at most %zu)", sb / 16);
     for (int f = 0; f < nf; ++f)
         if (!std::isfinite(omega[f])) return fail(s, CCPR_EINVAL, "non-finite frequency");
     ccpr_status st = join_lead(s);
@@ -1682,7 +1745,7 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
             if (st) return st;
             st = zero_state(s, 1);
             if (st) return st;
-            HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), std::max(s->nd, 1LL), 0.0, s->stream));
+            HIPCHK(ccpr_launch_fill_d(wsp<double>(s, L.gradacc), std::max(n_rho(s), 1LL), 0.0, s->stream));
             if (s->grad_dft) {
                 const long long ndm = std::max(s->nd, 1LL);
                 HIPCHK(ccpr_launch_fill(wsp<float>(s, L.T) + 6 * ndm, 6 * ndm, 0.f, s->stream));
@@ -1740,8 +1803,8 @@ ccpr_status ccpr_pipe_results(ccpr_solver* s, double* scal_host, double* grad_ho
 {
     const Layout& L = s->lay;
     double* stage = wsp<double>(s, L.stage);
-    HIPCHK(ccpr_launch_grad_out(stage, wsp<double>(s, L.gradacc), s->nd, wsp<double>(s, L.scal) + 5, s->stream));
-    HIPCHK(hipMemcpyAsync(grad_host, stage, s->nd * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(ccpr_launch_grad_out(stage, wsp<double>(s, L.gradacc), n_rho(s), wsp<double>(s, L.scal) + 5, s->stream));
+    HIPCHK(hipMemcpyAsync(grad_host, stage, n_rho(s) * 8, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(scal_host, wsp<double>(s, L.scal), 8 * sizeof(double), hipMemcpyDeviceToHost,
                           s->stream));
     return CCPR_OK;
@@ -1756,7 +1819,7 @@ ccpr_status ccpr_pipe_check(ccpr_solver* s, const double* scal_host, double* F)
     return CCPR_OK;
 }
 
-long long ccpr_pipe_design_voxels(const ccpr_solver* s) { return s->has_design ? s->nd : 0; }
+long long ccpr_pipe_design_voxels(const ccpr_solver* s) { return s->has_design ? n_rho(s) : 0; }
 
 ccpr_status ccpr_pipe_set_stream2(ccpr_solver* s, void* stream2)
 {

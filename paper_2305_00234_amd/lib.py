@@ -13,6 +13,8 @@ from typing import Optional, Sequence
 
 import numpy as np
 
+from .inputs import edge_shape
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libccprfdtd.so")
 
@@ -26,6 +28,7 @@ EX, EY, EZ, HX, HY, HZ = range(6)
 # every entry point declared in include/ccprfdtd.h
 EXPORTS = [
     "ccpr_create", "ccpr_destroy", "ccpr_last_error", "ccpr_set_material", "ccpr_set_design",
+    "ccpr_set_design_edges",
     "ccpr_set_source_dipole", "ccpr_set_source_planewave", "ccpr_set_objective",
     "ccpr_set_checkpointing", "ccpr_set_gradient_mode", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
     "ccpr_adjoint", "ccpr_gradient", "ccpr_gap_spectrum", "ccpr_reset", "ccpr_step", "ccpr_get_field",
@@ -76,6 +79,7 @@ def load():
         "ccpr_last_error": (C.c_char_p, [_p]),
         "ccpr_set_material": (_i, [_p, _i, _i, _d, _d, _i, _dp, _dp]),
         "ccpr_set_design": (_i, [_p, _ip, _ip, _d, _p, _i]),
+        "ccpr_set_design_edges": (_i, [_p, _ip, _ip, _d, _p, _i]),
         "ccpr_set_source_dipole": (_i, [_p, _ip, _i, _dp, _i]),
         "ccpr_set_source_planewave": (_i, [_p, _i, _i, _i, _ip, _ip, _dp, _i]),
         "ccpr_set_objective": (_i, [_p, _i, _ip, _ip, _d, _i, _i]),
@@ -198,6 +202,8 @@ class Solver:
         self._h = h
         self.shape = (nz, ny, nx)
         self._keep = []
+        self.design_dims = None
+        self.per_edge = False
 
     # -- plumbing
     def _chk(self, st, what):
@@ -244,6 +250,53 @@ class Solver:
                                                 r.ctypes.data_as(C.c_void_p), MEM_HOST),
                       "ccpr_set_design")
         self.design_dims = dims
+        self.per_edge = False
+
+    def set_design_edges(self, lo, dims, rho_edges, gamma=0.0):
+        """One density per E edge of a design of dims = (Nx, Ny, Nz) cells:
+        rho_edges = (rho_x, rho_y, rho_z) host float32 arrays shaped
+        edge_shape(dims, c), or one flat torch float32 CUDA tensor holding
+        the x, y, z edges in turn."""
+        dims = tuple(int(d) for d in dims)
+        n = sum(int(np.prod(edge_shape(dims, c))) for c in range(3))
+        if hasattr(rho_edges, "data_ptr") and getattr(rho_edges, "is_cuda", False):
+            import torch
+            assert rho_edges.dtype == torch.float32 and rho_edges.is_contiguous() and rho_edges.numel() == n
+            self._chk(self._lib.ccpr_set_design_edges(self._h, _i3(lo), _i3(dims), gamma,
+                                                      C.c_void_p(rho_edges.data_ptr()), MEM_DEVICE),
+                      "ccpr_set_design_edges")
+        else:
+            parts = []
+            for c in range(3):
+                r = np.asarray(rho_edges[c], dtype=np.float32)
+                if r.shape != edge_shape(dims, c):
+                    raise ValueError(f"edge densities of component {c}: shape {r.shape}, "
+                                     f"expected {edge_shape(dims, c)}")
+                parts.append(r.ravel())
+            flat = np.ascontiguousarray(np.concatenate(parts))
+            self._chk(self._lib.ccpr_set_design_edges(self._h, _i3(lo), _i3(dims), gamma,
+                                                      flat.ctypes.data_as(C.c_void_p), MEM_HOST),
+                      "ccpr_set_design_edges")
+        self.design_dims = dims
+        self.per_edge = True
+
+    @property
+    def gradient_size(self) -> int:
+        """Number of gradient values: voxels, or design edges."""
+        d = self.design_dims
+        if self.per_edge:
+            return sum(int(np.prod(edge_shape(d, c))) for c in range(3))
+        return int(np.prod(d))
+
+    def split_edges(self, flat):
+        """Flat per-edge values -> (x, y, z) arrays shaped edge_shape(dims, c)."""
+        out, o = [], 0
+        for c in range(3):
+            shp = edge_shape(self.design_dims, c)
+            k = int(np.prod(shp))
+            out.append(flat[o:o + k].reshape(shp))
+            o += k
+        return tuple(out)
 
     def set_source_dipole(self, cell, axis, wave):
         w, wp = _f64(wave)
@@ -315,17 +368,20 @@ class Solver:
         return out
 
     def gradient(self, out=None):
-        """Host numpy (dz,dy,dx) float64 by default; pass a torch float64 CUDA
-        tensor to receive it on the device (stream-ordered)."""
+        """Host numpy (dz,dy,dx) float64 by default (per-edge designs: the
+        (x, y, z) edge arrays); pass a torch float64 CUDA tensor of
+        gradient_size values to receive it on the device (stream-ordered)."""
         d = self.design_dims
         if out is not None and getattr(out, "is_cuda", False):
+            if out.numel() != self.gradient_size:
+                raise ValueError(f"gradient output holds {out.numel()} values, need {self.gradient_size}")
             self._chk(self._lib.ccpr_gradient(self._h, C.c_void_p(out.data_ptr()), MEM_DEVICE),
                       "ccpr_gradient")
             return out
-        g = np.empty((d[2], d[1], d[0]), dtype=np.float64)
+        g = np.empty(self.gradient_size, dtype=np.float64)
         self._chk(self._lib.ccpr_gradient(self._h, g.ctypes.data_as(C.c_void_p), MEM_HOST),
                   "ccpr_gradient")
-        return g
+        return self.split_edges(g) if self.per_edge else g.reshape(d[2], d[1], d[0])
 
     def reset(self):
         self._chk(self._lib.ccpr_reset(self._h), "ccpr_reset")
@@ -422,11 +478,12 @@ class Engine:
         in seconds since the engine was created)."""
         s = self._solvers[ticket]
         d = s.design_dims
-        g = np.empty((d[2], d[1], d[0]), dtype=np.float64)
+        g = np.empty(s.gradient_size, dtype=np.float64)
         F = C.c_double(0.0)
         times = (C.c_double * 3)()
         self._chk(self._lib.ccpr_engine_result(self._h, ticket, C.byref(F), g.ctypes.data_as(_dp), times),
                   "ccpr_engine_result")
+        g = s.split_edges(g) if s.per_edge else g.reshape(d[2], d[1], d[0])
         return F.value, g, tuple(times)
 
     def release(self, ticket: int):

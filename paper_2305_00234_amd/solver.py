@@ -15,7 +15,10 @@ def configure(w: Workload, s: Solver | None = None) -> Solver:
     for ax in range(3):
         for slot, m in ((1, w.mat1[ax]), (2, w.mat2[ax])):
             s.set_material(slot, ax, m.eps_inf, m.sigma, m.a, m.c)
-    s.set_design(w.design_lo, w.rho, w.gamma)
+    if w.rho_edges is not None:
+        s.set_design_edges(w.design_lo, w.design_dims, w.rho_edges, w.gamma)
+    else:
+        s.set_design(w.design_lo, w.rho, w.gamma)
     if w.source == "dipole":
         s.set_source_dipole(w.dipole_cell, w.dipole_axis, w.wave)
     else:

@@ -7,6 +7,7 @@ import re
 import numpy as np
 import pytest
 
+from paper_2305_00234_amd import inputs as I
 from paper_2305_00234_amd import lib as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -162,3 +163,39 @@ def test_filter_calls_validate_arguments(built):
     assert lib.ccpr_filter_project(p, p, p, p, L._i3((0, 8, 8)), 2.0, 8.0, 0.5, None) == L.EINVAL
     assert lib.ccpr_filter_project_grad(p, None, p, p, dims, 2.0, 8.0, 0.5, None) == L.EINVAL
     assert lib.ccpr_nondiscreteness(p, 0, p, None) == L.EINVAL
+
+
+def test_edge_design_validation_and_workspace(built):
+    """ccpr_set_design_edges: the far-face edges (box of N + 1 cells) must
+    stay out of the CPML; densities are checked; the workspace holds one
+    density and one gradient value per edge and the currents of the N + 1
+    box."""
+    s = L.Solver(32, 32, 32, 10e-9, npml=8)
+    dims = (4, 5, 6)
+    ok = I.random_edge_densities(dims, seed=1)
+    with pytest.raises(L.CcprError) as e:           # far faces reach the CPML (x: 20 + 4 + 1 > 32 - 8)
+        s.set_design_edges((20, 10, 10), dims, ok)
+    assert e.value.status == L.EINVAL
+    s.set_design((20, 10, 10), np.full((6, 5, 4), 0.5, np.float32))   # the voxels alone fit
+    bad = [r.copy() for r in ok]
+    bad[2][1, 1, 1] = np.nan
+    with pytest.raises(L.CcprError) as e:
+        s.set_design_edges((10, 10, 10), dims, bad)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(ValueError):
+        s.set_design_edges((10, 10, 10), dims, (ok[1], ok[0], ok[2]))
+    s.set_design_edges((19, 10, 10), dims, ok)      # x: 19 + 4 + 1 = 24
+    assert s.gradient_size == sum(r.size for r in ok) == 4 * 6 * 7 + 5 * 5 * 7 + 5 * 6 * 6
+    s.set_source_dipole((10, 16, 16), 0, np.ones(400))
+    s.set_objective(L.OBJ_DFT_E2, (11, 11, 11), (2, 2, 2), 3e15)
+    b_edge = s.workspace_size(0)
+    s.set_design((19, 10, 10), np.full((7, 6, 5), 0.5, np.float32))
+    assert s.gradient_size == 5 * 6 * 7
+    b_vox = s.workspace_size(0)    # same kernel box; densities and gradients per voxel
+
+    def a256(n):
+        return (n + 255) // 256 * 256
+
+    ne, nv = 523, 210
+    assert b_edge - b_vox == (a256(4 * ne) - a256(4 * nv)) + (a256(8 * ne) - a256(8 * nv))
+    s.close()
