@@ -17,6 +17,10 @@ shaped [nz][ny][nx]; distances in voxel units):
   weight sum of m;
 - Eq. MeasureOfNon-discretness: M_nd = sum 4 rho_b (1 - rho_b) / N x 100 %.
 
+Both the per-voxel density grid and the per-edge variables (one density per
+E edge at the staggered edge centres, the sphere then spanning all three
+components) are covered.
+
 The filter visits the sphere's offsets one at a time and shifts the whole
 array (zero outside the design box), which is the definition written out.
 """
@@ -101,3 +105,87 @@ def nondiscreteness(rho_b: np.ndarray) -> float:
     """Eq. MeasureOfNon-discretness, in percent."""
     r = np.asarray(rho_b, np.float64).ravel()
     return float(np.sum(4.0 * r * (1.0 - r)) / r.size * 100.0)
+
+
+# ----------------------------------------------------- per-edge design
+# With one density per E edge (Sec. "FDTD implementation and design
+# export") the variables sit at the staggered edge centres: for a design of
+# N = (Nx, Ny, Nz) cells, the x edges at (i + 1/2, j, k) with i < Nx, j <= Ny,
+# k <= Nz, the y edges at (i, j + 1/2, k), the z edges at (i, j, k + 1/2).
+# Eq. FilterFunction then sums over every variable, of any component, whose
+# position lies within R of the output's position.
+
+def edge_shape(dims, c):
+    """(z, y, x) shape of the component-c edges of an N-cell design."""
+    e = [dims[l] + (0 if l == c else 1) for l in range(3)]
+    return (e[2], e[1], e[0])
+
+
+def _half(c):
+    """(z, y, x) half-cell offset of component c's positions."""
+    h = [0.0, 0.0, 0.0]
+    h[2 - c] = 0.5
+    return h
+
+
+def edge_pair_offsets(radius: float, a: int, b: int):
+    """Integer index offsets o = (dz, dy, dx) such that input edge m = n + o
+    of component b lies within radius of output edge n of component a, with
+    the cone weight radius - |o + h_b - h_a|."""
+    ha, hb = _half(a), _half(b)
+    s = [hb[q] - ha[q] for q in range(3)]
+    r = int(math.ceil(radius)) + 1
+    out = []
+    for dz in range(-r, r + 1):
+        for dy in range(-r, r + 1):
+            for dx in range(-r, r + 1):
+                d = math.sqrt((dz + s[0]) ** 2 + (dy + s[1]) ** 2 + (dx + s[2]) ** 2)
+                if d < radius:
+                    out.append((dz, dy, dx, radius - d))
+    return out
+
+
+def _shifted_to(src: np.ndarray, out_shape, dz: int, dy: int, dx: int) -> np.ndarray:
+    """b[k,j,i] = src[k+dz, j+dy, i+dx] on out_shape, zero outside src."""
+    b = np.zeros(out_shape, dtype=np.float64)
+    lo = [max(0, -o) for o in (dz, dy, dx)]
+    hi = [min(out_shape[q], src.shape[q] - o) for q, o in enumerate((dz, dy, dx))]
+    if all(lo[q] < hi[q] for q in range(3)):
+        b[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = src[lo[0] + dz:hi[0] + dz, lo[1] + dy:hi[1] + dy,
+                                                       lo[2] + dx:hi[2] + dx]
+    return b
+
+
+def _edge_weighted_sums(vals, dims, radius):
+    """out_a[n] = sum_b sum_m w(|r_b(m) - r_a(n)|) vals_b[m] over the edges
+    within radius (vals: three arrays in edge_shape(dims, b))."""
+    out = []
+    for a in range(3):
+        acc = np.zeros(edge_shape(dims, a), dtype=np.float64)
+        for b in range(3):
+            src = np.asarray(vals[b], dtype=np.float64)
+            for dz, dy, dx, w in edge_pair_offsets(radius, a, b):
+                acc += w * _shifted_to(src, acc.shape, dz, dy, dx)
+        out.append(acc)
+    return out
+
+
+def edge_weight_sums(dims, radius: float):
+    """W_a[n] = sum of the cone weights of all design edges around edge n."""
+    return _edge_weighted_sums([np.ones(edge_shape(dims, c)) for c in range(3)], dims, radius)
+
+
+def cone_filter_edges(rho_edges, dims, radius: float):
+    """Eq. FilterFunction over the per-edge variables (x, y, z arrays)."""
+    num = _edge_weighted_sums(rho_edges, dims, radius)
+    W = edge_weight_sums(dims, radius)
+    return [num[a] / W[a] for a in range(3)]
+
+
+def filter_project_grad_edges(dF_drho_b, rho_edges, dims, radius: float, beta: float, eta: float):
+    """Eq. GradientsFiltered over the per-edge variables: dF/drho_n =
+    sum_m w(m, n) v_m with v = dF/drho_b * drho_b/drho_t / W (w symmetric)."""
+    rt = cone_filter_edges(rho_edges, dims, radius)
+    W = edge_weight_sums(dims, radius)
+    v = [np.asarray(dF_drho_b[a], np.float64) * project_derivative(rt[a], beta, eta) / W[a] for a in range(3)]
+    return _edge_weighted_sums(v, dims, radius)

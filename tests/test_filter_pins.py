@@ -89,3 +89,85 @@ def test_nondiscreteness_extremes():
     assert OF.nondiscreteness(np.array([0.0, 1.0, 1.0, 0.0])) == 0.0
     assert OF.nondiscreteness(np.full(10, 0.5)) == pytest.approx(100.0)
     assert OF.nondiscreteness(np.array([0.25])) == pytest.approx(75.0)
+
+
+# ------------------------------------------------ per-edge design variables
+def _edge_positions(dims):
+    """Physical positions (x, y, z) of every design edge, x edges first."""
+    pts = []
+    for c in range(3):
+        sz, sy, sx = OF.edge_shape(dims, c)
+        for k in range(sz):
+            for j in range(sy):
+                for i in range(sx):
+                    p = [float(i), float(j), float(k)]
+                    p[c] += 0.5
+                    pts.append(p)
+    return np.array(pts)
+
+
+def _brute_edge_filter(flat, dims, R):
+    """Eq. FilterFunction written out over the edge positions: every pair."""
+    P = _edge_positions(dims)
+    out = np.empty(len(P))
+    for n in range(len(P)):
+        d = np.sqrt(((P - P[n]) ** 2).sum(axis=1))
+        w = np.where(d < R, R - d, 0.0)
+        out[n] = (w * flat).sum() / w.sum()
+    return out
+
+
+def _flat(arrs):
+    return np.concatenate([np.asarray(a, np.float64).ravel() for a in arrs])
+
+
+@pytest.mark.parametrize("R", [1.0, 1.7, 2.5])
+def test_edge_filter_matches_brute_force(R):
+    dims = (3, 2, 4)
+    rng = np.random.default_rng(5)
+    rho = [rng.random(OF.edge_shape(dims, c)) for c in range(3)]
+    got = _flat(OF.cone_filter_edges(rho, dims, R))
+    assert np.allclose(got, _brute_edge_filter(_flat(rho), dims, R), rtol=0, atol=1e-14)
+
+
+def test_edge_filter_keeps_constants_and_interior_linear_fields():
+    """The per-edge filter reproduces a linear function of position wherever
+    the whole sphere holds design edges: the staggered positions enter with
+    their half-cell offsets (a filter that put every edge at its cell corner
+    would shift the field by half a cell)."""
+    dims, R = (9, 8, 10), 2.3
+    c = [np.full(OF.edge_shape(dims, a), 0.42) for a in range(3)]
+    assert all(np.allclose(x, 0.42, rtol=0, atol=1e-15) for x in OF.cone_filter_edges(c, dims, R))
+    lin, inner = [], []
+    m = int(math.ceil(R)) + 1
+    for a in range(3):
+        k, j, i = np.meshgrid(*[np.arange(s) for s in OF.edge_shape(dims, a)], indexing="ij")
+        x, y, z = i.astype(float), j.astype(float), k.astype(float)
+        (x, y, z)[a][...] += 0.5
+        lin.append(0.01 * x - 0.02 * y + 0.03 * z + 0.1)
+        sz, sy, sx = OF.edge_shape(dims, a)
+        inner.append((slice(m, sz - m), slice(m, sy - m), slice(m, sx - m)))
+    f = OF.cone_filter_edges(lin, dims, R)
+    for a in range(3):
+        assert np.allclose(f[a][inner[a]], lin[a][inner[a]], rtol=0, atol=1e-14)
+
+
+def test_edge_filter_chain_rule_matches_finite_differences():
+    rng = np.random.default_rng(7)
+    dims, R, beta, eta = (4, 3, 5), 2.1, 6.0, 0.45
+    rho = [rng.random(OF.edge_shape(dims, c)) for c in range(3)]
+    cvec = [rng.standard_normal(OF.edge_shape(dims, c)) for c in range(3)]
+
+    def F(r):
+        rt = OF.cone_filter_edges(r, dims, R)
+        return float(sum(np.sum(cvec[a] * OF.project(rt[a], beta, eta)) for a in range(3)))
+
+    g = OF.filter_project_grad_edges(cvec, rho, dims, R, beta, eta)
+    h = 1e-6
+    for (a, idx) in [(0, (0, 0, 0)), (0, (5, 3, 3)), (1, (2, 1, 4)), (1, (5, 2, 0)), (2, (3, 3, 4)), (2, (1, 0, 2))]:
+        rp = [x.copy() for x in rho]
+        rm = [x.copy() for x in rho]
+        rp[a][idx] += h
+        rm[a][idx] -= h
+        fd = (F(rp) - F(rm)) / (2 * h)
+        assert g[a][idx] == pytest.approx(fd, rel=1e-7, abs=1e-10)
