@@ -336,6 +336,21 @@ ccpr_status ccpr_filter_project_grad(const double* dF_dprojected, const float* r
                                      double* dF_drho, const int dims[3], double radius, double beta, double eta,
                                      void* hip_stream);
 
+/* ccpr_filter_project and ccpr_filter_project_grad for a per-edge design
+ * (ccpr_set_design_edges; Sec. "FDTD implementation and design export"):
+ * dims = (Nx, Ny, Nz) cells, arrays of N~_x + N~_y + N~_z values in the
+ * per-edge layout (x edges, then y, then z, each x fastest in its extents
+ * N_l + 1 - delta_kl).  Each density sits at its edge centre, (i+1/2, j, k)
+ * for x edges, (i, j+1/2, k) for y, (i, j, k+1/2) for z, and Eq.
+ * FilterFunction's sphere takes in the edges of all three components within
+ * R of it.  Same arguments, precision and errors as the per-voxel calls. */
+ccpr_status ccpr_filter_project_edges(const float* rho, float* rho_filtered, float* rho_projected,
+                                      float* weight_sum, const int dims[3], double radius, double beta, double eta,
+                                      void* hip_stream);
+ccpr_status ccpr_filter_project_grad_edges(const double* dF_dprojected, const float* rho_filtered,
+                                           const float* weight_sum, double* dF_drho, const int dims[3], double radius,
+                                           double beta, double eta, void* hip_stream);
+
 /* Eq. MeasureOfNon-discretness: *out = sum 4 rho (1 - rho) / n x 100 (per
  * cent) over n projected densities, FP64, written to device memory; the
  * summation order is fixed (bitwise reproducible). */

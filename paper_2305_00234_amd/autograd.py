@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import torch
 
-from .lib import Solver, filter_project, filter_project_grad
+from .lib import Solver, filter_project, filter_project_edges, filter_project_grad, filter_project_grad_edges
 
 
 class CCPRObjective(torch.autograd.Function):
@@ -88,3 +88,64 @@ def filtered_objective(rho, solver: Solver, nsteps: int, design_lo, gamma: float
     projected one; autograd chains Eq. GradientsFiltered after the adjoint
     gradient."""
     return CCPRObjective.apply(FilterProject.apply(rho, radius, beta, eta), solver, nsteps, design_lo, gamma)
+
+
+# ---- per-edge design variables (one density per E edge, flat x, y, z edges
+# of a dims-cell design; Sec. "FDTD implementation and design export")
+
+class CCPREdgeObjective(torch.autograd.Function):
+    """F = CCPREdgeObjective.apply(rho, solver, nsteps, design_lo, dims, gamma)
+    for a flat CUDA tensor of per-edge densities (ccpr_set_design_edges
+    layout); backward returns dF/drho per edge in rho's dtype."""
+
+    @staticmethod
+    def forward(ctx, rho, solver: Solver, nsteps: int, design_lo, dims, gamma: float):
+        if not rho.is_cuda:
+            raise ValueError("rho must be a CUDA tensor")
+        r32 = rho.detach().to(torch.float32).contiguous()
+        solver.set_design_edges(design_lo, dims, r32, gamma)
+        F = solver.forward(int(nsteps))
+        ctx.solver = solver
+        ctx.rho_dtype = rho.dtype
+        ctx.n = rho.numel()
+        return torch.tensor(F, dtype=torch.float64, device=rho.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        s: Solver = ctx.solver
+        s.adjoint()
+        g = torch.empty(ctx.n, dtype=torch.float64, device=grad_out.device)
+        s.gradient(out=g)
+        return (grad_out.to(torch.float64) * g).to(ctx.rho_dtype), None, None, None, None, None
+
+
+class FilterProjectEdges(torch.autograd.Function):
+    """FilterProject for per-edge densities: the cone filter over the
+    staggered edge positions (all three components in the sphere) and the
+    projection; backward is Eq. GradientsFiltered over the same sphere."""
+
+    @staticmethod
+    def forward(ctx, rho, dims, radius: float, beta: float, eta: float):
+        if not rho.is_cuda:
+            raise ValueError("rho must be a CUDA tensor")
+        r32 = rho.detach().to(torch.float32).contiguous()
+        rt, rb, ws = filter_project_edges(r32, dims, radius, beta, eta)
+        ctx.save_for_backward(rt, ws)
+        ctx.params = (tuple(dims), radius, beta, eta)
+        ctx.rho_dtype = rho.dtype
+        return rb.to(rho.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        rt, ws = ctx.saved_tensors
+        dims, radius, beta, eta = ctx.params
+        g = filter_project_grad_edges(grad_out.detach().to(torch.float64).contiguous(), rt, ws, dims, radius,
+                                      beta, eta)
+        return g.to(ctx.rho_dtype), None, None, None, None
+
+
+def filtered_edge_objective(rho, solver: Solver, nsteps: int, design_lo, dims, gamma: float, radius: float,
+                            beta: float, eta: float = 0.5):
+    """F(project(filter(rho))) for per-edge densities (flat CUDA tensor)."""
+    return CCPREdgeObjective.apply(FilterProjectEdges.apply(rho, dims, radius, beta, eta), solver, nsteps,
+                                   design_lo, dims, gamma)

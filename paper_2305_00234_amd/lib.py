@@ -37,6 +37,7 @@ EXPORTS = [
     "ccpr_engine_create", "ccpr_engine_submit", "ccpr_engine_poll", "ccpr_engine_wait",
     "ccpr_engine_result", "ccpr_engine_release", "ccpr_engine_last_error", "ccpr_engine_destroy",
     "ccpr_filter_project", "ccpr_filter_project_grad", "ccpr_nondiscreteness",
+    "ccpr_filter_project_edges", "ccpr_filter_project_grad_edges",
 ]
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 GRAD_TIME_EXACT, GRAD_DFT = 0, 1
@@ -111,6 +112,8 @@ def load():
         "ccpr_engine_destroy": (None, [_p]),
         "ccpr_filter_project": (_i, [_p, _p, _p, _p, _ip, _d, _d, _d, _p]),
         "ccpr_filter_project_grad": (_i, [_p, _p, _p, _p, _ip, _d, _d, _d, _p]),
+        "ccpr_filter_project_edges": (_i, [_p, _p, _p, _p, _ip, _d, _d, _d, _p]),
+        "ccpr_filter_project_grad_edges": (_i, [_p, _p, _p, _p, _ip, _d, _d, _d, _p]),
         "ccpr_nondiscreteness": (_i, [_p, C.c_longlong, _p, _p]),
     }
     for name, (res, args) in sig.items():
@@ -171,6 +174,52 @@ def filter_project_grad(dF_dprojected, rho_filtered, weight_sum, radius: float, 
                                          C.c_void_p(g.data_ptr()), dims, radius, beta, eta,
                                          C.c_void_p(torch.cuda.current_stream(g.device).cuda_stream))
     _check_free(st, "ccpr_filter_project_grad")
+    return g
+
+
+def edge_count(dims) -> int:
+    """Design edges of an N-cell per-edge design (N~_x + N~_y + N~_z)."""
+    return sum(int(np.prod(edge_shape(dims, c))) for c in range(3))
+
+
+def _flat_cuda(t, dtype, n, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+            and t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor of {n} values (per-edge layout)")
+    return t
+
+
+def filter_project_edges(rho, dims, radius: float, beta: float, eta: float):
+    """ccpr_filter_project_edges on a flat float32 CUDA tensor of per-edge
+    densities (x, y, z edges of a dims-cell design): returns
+    (rho_filtered, rho_projected, weight_sum), same layout."""
+    import torch
+    _flat_cuda(rho, torch.float32, edge_count(dims), "rho")
+    rt, rb, ws = torch.empty_like(rho), torch.empty_like(rho), torch.empty_like(rho)
+    st = load().ccpr_filter_project_edges(C.c_void_p(rho.data_ptr()), C.c_void_p(rt.data_ptr()),
+                                          C.c_void_p(rb.data_ptr()), C.c_void_p(ws.data_ptr()), _i3(dims),
+                                          radius, beta, eta,
+                                          C.c_void_p(torch.cuda.current_stream(rho.device).cuda_stream))
+    _check_free(st, "ccpr_filter_project_edges")
+    return rt, rb, ws
+
+
+def filter_project_grad_edges(dF_dprojected, rho_filtered, weight_sum, dims, radius: float, beta: float,
+                              eta: float):
+    """ccpr_filter_project_grad_edges: the per-edge chain rule (float64)."""
+    import torch
+    n = edge_count(dims)
+    _flat_cuda(dF_dprojected, torch.float64, n, "dF_dprojected")
+    _flat_cuda(rho_filtered, torch.float32, n, "rho_filtered")
+    _flat_cuda(weight_sum, torch.float32, n, "weight_sum")
+    g = torch.empty_like(dF_dprojected)
+    st = load().ccpr_filter_project_grad_edges(C.c_void_p(dF_dprojected.data_ptr()),
+                                               C.c_void_p(rho_filtered.data_ptr()),
+                                               C.c_void_p(weight_sum.data_ptr()), C.c_void_p(g.data_ptr()),
+                                               _i3(dims), radius, beta, eta,
+                                               C.c_void_p(torch.cuda.current_stream(g.device).cuda_stream))
+    _check_free(st, "ccpr_filter_project_grad_edges")
     return g
 
 

@@ -163,6 +163,10 @@ def test_filter_calls_validate_arguments(built):
     assert lib.ccpr_filter_project(p, p, p, p, L._i3((0, 8, 8)), 2.0, 8.0, 0.5, None) == L.EINVAL
     assert lib.ccpr_filter_project_grad(p, None, p, p, dims, 2.0, 8.0, 0.5, None) == L.EINVAL
     assert lib.ccpr_nondiscreteness(p, 0, p, None) == L.EINVAL
+    assert lib.ccpr_filter_project_edges(None, p, p, p, dims, 2.0, 8.0, 0.5, None) == L.EINVAL
+    assert lib.ccpr_filter_project_edges(p, p, p, p, dims, 17.5, 8.0, 0.5, None) == L.EINVAL
+    assert lib.ccpr_filter_project_edges(p, p, p, p, L._i3((8, 8, 65535)), 2.0, 8.0, 0.5, None) == L.EINVAL
+    assert lib.ccpr_filter_project_grad_edges(p, p, p, p, dims, 2.0, -1.0, 0.5, None) == L.EINVAL
 
 
 def test_edge_design_validation_and_workspace(built):
