@@ -166,10 +166,17 @@ ccpr_status ccpr_set_objective(ccpr_solver* s, int kind, const int lo[3], const 
 /* Forward-history checkpointing for the time-exact gradient.  The forward run
  * stores one gradient factor (3 floats) per design voxel and step; when the
  * full history does not fit, the run is split into segments of
- * checkpoint_every steps that are recomputed from state checkpoints during the
- * adjoint.  0 = the smallest segment count that fits the bound workspace.
- * Results are bit-identical for every segment size. */
+ * checkpoint_every steps.  The last segments whose history fits the bound
+ * workspace keep the forward run's records ("resident" segments); the others
+ * start from state checkpoints and are recomputed during the adjoint.
+ * 0 = choose the segment length that recomputes the fewest steps within the
+ * bound workspace.  Results are bit-identical for every segmentation. */
 ccpr_status ccpr_set_checkpointing(ccpr_solver* s, int checkpoint_every);
+
+/* At most max_resident resident segments (0, the default: as many as fit the
+ * workspace).  1 recomputes every segment but the last, with the smallest
+ * history buffer.  CCPR_EINVAL if negative. */
+ccpr_status ccpr_set_resident_segments(ccpr_solver* s, int max_resident);
 
 /* Gradient estimator (default CCPR_GRAD_TIME_EXACT: the exact discrete
  * gradient of ccpr_gradient, from the stored or recomputed forward history).
@@ -193,8 +200,14 @@ ccpr_status ccpr_set_gradient_mode(ccpr_solver* s, int mode);
 
 /* Device bytes needed for a forward + adjoint + gradient solve of nsteps
  * (nsteps = 0: field stepping only) with the current configuration and
- * checkpoint_every (0: full history).  Drives admission in serving. */
+ * checkpoint_every (0: full history), with one resident segment.  Drives
+ * admission in serving. */
 ccpr_status ccpr_workspace_size(const ccpr_solver* s, int nsteps, uint64_t* bytes);
+
+/* The most device bytes such a solve can use: every segment resident (at
+ * most max_resident of them), so nothing is recomputed.  Between the two
+ * sizes the solver keeps as many of the last segments resident as fit. */
+ccpr_status ccpr_workspace_size_max(const ccpr_solver* s, int nsteps, uint64_t* bytes);
 
 /* Borrow a device buffer of 'bytes' (256-byte aligned) as workspace and bind a
  * HIP stream (hipStream_t, may be NULL for the null stream).  The library
@@ -281,6 +294,10 @@ ccpr_status ccpr_get_grid_timing(const ccpr_solver* s, double* grid_ms_total, lo
  * z-planes one workgroup of the step kernel marches over.  Any pointer may be
  * NULL. */
 ccpr_status ccpr_get_info(const ccpr_solver* s, int* segments, int* segment_steps, int* tile_planes);
+
+/* Resident segments of the last ccpr_forward layout (segments - resident of
+ * them are recomputed by ccpr_adjoint).  CCPR_EINVAL for NULL arguments. */
+ccpr_status ccpr_get_resident_segments(const ccpr_solver* s, int* resident);
 
 /* Launch shape: nominal z-planes per workgroup of the step kernel (default
  * 5; the planes are split into about nz/planes chunks of equal estimated

@@ -54,6 +54,8 @@ struct Layout {
     size_t src_fwd, src_adj, wave, lineE, lineH, incE, incH, tf, gap, T, ckpt, stage;
     size_t total;
     int K = 0, S = 1;            // segment length / count
+    int R = 1;                   // resident segments: the last R segments keep the
+                                 // forward run's history; the others are recomputed
     size_t ckpt_bytes = 0;
     int inc_steps = 0, line_L = 0;
 };
@@ -92,6 +94,7 @@ struct ccpr_solver {
     int obj_kind = 1, glo[3]{}, gdim[3]{}, gncell = 0, nb = 0, ne = -1;
     double omega = 0;
     int ckpt_every = 0;
+    int resident_max = 0;       // at most this many resident segments (0: as many as fit)
     bool grad_dft = false;      // DFT-mode gradient estimator (CCPR_GRAD_DFT)
     // workspace
     char* ws = nullptr;
@@ -239,7 +242,7 @@ size_t stage_bytes(const ccpr_solver* s)
     return std::max((size_t)s->ncell * 4, (size_t)std::max(n_rho(s), 1LL) * 8);
 }
 
-Layout make_layout(const ccpr_solver* s, int M, int K_req)
+Layout make_layout(const ccpr_solver* s, int M, int K_req, int R_req = 1)
 {
     Layout L{};
     size_t o = 0;
@@ -296,9 +299,12 @@ Layout make_layout(const ccpr_solver* s, int M, int K_req)
         int K = s->grad_dft ? M : K_req > 0 ? std::min(K_req, M) : M;
         L.K = K;
         L.S = (M + K - 1) / K;
-        L.T = take(s->grad_dft ? 12 * nd * 4 : (size_t)K * 3 * nd * 4);
+        // the history holds the last R segments (R K steps); checkpoints start
+        // the segments 1 .. S-R-1 that are recomputed (segment 0 starts from zero)
+        L.R = std::max(1, std::min(R_req, L.S));
+        L.T = take(s->grad_dft ? 12 * nd * 4 : (size_t)L.R * K * 3 * nd * 4);
         L.ckpt_bytes = (6 * nc + 2 * (size_t)std::max(s->npairs_total, 1) * nd + 2 * psi) * 4 + 8 * 3 * 8;
-        L.ckpt = take((size_t)(L.S - 1) * align256(L.ckpt_bytes));
+        L.ckpt = take((size_t)std::max(L.S - L.R - 1, 0) * align256(L.ckpt_bytes));
     }
     L.stage = take(stage_bytes(s));
     L.total = o;
@@ -894,14 +900,37 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
     return CCPR_OK;
 }
 
+// Forward step n of a full run starts a segment whose state is saved as a
+// checkpoint (slot seg-1): segments 1 .. S-R-1, the ones the adjoint recomputes.
+bool saves_checkpoint(const Layout& L, int n)
+{
+    if (L.K <= 0 || n % L.K != 0) return false;
+    const int seg = n / L.K;
+    return seg >= 1 && seg < L.S - L.R;
+}
+
+// History slot of forward step n during the forward run: resident segments
+// (the last R) keep their records, in order; -1 for the recomputed ones.
+int forward_slot(const Layout& L, int n)
+{
+    const int seg = n / L.K, first = L.S - L.R;
+    return seg >= first ? n - first * L.K : -1;
+}
+
+// First history slot of segment seg during the adjoint run: a resident
+// segment's own place, or slot 0 where a recomputed segment is written.
+int segment_base(const Layout& L, int seg)
+{
+    const int first = L.S - L.R;
+    return seg >= first ? (seg - first) * L.K : 0;
+}
+
 // Whether forward step m of a full run follows its predecessor at once: not
 // past the end and not after a checkpoint save (which must see the plain state).
 bool fuse_forward(const ccpr_solver* s, int m)
 {
-    const int K = s->lay.K, S = s->lay.S;
     if (m >= s->M) return false;
-    const int seg = K > 0 ? m / K : 0;
-    return !(K > 0 && m % K == 0 && seg >= 1 && seg < S);
+    return !saves_checkpoint(s->lay, m);
 }
 
 // One forward step n of the forward state; tslot >= 0 records the gradient
@@ -924,8 +953,8 @@ ccpr_status forward_step(ccpr_solver* s, int n, int tslot, bool gap, bool fuse)
     return launch_step(s, A, 0, fuse);
 }
 
-// Adjoint step p = M-1-n (it pairs with forward step n of the segment that
-// starts at n0): time-exact correlation with history slot n-n0, or, in DFT
+// Adjoint step p = M-1-n (it pairs with forward step n, whose record is in
+// history slot n - n0): time-exact correlation with that slot, or, in DFT
 // mode, the projection of the new adjoint field Et^{p+1} when it lies in the
 // fit window.
 ccpr_status adjoint_step(ccpr_solver* s, int n, int n0, bool fuse)
@@ -1081,13 +1110,41 @@ ccpr_status adopt_layout(ccpr_solver* s, int M)
     if (st0) return st0;
     build_mats(s);
     int K = s->ckpt_every;
+    const int rmax = s->resident_max;
     Layout L = make_layout(s, M, K);
-    if (M > 0 && K == 0 && L.total > s->ws_bytes) {
-        // smallest segment count that fits the workspace
-        for (int S = 2; S <= M; ++S) {
-            int Kt = (M + S - 1) / S;
-            L = make_layout(s, M, Kt);
-            if (L.total <= s->ws_bytes) break;
+    // most resident segments (fewest recomputed steps) that fit, for segment
+    // length Kt
+    auto best_r = [&](int Kt) {
+        Layout b = make_layout(s, M, Kt, 1);
+        const int lim = rmax > 0 ? std::min(rmax, b.S) : b.S;
+        for (int r = lim; r > 1; --r) {
+            Layout t = make_layout(s, M, Kt, r);
+            if (t.total <= s->ws_bytes) return t;
+        }
+        return b;
+    };
+    auto recomputed = [&](const Layout& t) { return (t.S - t.R) * t.K; };  // the last segment is resident
+    if (M > 0 && !s->grad_dft) {
+        if (K > 0) {
+            L = best_r(K);
+        } else if (L.total > s->ws_bytes) {
+            // the whole history does not fit: choose the segment length that
+            // recomputes the fewest steps (then the fewest segments)
+            bool found = false;
+            for (int S = 2; S <= std::min(M, 128); ++S) {
+                const int Kt = (M + S - 1) / S;
+                Layout t = best_r(Kt);
+                if (t.total > s->ws_bytes) continue;
+                if (!found || recomputed(t) < recomputed(L)) L = t;
+                found = true;
+            }
+            if (!found) {
+                // fall back to the smallest segment count that fits with one resident segment
+                for (int S = 129; S <= M; ++S) {
+                    L = make_layout(s, M, (M + S - 1) / S);
+                    if (L.total <= s->ws_bytes) break;
+                }
+            }
         }
     }
     if (L.total > s->ws_bytes)
@@ -1374,6 +1431,23 @@ ccpr_status ccpr_workspace_size(const ccpr_solver* s, int nsteps, uint64_t* byte
     return CCPR_OK;
 }
 
+ccpr_status ccpr_workspace_size_max(const ccpr_solver* s, int nsteps, uint64_t* bytes)
+{
+    if (!s || !bytes || nsteps < 0) return CCPR_EINVAL;
+    const Layout L = make_layout(s, nsteps, s->ckpt_every);
+    const int r = s->resident_max > 0 ? std::min(s->resident_max, L.S) : L.S;
+    *bytes = make_layout(s, nsteps, s->ckpt_every, r).total;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_set_resident_segments(ccpr_solver* s, int max_resident)
+{
+    if (!s) return CCPR_EINVAL;
+    if (max_resident < 0) return fail(s, CCPR_EINVAL, "resident segments must be >= 0");
+    s->resident_max = max_resident;
+    return CCPR_OK;
+}
+
 ccpr_status ccpr_bind_workspace(ccpr_solver* s, void* dev_ptr, uint64_t bytes, void* hip_stream)
 {
     if (!s) return CCPR_EINVAL;
@@ -1485,12 +1559,11 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
     }
     s->timed_loop = s->timing;
     for (int n = 0; n < M; ++n) {
-        const int seg = n / K;
-        if (n % K == 0 && seg >= 1 && seg < S) {
-            st = checkpoint(s, seg - 1, true);
+        if (saves_checkpoint(L, n)) {
+            st = checkpoint(s, n / K - 1, true);
             if (st) return st;
         }
-        st = forward_step(s, n, seg == S - 1 ? n - seg * K : -1, true, fuse_forward(s, n + 1));
+        st = forward_step(s, n, forward_slot(L, n), true, fuse_forward(s, n + 1));
         if (st) return st;
     }
     st = join_lead(s);
@@ -1543,7 +1616,7 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
     s->timed_loop = s->timing;
     for (int seg = S - 1; seg >= 0; --seg) {
         const int n0 = seg * K, n1 = std::min(M, n0 + K);
-        if (seg < S - 1) {
+        if (seg < S - L.R) {
             // recompute the forward segment from its checkpoint, writing the history
             if (seg == 0) st = zero_state(s, 0);
             else st = checkpoint(s, seg - 1, false);
@@ -1555,13 +1628,14 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
             st = join_lead(s);
             if (st) return st;
         }
+        const int h0 = n0 - segment_base(L, seg);  // history slot of step n is n - h0
         if (s->timing) {
             HIPCHK(hipEventCreate(&e0));
             HIPCHK(hipEventCreate(&e1));
             HIPCHK(hipEventRecord(e0, s->stream));
         }
         for (int n = n1 - 1; n >= n0; --n) {
-            st = adjoint_step(s, n, n0, n > 0);
+            st = adjoint_step(s, n, h0, n > 0);
             if (st) return st;
         }
         st = join_lead(s);
@@ -1668,6 +1742,13 @@ ccpr_status ccpr_get_info(const ccpr_solver* s, int* segments, int* segment_step
     return CCPR_OK;
 }
 
+ccpr_status ccpr_get_resident_segments(const ccpr_solver* s, int* resident)
+{
+    if (!s || !resident) return CCPR_EINVAL;
+    *resident = s->lay.R;
+    return CCPR_OK;
+}
+
 ccpr_status ccpr_set_tile_planes(ccpr_solver* s, int planes)
 {
     if (!s) return CCPR_EINVAL;
@@ -1731,12 +1812,11 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
                 s->pipe_phase = 1;
                 continue;
             }
-            const int seg = n / K;
-            if (n % K == 0 && seg >= 1 && seg < S) {
-                st = checkpoint(s, seg - 1, true);
+            if (saves_checkpoint(L, n)) {
+                st = checkpoint(s, n / K - 1, true);
                 if (st) return st;
             }
-            st = forward_step(s, n, seg == S - 1 ? n - seg * K : -1, true, fuse_forward(s, n + 1));
+            st = forward_step(s, n, forward_slot(L, n), true, fuse_forward(s, n + 1));
             if (st) return st;
             ++s->pipe_n;
             ++done;
@@ -1752,7 +1832,7 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
             }
             s->pipe_phase = 2;
             s->pipe_seg = S - 1;
-            s->pipe_sub = 1;  // the last segment's history is already written
+            s->pipe_sub = 1;  // the last segments' history is already written
             s->pipe_k = 0;
         } else {  // adjoint over segment pipe_seg
             const int seg = s->pipe_seg;
@@ -1772,7 +1852,7 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
                 }
             } else {  // adjoint step p pairs with forward step n
                 const int n = n1 - 1 - s->pipe_k;
-                st = adjoint_step(s, n, n0, n > 0);
+                st = adjoint_step(s, n, n0 - segment_base(L, seg), n > 0);
                 if (st) return st;
                 ++done;
                 if (n == n0) {
@@ -1785,7 +1865,7 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
                         s->step_count = M;
                         s->current_state = 1;
                     } else {
-                        s->pipe_sub = 0;
+                        s->pipe_sub = s->pipe_seg >= S - L.R ? 1 : 0;  // resident: no recompute
                         s->pipe_k = 0;
                     }
                 } else {

@@ -28,7 +28,8 @@ EX, EY, EZ, HX, HY, HZ = range(6)
 # every entry point declared in include/ccprfdtd.h
 EXPORTS = [
     "ccpr_create", "ccpr_destroy", "ccpr_last_error", "ccpr_set_material", "ccpr_set_design",
-    "ccpr_set_design_edges",
+    "ccpr_set_design_edges", "ccpr_workspace_size_max", "ccpr_set_resident_segments",
+    "ccpr_get_resident_segments",
     "ccpr_set_source_dipole", "ccpr_set_source_planewave", "ccpr_set_objective",
     "ccpr_set_checkpointing", "ccpr_set_gradient_mode", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
     "ccpr_adjoint", "ccpr_gradient", "ccpr_gap_spectrum", "ccpr_reset", "ccpr_step", "ccpr_get_field",
@@ -87,6 +88,9 @@ def load():
         "ccpr_set_checkpointing": (_i, [_p, _i]),
         "ccpr_set_gradient_mode": (_i, [_p, _i]),
         "ccpr_workspace_size": (_i, [_p, _i, C.POINTER(C.c_uint64)]),
+        "ccpr_workspace_size_max": (_i, [_p, _i, C.POINTER(C.c_uint64)]),
+        "ccpr_set_resident_segments": (_i, [_p, _i]),
+        "ccpr_get_resident_segments": (_i, [_p, _ip]),
         "ccpr_bind_workspace": (_i, [_p, _p, C.c_uint64, _p]),
         "ccpr_forward": (_i, [_p, _i, _dp]),
         "ccpr_adjoint": (_i, [_p]),
@@ -365,6 +369,10 @@ class Solver:
     def set_checkpointing(self, every):
         self._chk(self._lib.ccpr_set_checkpointing(self._h, every), "ccpr_set_checkpointing")
 
+    def set_resident_segments(self, max_resident):
+        """At most this many segments keep the forward history (0: as many as fit)."""
+        self._chk(self._lib.ccpr_set_resident_segments(self._h, max_resident), "ccpr_set_resident_segments")
+
     def set_gradient_mode(self, mode):
         """"time" (exact discrete gradient, default) or "dft" (single-frequency
         estimator for the DFT objective)."""
@@ -376,19 +384,26 @@ class Solver:
         self._chk(self._lib.ccpr_workspace_size(self._h, nsteps, C.byref(b)), "ccpr_workspace_size")
         return int(b.value)
 
+    def workspace_size_max(self, nsteps):
+        b = C.c_uint64(0)
+        self._chk(self._lib.ccpr_workspace_size_max(self._h, nsteps, C.byref(b)), "ccpr_workspace_size_max")
+        return int(b.value)
+
     def bind_workspace(self, ptr: int, nbytes: int, stream: int = 0):
         self._chk(self._lib.ccpr_bind_workspace(self._h, C.c_void_p(ptr), nbytes, C.c_void_p(stream)),
                   "ccpr_bind_workspace")
 
     def bind_torch(self, nsteps: int, device=None, extra: int = 0, reserve: int = 4 << 30):
         """Allocate the workspace as a torch uint8 CUDA tensor and bind it with
-        torch's current stream on that device.  When the full gradient history
-        does not fit in the device's free memory (less 'reserve' bytes), the
-        workspace takes what is free and the library splits the run into
-        checkpointed segments (ccpr_set_checkpointing(0), the default)."""
+        torch's current stream on that device.  It takes what the solve can use
+        (ccpr_workspace_size_max: every checkpointed segment's history resident)
+        up to the device's free memory less 'reserve' bytes; with less, the
+        library keeps as many segments resident as fit and recomputes the
+        others (or, with ccpr_set_checkpointing(0), the default, picks the
+        segmentation that recomputes least)."""
         import torch
         dev = torch.device(device or "cuda")
-        nbytes = self.workspace_size(nsteps) + extra
+        nbytes = max(self.workspace_size(nsteps), self.workspace_size_max(nsteps)) + extra
         free, _ = torch.cuda.mem_get_info(dev)
         if nbytes > free - reserve:
             nbytes = max(free - reserve, 1 << 20)
@@ -473,7 +488,10 @@ class Solver:
         a, b, c = C.c_int(0), C.c_int(0), C.c_int(0)
         self._chk(self._lib.ccpr_get_info(self._h, C.byref(a), C.byref(b), C.byref(c)),
                   "ccpr_get_info")
-        return {"segments": a.value, "segment_steps": b.value, "tile_planes": c.value}
+        r = C.c_int(0)
+        self._chk(self._lib.ccpr_get_resident_segments(self._h, C.byref(r)), "ccpr_get_resident_segments")
+        return {"segments": a.value, "segment_steps": b.value, "tile_planes": c.value,
+                "resident_segments": r.value}
 
     def set_tile_planes(self, planes):
         self._chk(self._lib.ccpr_set_tile_planes(self._h, planes), "ccpr_set_tile_planes")

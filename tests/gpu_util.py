@@ -68,7 +68,7 @@ def oracle_fields_after_steps(w: Workload, steps: int):
     return o.fields()
 
 
-def gpu_gradient(w: Workload, tile_planes=None, checkpoint_every=None, want_adjoint_fields=False):
+def gpu_gradient(w: Workload, tile_planes=None, checkpoint_every=None, want_adjoint_fields=False, resident=None):
     from paper_2305_00234_amd.solver import configure
     torch = require_gpu()
     s = configure(w)
@@ -76,6 +76,8 @@ def gpu_gradient(w: Workload, tile_planes=None, checkpoint_every=None, want_adjo
         s.set_tile_planes(tile_planes)
     if checkpoint_every is not None:
         s.set_checkpointing(checkpoint_every)
+    if resident is not None:
+        s.set_resident_segments(resident)
     s.bind_torch(w.steps)
     F = s.forward(w.steps)
     fwd = [s.field(c) for c in range(6)]

@@ -117,6 +117,19 @@ def test_workspace_size_model(built):
     assert b2 < b1
     state = 32 ** 3 * 4 * 6
     assert b2 >= b0 + 1000 * 3 * 512 * 4 + 19 * state
+    # the most the solve can use: all 20 segments' history resident, no checkpoint
+    bmax = s.workspace_size_max(20000)
+    assert bmax >= b1 - 4096 and bmax > b2
+    s.set_resident_segments(2)
+    br2 = s.workspace_size_max(20000)
+    s.set_resident_segments(3)
+    b3 = s.workspace_size_max(20000)
+    assert b2 < br2 < b3 < bmax
+    # each further resident segment adds 1000 steps of history and drops one checkpoint
+    step = br2 - b2
+    assert abs((b3 - br2) - step) <= 512
+    assert 0 < 1000 * 3 * 512 * 4 - step < 4 * state
+    assert s._lib.ccpr_set_resident_segments(s._h, -1) == L.EINVAL
     s.close()
 
 

@@ -100,8 +100,8 @@ def test_full_size_time_domain_checkpoint_invariance():
         F = objective(rho, s, w.steps, w.design_lo, w.gamma)
         F.backward()
         info = s.info()
-        say("segments", info, "F", float(F))
-        out.append((float(F), rho.grad.detach().cpu().numpy(), info["segments"]))
+        say("segments", info, "F", float(F.detach()))
+        out.append((float(F.detach()), rho.grad.detach().cpu().numpy(), info["segments"]))
         s.close()
         del s, rho, F
         torch.cuda.empty_cache()

@@ -165,18 +165,21 @@ def test_drude_dipole_32_objective_and_gradient(gamma):
 
 def test_time_objective_gradient_and_checkpoint_bitwise():
     """Time-domain objective (Eq. 2) with a window; the checkpointed gradient
-    is bit-identical to the full-history one."""
+    is bit-identical to the full-history one, whether every segment but the
+    last is recomputed, some are, or all keep the forward history."""
     w = _dipole_box(n=(40, 30, 36), npml=5, steps=300,
                     mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
     w.objective = "time"
     w.window = (40, 280)
     say("time objective", w.shape)
     F1, g1, _, _, i1 = gpu_gradient(w, tile_planes=8)
-    F2, g2, _, _, i2 = gpu_gradient(w, tile_planes=8, checkpoint_every=70)
-    say("segments", i1, i2)
-    assert i1["segments"] == 1 and i2["segments"] == 5
-    assert F1 == F2
-    assert np.array_equal(g1, g2)
+    assert i1["segments"] == 1
+    for resident, expect in ((1, 1), (3, 3), (0, 5)):
+        F2, g2, _, _, i2 = gpu_gradient(w, tile_planes=8, checkpoint_every=70, resident=resident)
+        say("segments", i1, i2)
+        assert i2["segments"] == 5 and i2["resident_segments"] == expect
+        assert F1 == F2
+        assert np.array_equal(g1, g2)
     Fo, go, _, _ = oracle_gradient(w)
     say("F", F1, Fo, "grad rel L2", rel_l2(g1, go))
     assert abs(F1 - Fo) <= FIELD_TOL * abs(Fo)
