@@ -9,7 +9,10 @@ Prints one JSON line.  value = cell-updates of the forward and adjoint runs
 for the grid kernel (ccpr_step_kernel, the one that streams every cell):
 algorithmic bytes per launch (algorithmic_bytes) over its average launch
 duration, timed with HIP events on the library's stream around every launch
-inside the timed region; "step" gives the same for whole leapfrog steps.  The CPU baseline is the FP64 oracle on a bounded
+inside the timed region; "step" gives the same for whole leapfrog steps;
+roofline.copy_GBs is the measured rate of a plain 1 GiB device copy (bytes
+read + written per second, the practical HBM ceiling) and frac_of_copy the
+grid kernel's share of it.  The CPU baseline is the FP64 oracle on a bounded
 sample of the same workload (a few forward + adjoint steps on the full grid).
 """
 from __future__ import annotations
@@ -217,6 +220,30 @@ def serving(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_rate_gbs(nbytes=1 << 30, reps=10):
+    """Measured HBM ceiling: bytes read + written per second by a plain
+    device-to-device copy of 1 GiB on torch's current stream (HIP events on
+    that stream).  None if the memory is not there."""
+    import torch
+    try:
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+    except torch.cuda.OutOfMemoryError:
+        return None
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +330,7 @@ def main():
     achieved = alg / avg_launch_s / 1e9
     sb = step_bytes(w)
     traffic = traffic_from_profile(kernel_hash(), w.name)
+    copy_gbs = copy_rate_gbs()
 
     out = {
         "metric": METRIC,
@@ -330,7 +358,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "ccpr_step_kernel",
                      "alg_bytes_per_launch": int(alg),
-                     "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": grid_launches},
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": grid_launches,
+                     "copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
+                     "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None},
         "step": {"avg_step_us": round(avg_step_s * 1e6, 2), "alg_bytes_per_step": int(sb),
                  "achieved_GBs": round(sb / avg_step_s / 1e9, 1),
                  "frac": round(sb / avg_step_s / 1e9 / HBM_PEAK_GBS, 4), "steps": launches},
