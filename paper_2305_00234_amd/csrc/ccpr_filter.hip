@@ -160,15 +160,17 @@ struct EdgeGeom {
 // sum over the taps of input component b around the output tile; 'stage'
 // fills the tile (one LDS word per position, zero outside b's edges) and
 // 'tap' consumes one staged word with its weight.  Offsets and weights are
-// uniform across the workgroup.
+// uniform across the workgroup: each z offset's cone weights (zero outside
+// the sphere) are tabulated once in LDS (wts, (2H+1)^2 words) while the
+// tile is staged, so a tap costs two LDS reads and the accumulation.
 template <typename Stage, typename Tap>
 __device__ __forceinline__ void edge_taps(int a, int b, const EdgeGeom& g, int k, float R, float R2, int H,
-                                          Stage stage, Tap tap)
+                                          float* wts, Stage stage, Tap tap)
 {
     const int tx = threadIdx.x % kFT, ty = threadIdx.x / kFT;
     const float sx = 0.5f * ((b == 0) - (a == 0)), sy = 0.5f * ((b == 1) - (a == 1)),
                 sz = 0.5f * ((b == 2) - (a == 2));
-    const int W = kFT + 2 * H;
+    const int W = kFT + 2 * H, D = 2 * H + 1;
     for (int dz = -H; dz <= H; ++dz) {
         const int kk = k + dz;
         const float fz = (float)dz + sz;
@@ -176,6 +178,12 @@ __device__ __forceinline__ void edge_taps(int a, int b, const EdgeGeom& g, int k
         if (kk < 0 || kk >= g.shp[b][2] || rz2 <= 0.f) continue;  // uniform
         __syncthreads();
         stage(kk, W);
+        for (int t = threadIdx.x; t < D * D; t += blockDim.x) {
+            const int qy = t / D, qx = t - qy * D;
+            const float fx = (float)(qx - H) + sx, fy = (float)(qy - H) + sy;
+            const float d2 = fx * fx + fy * fy + fz * fz;
+            wts[t] = d2 < R2 ? R - sqrtf(d2) : 0.f;
+        }
         __syncthreads();
         for (int dy = -H; dy <= H; ++dy) {
             const float fy = (float)dy + sy;
@@ -184,11 +192,8 @@ __device__ __forceinline__ void edge_taps(int a, int b, const EdgeGeom& g, int k
             const float rr = sqrtf(ry2);
             const int dxl = max(-H, (int)floorf(-sx - rr)), dxh = min(H, (int)ceilf(-sx + rr));
             const int rowb = (ty + H + dy) * W + (tx + H);
-            for (int dx = dxl; dx <= dxh; ++dx) {
-                const float fx = (float)dx + sx;
-                const float d2 = fx * fx + fy * fy + fz * fz;
-                if (d2 < R2) tap(rowb + dx, R - sqrtf(d2));  // uniform
-            }
+            const float* wrow = wts + (dy + H) * D + H;
+            for (int dx = dxl; dx <= dxh; ++dx) tap(rowb + dx, wrow[dx]);  // zero weight outside the sphere
         }
     }
 }
@@ -199,6 +204,7 @@ __global__ __launch_bounds__(256) void edge_filter_project_kernel(const float* _
                                                                   float eta, float tbe, float inv_den)
 {
     __shared__ float2 tile[kTWE * kTWE];  // (density, 1) on an edge of b, (0, 0) elsewhere
+    __shared__ float wts[(2 * kMaxH + 1) * (2 * kMaxH + 1)];
     const int tx = threadIdx.x % kFT, ty = threadIdx.x / kFT;
     const int i = blockIdx.x * kFT + tx, j = blockIdx.y * kFT + ty, k = blockIdx.z;
     const int gx0 = blockIdx.x * kFT - H, gy0 = blockIdx.y * kFT - H;
@@ -219,7 +225,7 @@ __global__ __launch_bounds__(256) void edge_filter_project_kernel(const float* _
             num = fmaf(w, v.x, num);
             den = fmaf(w, v.y, den);
         };
-        edge_taps(a, b, g, k, R, R2, H, stage, tap);
+        edge_taps(a, b, g, k, R, R2, H, wts, stage, tap);
     }
     if (i < g.shp[a][0] && j < g.shp[a][1]) {
         const long long n = g.off[a] + ((long long)k * g.shp[a][1] + j) * g.shp[a][0] + i;
@@ -238,6 +244,7 @@ __global__ __launch_bounds__(256) void edge_filter_project_grad_kernel(const dou
                                                                        double inv_den)
 {
     __shared__ double tile[kTWE * kTWE];  // v = dF/drho_b * drho_b/drho_t / W on an edge of b, 0 elsewhere
+    __shared__ float wts[(2 * kMaxH + 1) * (2 * kMaxH + 1)];
     const int tx = threadIdx.x % kFT, ty = threadIdx.x / kFT;
     const int i = blockIdx.x * kFT + tx, j = blockIdx.y * kFT + ty, k = blockIdx.z;
     const int gx0 = blockIdx.x * kFT - H, gy0 = blockIdx.y * kFT - H;
@@ -259,7 +266,7 @@ __global__ __launch_bounds__(256) void edge_filter_project_grad_kernel(const dou
             }
         };
         auto tap = [&](int idx, float w) { acc = fma((double)w, tile[idx], acc); };
-        edge_taps(a, b, g, k, R, R2, H, stage, tap);
+        edge_taps(a, b, g, k, R, R2, H, wts, stage, tap);
     }
     if (i < g.shp[a][0] && j < g.shp[a][1]) gout[g.off[a] + ((long long)k * g.shp[a][1] + j) * g.shp[a][0] + i] = acc;
 }

@@ -164,3 +164,24 @@ def test_edge_gradient_mirror_symmetry_and_oracle():
     assert abs(F - Fo) <= 1e-5 * abs(Fo)
     assert err <= GRAD_TOL
     assert asym_x <= 1e-4 and asym_z <= 1e-4
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_edge_design_dipole_on_far_face(axis):
+    """A dipole on the far x face of the per-edge box (cell lo_x + N_x): along
+    x that edge is not a design edge (vacuum, driven through the FP64 source
+    shadow), along y it is a dispersive design edge carrying the source."""
+    require_gpu()
+    w = _aniso_dipole_case(steps=250)
+    lo, d = w.design_lo, w.design_dims
+    w.dipole_cell, w.dipole_axis = (lo[0] + d[0], lo[1] + 3, lo[2] + 4), axis
+    g = gpu_fields_after_steps(w, 120)
+    o = oracle_fields_after_steps(w, 120)
+    st, _, _ = field_errors(g, o)
+    F, gg, _, _, _ = gpu_gradient(w)
+    Fo, go, _, _ = oracle_gradient(w)
+    err = rel_l2(_flat(gg), _flat(go))
+    say("far-face dipole axis", axis, "fields", st, "F", F, Fo, "grad rel L2", err)
+    assert st <= FIELD_TOL
+    assert abs(F - Fo) <= 1e-5 * abs(Fo)
+    assert err <= GRAD_TOL
