@@ -7,9 +7,10 @@
 // The filter is a 3-D stencil over the sphere |d| < R (R <= 17 voxels).  A
 // workgroup owns a 16 x 16 tile of one output plane; for every z offset it
 // stages the input plane's tile plus an R-wide halo in LDS as (value, inside)
-// pairs and each lane sums the disk of that offset straight from LDS, so
-// every input word is read from HBM once per (output plane, offset) workgroup
-// and the taps cost LDS reads only.  Loop bounds are uniform per workgroup.
+// pairs, with the cone weights of that offset's disk, and each lane sums the
+// disk straight from LDS, so every input word is read from HBM once per
+// (output plane, offset) workgroup and the taps cost LDS reads only.  Loop
+// bounds are uniform per workgroup.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,9 +31,10 @@ __global__ __launch_bounds__(256) void filter_project_kernel(const float* __rest
                                                              float inv_den)
 {
     __shared__ float2 tile[kTW * kTW];  // (density, 1) inside the box, (0, 0) outside
+    __shared__ float wts[(2 * kMaxRi + 1) * (2 * kMaxRi + 1)];  // cone weights of one z offset
     const int tx = threadIdx.x % kFT, ty = threadIdx.x / kFT;
     const int i = blockIdx.x * kFT + tx, j = blockIdx.y * kFT + ty, k = blockIdx.z;
-    const int W = kFT + 2 * Ri;
+    const int W = kFT + 2 * Ri, D = 2 * Ri + 1;
     const int gx0 = blockIdx.x * kFT - Ri, gy0 = blockIdx.y * kFT - Ri;
     float num = 0.f, den = 0.f;
     for (int dz = -Ri; dz <= Ri; ++dz) {
@@ -46,15 +48,19 @@ __global__ __launch_bounds__(256) void filter_project_kernel(const float* __rest
             const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
             tile[t] = in ? make_float2(rho[((long long)kk * ny + gy) * nx + gx], 1.f) : make_float2(0.f, 0.f);
         }
+        for (int t = threadIdx.x; t < D * D; t += blockDim.x) {
+            const int qy = t / D - Ri, qx = t % D - Ri;
+            wts[t] = R - sqrtf((float)(qx * qx + qy * qy + dz * dz));  // used inside the sphere only
+        }
         __syncthreads();
         for (int dy = -Ri; dy <= Ri; ++dy) {
             const float ry2 = rz2 - (float)(dy * dy);
             if (ry2 <= 0.f) continue;  // uniform
             const int dxm = (int)ceilf(sqrtf(ry2)) - 1;  // dx^2 < ry2
-            const int d2yz = dy * dy + dz * dz;
             const float2* row = tile + (ty + Ri + dy) * W + (tx + Ri);
+            const float* wrow = wts + (dy + Ri) * D + Ri;
             for (int dx = -dxm; dx <= dxm; ++dx) {
-                const float w = R - sqrtf((float)(dx * dx + d2yz));
+                const float w = wrow[dx];
                 const float2 v = row[dx];
                 num = fmaf(w, v.x, num);
                 den = fmaf(w, v.y, den);
@@ -80,9 +86,10 @@ __global__ __launch_bounds__(256) void filter_project_grad_kernel(const double* 
                                                                   double beta, double eta, double inv_den)
 {
     __shared__ double tile[kTW * kTW];
+    __shared__ float wts[(2 * kMaxRi + 1) * (2 * kMaxRi + 1)];  // cone weights of one z offset
     const int tx = threadIdx.x % kFT, ty = threadIdx.x / kFT;
     const int i = blockIdx.x * kFT + tx, j = blockIdx.y * kFT + ty, k = blockIdx.z;
-    const int W = kFT + 2 * Ri;
+    const int W = kFT + 2 * Ri, D = 2 * Ri + 1;
     const int gx0 = blockIdx.x * kFT - Ri, gy0 = blockIdx.y * kFT - Ri;
     double acc = 0.0;
     for (int dz = -Ri; dz <= Ri; ++dz) {
@@ -101,17 +108,18 @@ __global__ __launch_bounds__(256) void filter_project_grad_kernel(const double* 
             }
             tile[t] = v;
         }
+        for (int t = threadIdx.x; t < D * D; t += blockDim.x) {
+            const int qy = t / D - Ri, qx = t % D - Ri;
+            wts[t] = R - sqrtf((float)(qx * qx + qy * qy + dz * dz));
+        }
         __syncthreads();
         for (int dy = -Ri; dy <= Ri; ++dy) {
             const float ry2 = rz2 - (float)(dy * dy);
             if (ry2 <= 0.f) continue;  // uniform
             const int dxm = (int)ceilf(sqrtf(ry2)) - 1;
-            const int d2yz = dy * dy + dz * dz;
             const double* row = tile + (ty + Ri + dy) * W + (tx + Ri);
-            for (int dx = -dxm; dx <= dxm; ++dx) {
-                const float w = R - sqrtf((float)(dx * dx + d2yz));
-                acc = fma((double)w, row[dx], acc);
-            }
+            const float* wrow = wts + (dy + Ri) * D + Ri;
+            for (int dx = -dxm; dx <= dxm; ++dx) acc = fma((double)wrow[dx], row[dx], acc);
         }
     }
     if (i < nx && j < ny) g[((long long)k * ny + j) * nx + i] = acc;
