@@ -185,3 +185,20 @@ def test_edge_design_dipole_on_far_face(axis):
     assert st <= FIELD_TOL
     assert abs(F - Fo) <= 1e-5 * abs(Fo)
     assert err <= GRAD_TOL
+
+
+def test_edge_gradient_checkpointed_bitwise():
+    """Per-edge design, time objective: segments recomputed from checkpoints
+    (one resident segment), some resident, or the whole history give the
+    same gradient bit for bit."""
+    require_gpu()
+    w = _aniso_dipole_case(steps=210)
+    w.objective = "time"
+    w.window = (20, 200)
+    F1, g1, _, _, i1 = gpu_gradient(w)
+    for resident in (1, 2):
+        F2, g2, _, _, i2 = gpu_gradient(w, checkpoint_every=50, resident=resident)
+        say("per-edge checkpointing", i1, i2)
+        assert i2["segments"] == 5 and i2["resident_segments"] == resident
+        assert F1 == F2
+        assert np.array_equal(_flat(g1), _flat(g2))
