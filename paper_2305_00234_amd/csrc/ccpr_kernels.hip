@@ -11,11 +11,12 @@
 //    y/z CPML memories, as two concurrent launches (tiles that touch a y or z
 //    CPML layer, interior tiles).  For design and source cells it also stores
 //    the E drive S curl H';
-//  - ccpr_aux_kernel, one thread per design voxel, redoes those cells' E
-//    update from E^n and the drive: CCPR pole-pair currents, source current,
-//    the forward gradient record and the adjoint gradient correlation (Eq.
-//    Gradient_FDTD, or the running transforms of the DFT-mode estimator), and
-//    the gap monitor;
+//  - ccpr_aux_kernel, one thread per cell of the design box (a per-edge
+//    design's box of N + 1 cells, each edge with its own density), redoes
+//    those cells' E update from E^n and the drive: CCPR pole-pair currents,
+//    source current, the forward gradient record and the adjoint gradient
+//    correlation (Eq. Gradient_FDTD, or the running transforms of the
+//    DFT-mode estimator), and the gap monitor;
 //  - ccpr_post_kernel: the x-CPML correction of E^{n+1}, the source and gap
 //    cells outside the design and the TF/SF E faces; ccpr_post_fused_kernel
 //    does the same and also the next step's pre work when that step follows

@@ -214,7 +214,6 @@ int dft_window(int M, double omega, double dt)
     return std::min(L, M);
 }
 
-// Workspace layout for a solve of M steps (M = 0: stepping only).
 // density values and gradient values: one per voxel, or one per design edge
 long long n_rho(const ccpr_solver* s) { return s->edge ? s->nrho : s->nd; }
 
@@ -242,6 +241,8 @@ size_t stage_bytes(const ccpr_solver* s)
     return std::max((size_t)s->ncell * 4, (size_t)std::max(n_rho(s), 1LL) * 8);
 }
 
+// Workspace layout for a solve of M steps (M = 0: stepping only) in segments
+// of K_req steps (0: one segment) with R_req resident segments.
 Layout make_layout(const ccpr_solver* s, int M, int K_req, int R_req = 1)
 {
     Layout L{};
