@@ -100,7 +100,10 @@ const char* ccpr_last_error(const ccpr_solver* s);
  * formulation").  slot 1 is the material at rho = 0, slot 2 at rho = 1
  * (Eqs. eps_mixed, sigma_mixed, Poles_mixed).  a, c: npairs complex numbers as
  * (re, im) doubles [1/s].  Unset slots are vacuum (eps_inf 1, no poles).
- * CCPR_EINVAL for axis/slot out of range, npairs < 0, or non-finite values;
+ * CCPR_EINVAL for axis/slot out of range, npairs < 0, non-finite values or
+ * a pole with Re a > 0 (it grows on its own: not a passive material; other
+ * non-passive sets, e.g. a negative static susceptibility, make the fields
+ * grow and the next ccpr_forward return CCPR_EDIVERGED);
  * CCPR_ENOTSUP if the two slots together exceed CCPR_MAX_PAIRS_PER_AXIS on an
  * axis. */
 ccpr_status ccpr_set_material(ccpr_solver* s, int slot, int axis, double eps_inf,
@@ -216,7 +219,9 @@ ccpr_status ccpr_bind_workspace(ccpr_solver* s, void* dev_ptr, uint64_t bytes, v
 
 /* Forward run of nsteps from zero fields, recording the gap monitor and the
  * gradient history (DFT gradient mode: its transform), then the objective
- * (synchronises the stream to return *objective_out, which may be NULL). */
+ * (synchronises the stream to return *objective_out, which may be NULL).
+ * CCPR_EDIVERGED when the objective is not finite (fields that overflowed:
+ * a non-passive material); the solve is then not usable for ccpr_adjoint. */
 ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out);
 
 /* Adjoint run (same update, zero initial fields, time-reversed source

@@ -1319,6 +1319,8 @@ ccpr_status ccpr_set_material(ccpr_solver* s, int slot, int axis, double eps_inf
         for (int q = 0; q < 2; ++q)
             if (!std::isfinite(a[2 * p + q]) || !std::isfinite(c[2 * p + q]))
                 return fail(s, CCPR_EINVAL, "non-finite pole or residue");
+        // a pole in the right half plane grows without any field driving it
+        if (a[2 * p] > 0) return fail(s, CCPR_EINVAL, "pole pair %d has Re a > 0 (a growing, non-passive pole)", p);
         m.a.push_back(cd(a[2 * p], a[2 * p + 1]));
         m.c.push_back(cd(c[2 * p], c[2 * p + 1]));
     }

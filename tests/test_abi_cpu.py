@@ -64,6 +64,10 @@ def test_configuration_validation_and_call_order(built):
     with pytest.raises(L.CcprError) as e:
         s.set_material(2, 0, 1.0, 0.0, [-1e14] * 9, [1e17] * 9)
     assert e.value.status == L.ENOTSUP
+    with pytest.raises(L.CcprError) as e:          # a growing pole (Re a > 0): not passive
+        s.set_material(2, 0, 1.0, 0.0, [complex(1e12, 3e15)], [1e17])
+    assert e.value.status == L.EINVAL
+    s.set_material(2, 0, 1.0, 0.0, [complex(0.0, 3e15)], [complex(0.0, -1e30)])  # lossless Lorentz pair
     rho = np.full((4, 4, 4), 0.5, np.float32)
     with pytest.raises(L.CcprError) as e:          # inside the CPML
         s.set_design((2, 12, 12), rho)

@@ -1,0 +1,48 @@
+"""Failure detection forced from the host, with every kernel exiting
+normally: a non-passive material (negative static susceptibility) makes the
+fields grow until they overflow; ccpr_forward reports CCPR_EDIVERGED, the
+adjoint refuses to run on that solve, and the solver runs again once the
+material is passive."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2305_00234_amd import inputs as I
+from tests.gpu_util import require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299792458.0
+
+
+def test_active_medium_reports_divergence_and_recovers():
+    require_gpu()
+    from paper_2305_00234_amd import lib as L
+    from paper_2305_00234_amd.solver import configure
+    w = I.drude_dipole_32(steps=2000, n=24, npml=0, gamma=0.0)
+    w.design_lo = (8, 8, 8)
+    w.rho = np.ones((8, 8, 8), np.float32)
+    w.gap_lo, w.gap_dims = (11, 11, 11), (2, 2, 2)
+    w.dipole_cell = (6, 12, 12)
+    active = I.lorentz(1.0, -3.0, 2 * math.pi * C0 / 500e-9, 1e13)  # static eps 1 - 3 < 0
+    w.mat2 = (active,) * 3
+    s = configure(w)
+    s.bind_torch(w.steps)
+    with pytest.raises(L.CcprError) as e:
+        s.forward(w.steps)
+    say("active medium:", e.value)
+    assert e.value.status == L.EDIVERGED
+    with pytest.raises(L.CcprError) as e:
+        s.adjoint()
+    assert e.value.status == L.ESTATE
+    # a passive material on the same solver and workspace runs normally
+    for ax in range(3):
+        m = I.GOLD_TABLE1
+        s.set_material(2, ax, m.eps_inf, m.sigma, m.a, m.c)
+    F = s.forward(w.steps)
+    s.adjoint()
+    g = s.gradient()
+    s.close()
+    say("passive again: F", F)
+    assert np.isfinite(F) and F > 0 and np.all(np.isfinite(g))
