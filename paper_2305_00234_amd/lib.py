@@ -393,17 +393,20 @@ class Solver:
         self._chk(self._lib.ccpr_bind_workspace(self._h, C.c_void_p(ptr), nbytes, C.c_void_p(stream)),
                   "ccpr_bind_workspace")
 
-    def bind_torch(self, nsteps: int, device=None, extra: int = 0, reserve: int = 4 << 30):
+    def bind_torch(self, nsteps: int, device=None, extra: int = 0, reserve: int = 4 << 30,
+                   greedy: bool = True):
         """Allocate the workspace as a torch uint8 CUDA tensor and bind it with
         torch's current stream on that device.  It takes what the solve can use
-        (ccpr_workspace_size_max: every checkpointed segment's history resident)
-        up to the device's free memory less 'reserve' bytes; with less, the
-        library keeps as many segments resident as fit and recomputes the
-        others (or, with ccpr_set_checkpointing(0), the default, picks the
-        segmentation that recomputes least)."""
+        (ccpr_workspace_size_max: every checkpointed segment's history resident;
+        greedy=False: only ccpr_workspace_size) up to the device's free memory
+        less 'reserve' bytes; with less, the library keeps as many segments
+        resident as fit and recomputes the others (or, with
+        ccpr_set_checkpointing(0), the default, picks the segmentation that
+        recomputes least)."""
         import torch
         dev = torch.device(device or "cuda")
-        nbytes = max(self.workspace_size(nsteps), self.workspace_size_max(nsteps)) + extra
+        want = self.workspace_size_max(nsteps) if greedy else 0
+        nbytes = max(self.workspace_size(nsteps), want) + extra
         free, _ = torch.cuda.mem_get_info(dev)
         if nbytes > free - reserve:
             nbytes = max(free - reserve, 1 << 20)
