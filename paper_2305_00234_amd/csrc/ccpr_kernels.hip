@@ -801,7 +801,20 @@ __global__ __launch_bounds__(256) void ccpr_post_fused_kernel(const StepArgs a, 
     const unsigned x = (unsigned)u * np2 + xs;
     const unsigned sz = (unsigned)a.nz * a.ny * np2;
     float hy = 0.f, hz = 0.f, ey = 0.f, ez = 0.f;
+    // loads of the H pre-correction that nothing in this launch writes, issued
+    // with the first phase's: the other H-side psi buffer, its coefficients
+    // and, for the last cell of the low layer, E^{n+1} just inside the layer
+    float4 cfh = make_float4(0.f, 0.f, 0.f, 0.f);
+    float ph0 = 0.f, ph1 = 0.f, eyr = 0.f, ezr = 0.f;  // E^{n+1} at x+1 (zero past the high wall)
     if (valid) {
+        cfh = c.pmlH[0][i];
+        const float* pin = c.psiH[a.psi_in ^ 1][0];
+        ph0 = pin[x];
+        ph1 = pin[sz + x];
+        if (xs == a.npml - 1) {
+            eyr = ldf(a.Eo, o + 4 + cs);
+            ezr = ldf(a.Eo, o + 4 + 2 * cs);
+        }
         hy = ldf(a.Ho, o + cs);
         hz = ldf(a.Ho, o + 2 * cs);
         ey = ldf(a.Eo, o + cs);
@@ -829,24 +842,18 @@ __global__ __launch_bounds__(256) void ccpr_post_fused_kernel(const StepArgs a, 
     }
     __syncthreads();
     if (!valid) return;
-    float eyr = 0.f, ezr = 0.f;  // E^{n+1} at x+1 (zero past the high wall)
-    if (xs == a.npml - 1) {
-        eyr = ldf(a.Eo, o + 4 + cs);
-        ezr = ldf(a.Eo, o + 4 + 2 * cs);
-    } else if (xs != np2 - 1) {
+    if (xs != a.npml - 1 && xs != np2 - 1) {
         eyr = se[0][tid + 1];
         ezr = se[1][tid + 1];
     }
     const float dEz = ezr - ez, dEy = eyr - ey;
-    const float4 cf = c.pmlH[0][i];
-    const float* pin = c.psiH[a.psi_in ^ 1][0];
     float* pout = c.psiH[a.psi_in][0];
-    const float p0 = fmaf(cf.x, pin[x], cf.y * dEz);
-    const float p1 = fmaf(cf.x, pin[sz + x], cf.y * dEy);
+    const float p0 = fmaf(cfh.x, ph0, cfh.y * dEz);
+    const float p1 = fmaf(cfh.x, ph1, cfh.y * dEy);
     st_stream<NT>(&pout[x], p0);
     st_stream<NT>(&pout[sz + x], p1);
-    stf_nt<NT>(a.Ho, o + cs, hy + a.S * fmaf(cf.z - 1.f, dEz, p0));
-    stf_nt<NT>(a.Ho, o + 2 * cs, hz - a.S * fmaf(cf.z - 1.f, dEy, p1));
+    stf_nt<NT>(a.Ho, o + cs, hy + a.S * fmaf(cfh.z - 1.f, dEz, p0));
+    stf_nt<NT>(a.Ho, o + 2 * cs, hz - a.S * fmaf(cfh.z - 1.f, dEy, p1));
 }
 
 // DFT-mode gradient of each design voxel (see ccpr_set_gradient_mode): the
