@@ -56,11 +56,20 @@ def algorithmic_bytes(w):
     are counted in step_bytes, not here."""
     nx, ny, nz = w.shape
     n = nx * ny * nz
-    nd = int(np.prod(w.design_dims))
+    nd = design_box_cells(w)
     p = w.npml
     yz_layer_cells = 2 * p * nx * nz + 2 * p * nx * ny if p else 0
     src_cells = 1 if w.source == "dipole" else 0
     return 48 * n + 32 * yz_layer_cells + 12 * (nd + src_cells)
+
+
+def design_box_cells(w):
+    """Cells the design kernels run over: the design voxels, or for a per-edge
+    design the box of N + 1 cells per axis that holds every design edge."""
+    d = w.design_dims
+    if w.rho_edges is not None:
+        return int((d[0] + 1) * (d[1] + 1) * (d[2] + 1))
+    return int(np.prod(d))
 
 
 def step_bytes(w):
@@ -72,18 +81,21 @@ def step_bytes(w):
     gradient history: 12 B record (forward), 12 B read + 16 B FP64 accumulator
     read/write (adjoint); DFT-mode gradient instead: 24 B complex transform
     of T read + write (forward), 24 B projection of the adjoint E read + write
-    over the fit window (about half the adjoint steps)."""
+    over the fit window (about half the adjoint steps).  Per-edge designs:
+    the design box of N + 1 cells, three densities and three accumulators per
+    cell."""
     nx, ny, nz = w.shape
-    nd = int(np.prod(w.design_dims))
+    nd = design_box_cells(w)
+    per_cell = 3 if w.rho_edges is not None else 1
     pairs = sum(w.mat1[a].npairs + w.mat2[a].npairs for a in range(3))
     p = w.npml
     x_layer_cells = 2 * p * ny * nz if p else 0
-    design = (16 * pairs + 4 + 36) * nd
+    design = (16 * pairs + 4 * per_cell + 36) * nd
     xpml = (32 + 16) * x_layer_cells
     if w.gradient == "dft":
         record = (48 * nd + 48 * nd * 0.5) / 2.0
     else:
-        record = (12 * nd + (12 + 16) * nd) / 2.0
+        record = (12 * nd + (12 + 16 * per_cell) * nd) / 2.0
     return algorithmic_bytes(w) + design + xpml + record
 
 
@@ -253,6 +265,8 @@ def main():
     ap.add_argument("--solve-steps", type=int, default=None,
                     help="leapfrog steps per solve (default: the workload's)")
     ap.add_argument("--tile-planes", type=int, default=None)
+    ap.add_argument("--per-edge", action="store_true",
+                    help="one density per E edge (seeded uniform) instead of per voxel")
     ap.add_argument("--gradient", choices=["time", "dft"], default="time",
                     help="time: exact discrete gradient (default); dft: single-frequency estimator")
     ap.add_argument("--cpu-sample-steps", type=int, default=4)
@@ -281,12 +295,15 @@ def main():
 
     w = workload_by_name(args.workload, args.solve_steps)
     w.gradient = args.gradient
+    if args.per_edge:
+        from paper_2305_00234_amd import inputs as I
+        w.rho_edges = I.random_edge_densities(w.design_dims, seed=7)
+        w.name += "_edges"
     M = w.steps
     s = solver_for(w)
     if args.tile_planes:
         s.set_tile_planes(args.tile_planes)
-    d = w.design_dims
-    grad = torch.empty((d[2], d[1], d[0]), dtype=torch.float64, device="cuda")
+    grad = torch.empty(s.gradient_size, dtype=torch.float64, device="cuda")
 
     def one_solve():
         F = s.forward(M)
@@ -350,6 +367,7 @@ def main():
                    "pole_pairs_per_axis": w.max_pairs(), "cpml": w.npml,
                    "source": w.source, "objective": w.objective,
                    "gradient": "time-exact" if w.gradient == "time" else "dft",
+                   "design_variables": "per-edge" if w.rho_edges is not None else "per-voxel",
                    "history_segments": info["segments"], "tile_planes": info["tile_planes"]},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 2)},
