@@ -320,6 +320,27 @@ def test_full_size_320_gradient_vs_oracle():
     assert err <= GRAD_TOL
 
 
+def test_full_size_512_time_domain_fields_vs_oracle():
+    """The 512x512x256 time-domain workload's grid at full size (256x256x64
+    design of Table-1 gold, 12-cell CPML) in the benchmark's launch
+    configuration: a dipole on the design's edge drives the dispersive
+    voxels from the first step; all six field components after 16 steps
+    against the oracle on the full grid."""
+    w = I.gold_gap_timedomain_512(steps=16)
+    w.source = "dipole"
+    lo, d = w.design_lo, w.design_dims
+    w.dipole_cell = (lo[0] - 2, lo[1] + d[1] // 2, lo[2] + d[2] // 2)
+    w.dipole_axis = 0
+    t = (np.arange(w.steps) + 0.5) * w.dt
+    w.wave = I.gaussian_sine(t, 300e-9, 0.1e-15, 0.1e-15, amp=1e9)
+    say("full-size 512x512x256 fields, 16 steps")
+    g = gpu_fields_after_steps(w, 16)
+    o = oracle_fields_after_steps(w, 16)
+    st, eE, eH = field_errors(g, o)
+    say("rel L2 state", st, "E", eE, "H", eH)
+    assert st <= FIELD_TOL
+
+
 def test_full_size_384_anisotropic_fields_vs_oracle():
     """The 384^3 anisotropic two-material grid (192x192x96 design, 4 pole
     pairs per component, different on each axis) at full size: a dipole on
