@@ -80,3 +80,71 @@ def test_random_config_matches_oracle(seed):
         w.objective, "dipole", w.dipole_axis, w.dipole_cell, "F", F, Fo, "grad", err)
     assert Fo > 0 and abs(F - Fo) <= 1e-5 * abs(Fo)
     assert err <= 1e-3
+
+
+def random_planewave_case(seed):
+    """A TF/SF plane wave of random axis, direction and polarisation around a
+    random design (inside the total-field box, which lies in the
+    background); DFT objective, time-exact or DFT-mode gradient."""
+    rng = np.random.default_rng(5000 + seed)
+    w = random_case(seed + 100)
+    n = w.shape
+    npml = w.npml
+    d = w.design_dims
+    box = 1 if w.rho_edges is not None else 0
+    # TF/SF box [tl, th] strictly inside the grid and outside the CPML, with
+    # the design (and the gap) at least one cell inside it
+    tl, th = [], []
+    for a in range(3):
+        lo_min, hi_max = npml + 1, n[a] - npml - 2
+        dl, dh = w.design_lo[a], w.design_lo[a] + d[a] + box
+        gl, gh = w.gap_lo[a], w.gap_lo[a] + w.gap_dims[a]
+        inner_lo, inner_hi = min(dl, gl) - 1, max(dh, gh) + 1
+        tl.append(int(rng.integers(lo_min, max(lo_min + 1, inner_lo + 1))) if inner_lo >= lo_min else lo_min)
+        th.append(int(rng.integers(min(inner_hi, hi_max), hi_max + 1)))
+    w.source = "planewave"
+    w.tfsf_lo, w.tfsf_hi = tuple(tl), tuple(th)
+    w.pw_prop_axis = int(rng.integers(0, 3))
+    w.pw_sign = int(rng.choice([-1, 1]))
+    w.pw_pol_axis = int(rng.choice([a for a in range(3) if a != w.pw_prop_axis]))
+    t = np.arange(w.steps + 1) * w.dt
+    lam = 2 * math.pi * C0 / w.omega
+    w.wave = I.gaussian_sine(t, lam, 1.0e-15, 1.5e-15, amp=1.0)
+    w.objective = "dft"
+    w.gradient = "dft" if rng.random() < 0.4 else "time"
+    if w.gradient == "dft":
+        w.steps = max(w.steps, 400)
+        t = np.arange(w.steps + 1) * w.dt
+        w.wave = I.gaussian_sine(t, lam, 1.0e-15, 1.5e-15, amp=1.0)
+    return w
+
+
+def _tfsf_ok(w):
+    """Whether the TF/SF box keeps the design and gap strictly inside and
+    stays strictly inside the grid outside the CPML."""
+    d, box = w.design_dims, 1 if w.rho_edges is not None else 0
+    for a in range(3):
+        if not (w.npml + 1 <= w.tfsf_lo[a] < w.tfsf_hi[a] <= w.shape[a] - w.npml - 2):
+            return False
+        lo = min(w.design_lo[a], w.gap_lo[a])
+        hi = max(w.design_lo[a] + d[a] + box, w.gap_lo[a] + w.gap_dims[a])
+        if not (w.tfsf_lo[a] < lo and hi < w.tfsf_hi[a]):
+            return False
+    return True
+
+
+PW_SEEDS = [s for s in range(40) if _tfsf_ok(random_planewave_case(s))][:12]
+
+
+@pytest.mark.parametrize("seed", PW_SEEDS)
+def test_random_planewave_config_matches_oracle(seed):
+    require_gpu()
+    w = random_planewave_case(seed)
+    F, g, _, _, _ = gpu_gradient(w)
+    Fo, go, _, _ = oracle_gradient(w)
+    flat = (lambda x: np.concatenate([np.ravel(a) for a in x])) if w.rho_edges is not None else np.ravel
+    err = rel_l2(flat(g), flat(go))
+    say("random plane wave", seed, w.shape, "npml", w.npml, "prop", w.pw_prop_axis, w.pw_sign, "pol",
+        w.pw_pol_axis, "tfsf", w.tfsf_lo, w.tfsf_hi, "gradient", w.gradient, "F", F, Fo, "grad", err)
+    assert Fo > 0 and abs(F - Fo) <= 1e-5 * abs(Fo)
+    assert err <= 1e-3
