@@ -359,3 +359,37 @@ def test_full_size_384_anisotropic_fields_vs_oracle():
     st, eE, eH = field_errors(g, o)
     say("rel L2 state", st, "E", eE, "H", eH)
     assert st <= FIELD_TOL
+
+
+@pytest.mark.parametrize("pairs", [(4, 4), (2, 3), (3, 4)])
+def test_most_pole_pairs_per_axis_gradient(pairs):
+    """The largest pole-pair counts per axis (both materials together: 8 =
+    the library's limit, 5 and 7, which run the 6- and 8-pair instances of the
+    design kernel), different per axis, with gamma: fields, objective and
+    gradient against the oracle."""
+    p1, p2 = pairs
+
+    def lorentz_set(count, scale, shift):
+        # passive Lorentz pairs at spread resonances
+        return [I.lorentz(1.0, 0.3 * scale, 2 * math.pi * I.C0 / (180e-9 + shift + 60e-9 * q), 2e14 * (1 + q))
+                for q in range(count)]
+
+    def combine(eps_inf, sigma, mats):
+        a = tuple(x for m in mats for x in m.a)
+        c = tuple(x for m in mats for x in m.c)
+        return I.CCPRMaterial(eps_inf, sigma, a, c)
+
+    m1 = combine(1.8, 0.0, lorentz_set(p1, 1.0, 0.0))
+    gold_extra = lorentz_set(max(0, p2 - 3), 0.5, 40e-9)
+    m2x = combine(I.GOLD_TABLE1.eps_inf, I.GOLD_TABLE1.sigma, [I.GOLD_TABLE1] + gold_extra)
+    m2y = combine(1.0, I.GOLD_TABLE1.sigma, [I.GOLD_TABLE1.first_pairs(min(3, p2))] + lorentz_set(max(0, p2 - 3), 0.8, 10e-9))
+    m2z = combine(2.5, 0.0, lorentz_set(p2, 1.2, 20e-9))
+    w = _dipole_box(n=(34, 29, 31), npml=4, steps=200, mats=((m1,) * 3, (m2x, m2y, m2z)))
+    say("pole pairs per axis", [w.mat1[a].npairs + w.mat2[a].npairs for a in range(3)])
+    Fg, gg, fg, _, _ = gpu_gradient(w)
+    Fo, go, fo, _ = oracle_gradient(w)
+    st, _, _ = field_errors(fg, fo)
+    say("fields", st, "F", Fg, Fo, "grad rel L2", rel_l2(gg, go))
+    assert st <= FIELD_TOL
+    assert abs(Fg - Fo) <= FIELD_TOL * abs(Fo)
+    assert rel_l2(gg, go) <= GRAD_TOL
