@@ -46,3 +46,64 @@ def test_active_medium_reports_divergence_and_recovers():
     s.close()
     say("passive again: F", F)
     assert np.isfinite(F) and F > 0 and np.all(np.isfinite(g))
+
+
+def test_invalid_device_densities_reported_at_the_next_run():
+    """Densities handed over in device memory are checked on the device (the
+    host cannot see them without a copy): a NaN or a value above 1 is
+    reported by the next forward run as CCPR_EINVAL, for per-voxel and
+    per-edge designs alike, and valid densities then run normally."""
+    torch = require_gpu()
+    from paper_2305_00234_amd import lib as L
+    from paper_2305_00234_amd.solver import configure
+    w = I.drude_dipole_32(steps=120)
+    s = configure(w)
+    s.bind_torch(w.steps)
+    bad = torch.tensor(w.rho, device="cuda")
+    bad[1, 2, 3] = float("nan")
+    s.set_design(w.design_lo, bad, w.gamma)
+    with pytest.raises(L.CcprError) as e:
+        s.forward(w.steps)
+    assert e.value.status == L.EINVAL
+    dims = w.design_dims
+    n = L.edge_count(dims)
+    bad_e = torch.rand(n, device="cuda")
+    bad_e[n // 2] = 1.5
+    s.set_design_edges(w.design_lo, dims, bad_e, w.gamma)
+    with pytest.raises(L.CcprError) as e:
+        s.forward(w.steps)
+    assert e.value.status == L.EINVAL
+    s.set_design(w.design_lo, torch.tensor(w.rho, device="cuda"), w.gamma)
+    F = s.forward(w.steps)
+    s.close()
+    assert np.isfinite(F) and F > 0
+
+
+def test_empty_and_out_of_order_calls():
+    """No steps, no forward before the adjoint, no gradient before the
+    adjoint: rejected with the documented codes, nothing launched."""
+    require_gpu()
+    from paper_2305_00234_amd import lib as L
+    from paper_2305_00234_amd.solver import configure
+    w = I.drude_dipole_32(steps=50)
+    s = configure(w)
+    s.bind_torch(w.steps)
+    with pytest.raises(L.CcprError) as e:
+        s.forward(0)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.CcprError) as e:
+        s.adjoint()
+    assert e.value.status == L.ESTATE
+    with pytest.raises(L.CcprError) as e:
+        s.gradient()
+    assert e.value.status == L.ESTATE
+    s.step(0)                       # zero steps: a no-op
+    assert s.step_count == 0
+    F = s.forward(w.steps)
+    with pytest.raises(L.CcprError) as e:
+        s.gradient()
+    assert e.value.status == L.ESTATE
+    s.adjoint()
+    g = s.gradient()
+    s.close()
+    assert np.isfinite(F) and np.all(np.isfinite(g))
