@@ -269,7 +269,8 @@ def main():
                     help="one density per E edge (seeded uniform) instead of per voxel")
     ap.add_argument("--gradient", choices=["time", "dft"], default="time",
                     help="time: exact discrete gradient (default); dft: single-frequency estimator")
-    ap.add_argument("--cpu-sample-steps", type=int, default=4)
+    ap.add_argument("--cpu-sample-steps", type=int, default=10,
+                    help="forward + adjoint steps of the oracle sample (about 10 s on 16 cores at 320^3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=0,
                     help="run the serving trace with this many requests instead")
