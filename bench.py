@@ -8,8 +8,9 @@ Prints one JSON line.  value = cell-updates of the forward and adjoint runs
 (cells x 2 x 6000 per solve) per second, in millions.  The roofline object is
 for the grid kernel (ccpr_step_kernel, the one that streams every cell):
 algorithmic bytes per launch (algorithmic_bytes) over its average launch
-duration, timed with HIP events on the library's stream around every launch
-inside the timed region; "step" gives the same for whole leapfrog steps;
+duration, timed with HIP events on the library's streams around the grid
+launches inside the timed region (every 10th pass by default, --timing-every);
+"step" gives the same for whole leapfrog steps;
 roofline.copy_GBs is the measured rate of a plain 1 GiB device copy (bytes
 read + written per second, the practical HBM ceiling) and frac_of_copy the
 grid kernel's share of it.  The CPU baseline is the FP64 oracle on a bounded
@@ -272,6 +273,8 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=10,
                     help="forward + adjoint steps of the oracle sample (about 10 s on 16 cores at 320^3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing-every", type=int, default=10,
+                    help="time every k-th grid pass with HIP events (fewer events in the stream)")
     ap.add_argument("--serving", type=int, default=0,
                     help="run the serving trace with this many requests instead")
     ap.add_argument("--rate", type=float, default=20.0)
@@ -321,7 +324,7 @@ def main():
         torch.cuda.synchronize()
         progress(f"warmup solve {q + 1} done")
 
-    s.set_timing(True)
+    s.set_timing(True, every=args.timing_every)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -279,7 +279,9 @@ int ccpr_step_count(const ccpr_solver* s);
  * ccpr_forward and ccpr_adjoint, and clear the counters.  Timing records HIP
  * events on the bound stream around each loop and around every launch of the
  * grid kernel (the one that streams all cells), and synchronises the stream
- * at the end of each loop. */
+ * at the end of each loop.  enable = k > 1 times only every k-th grid pass
+ * (the loops are still timed whole): fewer events in the stream, the same
+ * average pass duration.  CCPR_EINVAL if negative. */
 ccpr_status ccpr_set_timing(ccpr_solver* s, int enable);
 
 /* Accumulated event time [ms] of the timed leapfrog loops and the number of
@@ -287,8 +289,8 @@ ccpr_status ccpr_set_timing(ccpr_solver* s, int enable);
  * kernels of a step and launch gaps included). */
 ccpr_status ccpr_get_timing(const ccpr_solver* s, double* step_ms_total, long long* step_launches);
 
-/* Accumulated event time [ms] of the grid passes inside the timed loops and
- * their number (their ratio is the grid pass's average duration).  A pass is
+/* Accumulated event time [ms] of the timed grid passes inside the timed
+ * loops and their number (their ratio is the grid pass's average duration).  A pass is
  * one launch of the grid kernel, or two concurrent launches (CPML tiles on
  * the bound stream, interior tiles on a second stream); it is timed from an
  * event on the bound stream before the first launch to the later of the

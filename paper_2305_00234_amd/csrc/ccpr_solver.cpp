@@ -138,6 +138,8 @@ struct ccpr_solver {
     double stat_grid_ms = 0;
     long long stat_grid_launches = 0;
     bool timing = false;
+    int timing_every = 1;           // time every k-th grid pass of the timed loops
+    long long pass_no = 0;          // grid passes launched inside timed loops
     std::vector<hipEvent_t> tev;    // events around grid passes (start, end on each stream) of the current loop
     size_t tev_used = 0;
     bool timed_loop = false;        // inside a forward / adjoint loop with timing on
@@ -837,7 +839,7 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
     hipStream_t Fs = s->lead2 ? s->stream : s->stream2;
     int e = s->pre_done[st] ? 0 : ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, Ls);
     s->pre_done[st] = false;
-    const bool tm = s->timing && s->timed_loop;
+    const bool tm = s->timing && s->timed_loop && (s->pass_no++ % s->timing_every) == 0;
     if (tm) {
         while (s->tev.size() < s->tev_used + 3) {
             hipEvent_t ev;
@@ -1712,7 +1714,10 @@ ccpr_status ccpr_gap_spectrum(ccpr_solver* s, const double* omega, int nf, doubl
 ccpr_status ccpr_set_timing(ccpr_solver* s, int enable)
 {
     if (!s) return CCPR_EINVAL;
+    if (enable < 0) return fail(s, CCPR_EINVAL, "timing period must be >= 0");
     s->timing = enable != 0;
+    s->timing_every = enable > 1 ? enable : 1;
+    s->pass_no = 0;
     s->stat_ms = 0;
     s->stat_launches = 0;
     s->stat_grid_ms = 0;

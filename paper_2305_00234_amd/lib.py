@@ -471,8 +471,9 @@ class Solver:
         return self._lib.ccpr_step_count(self._h)
 
     # -- diagnostics
-    def set_timing(self, on=True):
-        self._chk(self._lib.ccpr_set_timing(self._h, 1 if on else 0), "ccpr_set_timing")
+    def set_timing(self, on=True, every: int = 1):
+        """Event timing of the loops and of every 'every'-th grid pass."""
+        self._chk(self._lib.ccpr_set_timing(self._h, max(1, int(every)) if on else 0), "ccpr_set_timing")
 
     def timing(self):
         ms = C.c_double(0.0)
