@@ -134,6 +134,7 @@ def test_workspace_size_model(built):
     assert abs((b3 - br2) - step) <= 512
     assert 0 < 1000 * 3 * 512 * 4 - step < 4 * state
     assert s._lib.ccpr_set_resident_segments(s._h, -1) == L.EINVAL
+    assert s._lib.ccpr_set_timing(s._h, -2) == L.EINVAL
     s.close()
 
 

@@ -107,3 +107,26 @@ def test_empty_and_out_of_order_calls():
     g = s.gradient()
     s.close()
     assert np.isfinite(F) and np.all(np.isfinite(g))
+
+
+def test_sampled_grid_pass_timing():
+    """ccpr_set_timing(k): the loops are timed whole and every k-th grid pass
+    is timed with events; the pass count is the sampled one and the average
+    pass duration stays positive and finite."""
+    require_gpu()
+    from paper_2305_00234_amd.solver import configure
+    w = I.drude_dipole_32(steps=100)
+    s = configure(w)
+    s.bind_torch(w.steps)
+    s.set_timing(True, every=10)
+    s.forward(w.steps)
+    s.adjoint()
+    ms, loops = s.timing()
+    gms, passes = s.grid_timing()
+    s.set_timing(True, every=1)
+    s.forward(w.steps)
+    gms1, passes1 = s.grid_timing()
+    s.close()
+    say("timing: loop ms", ms, "steps", loops, "sampled passes", passes, "all passes", passes1)
+    assert loops == 2 * w.steps and passes == 2 * w.steps // 10 and passes1 == w.steps
+    assert 0 < gms / passes < float("inf") and 0 < gms1 / passes1 < float("inf")
