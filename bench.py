@@ -120,6 +120,18 @@ def kernel_hash():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()
 
 
+def cpu_model():
+    """Host CPU model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, sample_steps):
     """FP64 oracle, as it stands, on the full grid of the same workload for
     sample_steps forward + sample_steps adjoint steps."""
@@ -136,7 +148,7 @@ def cpu_baseline(w, sample_steps):
     o.close()
     upd = w.cells * 2 * sample_steps
     return {"value": upd / dt / 1e6, "unit": "Mcell-updates/s", "cores": num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{w.name}: full {w.shape[0]}x{w.shape[1]}x{w.shape[2]} grid, "
                       f"{sample_steps} forward + {sample_steps} adjoint FP64 steps incl. "
                       f"objective and gradient ({dt:.1f} s wall)"}
