@@ -148,3 +148,24 @@ def test_random_planewave_config_matches_oracle(seed):
         w.pw_pol_axis, "tfsf", w.tfsf_lo, w.tfsf_hi, "gradient", w.gradient, "F", F, Fo, "grad", err)
     assert Fo > 0 and abs(F - Fo) <= 1e-5 * abs(Fo)
     assert err <= 1e-3
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_segmentation_bitwise(seed):
+    """Random problems with the time-domain objective, run with a random
+    segment length and number of resident segments: objective and gradient
+    bit for bit those of the whole history (the recompute is deterministic)."""
+    require_gpu()
+    rng = np.random.default_rng(7000 + seed)
+    w = random_case(seed + 200)
+    w.objective = "time"
+    w.window = (int(rng.integers(0, w.steps // 3)), -1)
+    every = int(rng.integers(7, max(8, w.steps // 2)))
+    resident = int(rng.integers(1, 4))
+    F1, g1, _, _, _ = gpu_gradient(w)
+    F2, g2, _, _, info = gpu_gradient(w, checkpoint_every=every, resident=resident)
+    flat = (lambda x: np.concatenate([np.ravel(a) for a in x])) if w.rho_edges is not None else np.ravel
+    say("segmentation", seed, w.shape, "every", every, "resident", resident, info)
+    assert info["segment_steps"] == every and info["resident_segments"] == min(resident, info["segments"])
+    assert F1 == F2
+    assert np.array_equal(flat(g1), flat(g2))
