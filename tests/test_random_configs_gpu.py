@@ -169,3 +169,65 @@ def test_random_segmentation_bitwise(seed):
     assert info["segment_steps"] == every and info["resident_segments"] == min(resident, info["segments"])
     assert F1 == F2
     assert np.array_equal(flat(g1), flat(g2))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_launch_shape_bitwise(seed):
+    """Random problems: the fields after the run do not depend on the launch
+    shape (z-chunk height, rows per thread), bit for bit."""
+    require_gpu()
+    from tests.gpu_util import gpu_fields_after_steps
+    rng = np.random.default_rng(8000 + seed)
+    w = random_case(seed + 300)
+    steps = min(w.steps, 120)
+    ref = gpu_fields_after_steps(w, steps)
+    for planes, rows in ((int(rng.integers(2, 9)), 2), (int(rng.integers(2, 9)), 4)):
+        got = gpu_fields_after_steps(w, steps, tile_planes=planes, tile_rows=rows)
+        say("launch shape", seed, w.shape, "planes", planes, "rows", rows)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_filter_matches_oracle(seed):
+    """Random design sizes, radii (1-8 voxels), sharpness and thresholds, per
+    voxel and per edge: filtered densities, projection and the chain rule
+    against the FP64 oracle (relative 1e-5)."""
+    torch = require_gpu()
+    from oracle import filters as OF
+    from paper_2305_00234_amd.lib import (filter_project, filter_project_edges, filter_project_grad,
+                                          filter_project_grad_edges)
+    rng = np.random.default_rng(9000 + seed)
+    dims = tuple(int(x) for x in rng.integers(3, 24, size=3))
+    R = float(1.0 + 7.0 * rng.random())
+    beta, eta = float(1.0 + 15.0 * rng.random()), float(0.2 + 0.6 * rng.random())
+    if seed % 2 == 0:
+        rho = rng.random((dims[2], dims[1], dims[0])).astype(np.float32)
+        gb = rng.standard_normal(rho.shape)
+        rt, rb, ws = filter_project(torch.tensor(rho, device="cuda"), R, beta, eta)
+        g = filter_project_grad(torch.tensor(gb, device="cuda"), rt, ws, R, beta, eta)
+        ot = OF.cone_filter(rho.astype(np.float64), R)
+        og = OF.filter_project_grad(gb, rho.astype(np.float64), R, beta, eta)
+        ot_flat, og_flat = ot.ravel(), og.ravel()
+    else:
+        parts = [rng.random(OF.edge_shape(dims, c)) for c in range(3)]
+        rho = np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+        gparts = [rng.standard_normal(OF.edge_shape(dims, c)) for c in range(3)]
+        gb = np.concatenate([p.ravel() for p in gparts])
+        rt, rb, ws = filter_project_edges(torch.tensor(rho, device="cuda"), dims, R, beta, eta)
+        g = filter_project_grad_edges(torch.tensor(gb, device="cuda"), rt, ws, dims, R, beta, eta)
+        split, o = [], 0
+        for c in range(3):
+            n = int(np.prod(OF.edge_shape(dims, c)))
+            split.append(rho[o:o + n].astype(np.float64).reshape(OF.edge_shape(dims, c)))
+            o += n
+        ot_flat = np.concatenate([x.ravel() for x in OF.cone_filter_edges(split, dims, R)])
+        og_flat = np.concatenate([x.ravel() for x in OF.filter_project_grad_edges(gparts, split, dims, R, beta, eta)])
+    torch.cuda.synchronize()
+    rt_h = rt.cpu().numpy().ravel()
+    e_t = rel_l2(rt_h, ot_flat)
+    e_b = rel_l2(rb.cpu().numpy().ravel(), OF.project(rt_h.astype(np.float64), beta, eta))
+    e_g = rel_l2(g.cpu().numpy().ravel(), og_flat)
+    say("random filter", seed, dims, "R", round(R, 2), "beta", round(beta, 2), "eta", round(eta, 2),
+        "edges" if seed % 2 else "voxels", "rho_t", e_t, "rho_b", e_b, "chain", e_g)
+    assert e_t <= 1e-5 and e_b <= 1e-5 and e_g <= 1e-5
