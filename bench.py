@@ -296,8 +296,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU (asked for {args.gpus}): this build has no "
-              "multi-GPU path.", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): the library runs a solve on "
+              "one GPU and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch

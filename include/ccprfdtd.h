@@ -51,7 +51,7 @@ typedef enum {
     CCPR_EDEVICE = -4,   /* HIP runtime error                                  */
     CCPR_ESTATE = -5,    /* call out of order (e.g. adjoint before forward)    */
     CCPR_EDIVERGED = -6, /* non-finite or exploding fields                     */
-    CCPR_ENOTSUP = -7    /* valid request outside what this build supports     */
+    CCPR_ENOTSUP = -7    /* valid request outside what the library supports    */
 } ccpr_status;
 
 enum { CCPR_MEM_HOST = 0, CCPR_MEM_DEVICE = 1 };
