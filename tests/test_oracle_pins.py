@@ -447,7 +447,7 @@ def test_edge_design_reduces_to_voxel_design():
     F_e, g_e = s.gradient(w.steps, OBJ_DFT, w.gap_lo, w.gap_dims, w.omega)
     nz, ny, nx = w.rho.shape
     summed = sum(g[:nz, :ny, :nx] for g in g_e)
-    assert F_e == pytest.approx(F_v, rel=1e-13)
+    assert F_e == pytest.approx(F_v, rel=1e-13, abs=0)
     assert np.max(np.abs(summed - g_v)) <= 1e-12 * np.max(np.abs(g_v))
 
 
@@ -500,3 +500,157 @@ def test_p10_mirror_symmetric_problem_has_mirror_symmetric_gradient(per_edge, ob
         assert np.max(np.abs(gz - gz.transpose(0, 2, 1))) <= 1e-10 * scale
     else:
         assert np.max(np.abs(g - g.transpose(0, 2, 1))) <= 1e-10 * np.max(np.abs(g))
+
+
+# ------------------------------------------------------- objectives (Eq. 2)
+def _gap_dipole_case(M=47):
+    """Small CPML grid, Drude design, dipole beside it, 2^3 gap."""
+    w = I.drude_dipole_32(steps=M, n=16, npml=3)
+    t = (np.arange(M) + 0.5) * w.dt
+    w.wave = I.gaussian_sine(t, 300e-9, 0.8e-15, 1.0e-15, amp=1e9)
+    return w
+
+
+def test_objectives_parseval_identity():
+    """The single-frequency objective F_dft(w) = sum_e |dt sum_{n=0..M} E_e^n
+    e^{-j w n dt}|^2 and the time-domain objective of Eq. 2 (rectangle rule,
+    eps_inf = 1 in the gap) over the whole run [0, M+1) are tied by
+    Parseval's identity for the DFT of length M+1: at the M+1 frequencies
+    w_k = 2 pi k / ((M+1) dt),
+        sum_k F_dft(w_k) = 2 (M+1) dt F_time / (eps0 dx^3).
+    A dropped or extra sample in either sum, a missing dt in the transform, a
+    wrong eps0/2, dx^3 or dt in Eq. 2 or a shifted time window breaks it."""
+    M = 47
+    w = _gap_dipole_case(M)
+    dt = w.dt
+    ft = oracle_from_workload(w).objective(M, OBJ_TIME, w.gap_lo, w.gap_dims, 0.0, 0, M + 1)
+    assert ft > 0
+    tot = 0.0
+    for k in range(M + 1):
+        wk = 2 * math.pi * k / ((M + 1) * dt)
+        tot += oracle_from_workload(w).objective(M, OBJ_DFT, w.gap_lo, w.gap_dims, wk)
+    expect = 2 * (M + 1) * dt * ft / (EPS0 * w.dx ** 3)
+    assert abs(tot - expect) <= 1e-11 * expect, (tot, expect)
+
+
+def test_time_objective_window_samples_the_state_after_n_steps():
+    """Eq. 2's window [n_begin, n_end) samples E^n, the field after n steps
+    (n = 0 is the zero initial state, n = M the last one): a one-sample
+    window [n, n+1) equals (eps0/2) dx^3 dt sum over the gap edges of
+    (E^n)^2 taken from the field state after n steps, and the windows
+    partition the run (additivity)."""
+    M = 47
+    w = _gap_dipole_case(M)
+    sim = oracle_from_workload(w)
+    lo, dims = w.gap_lo, w.gap_dims
+    wgt = 0.5 * EPS0 * w.dx ** 3 * w.dt
+
+    def window(a, b):
+        return oracle_from_workload(w).objective(M, OBJ_TIME, lo, dims, 0.0, a, b)
+
+    sl = (slice(lo[2], lo[2] + dims[2]), slice(lo[1], lo[1] + dims[1]), slice(lo[0], lo[0] + dims[0]))
+    for n in (20, 33, M):
+        sim.reset()
+        sim.run(n)
+        e2 = sum(float(np.sum(sim.field(c)[sl] ** 2)) for c in range(3))
+        assert e2 > 0
+        assert window(n, n + 1) == pytest.approx(wgt * e2, rel=1e-12, abs=0)
+    assert window(0, 1) == 0.0
+    whole = window(0, M + 1)
+    for a in (1, 17, 30, M):
+        assert window(0, a) + window(a, M + 1) == pytest.approx(whole, rel=1e-12, abs=0)
+
+
+# ------------------------------------------------ TF/SF incident amplitude
+def _line_1d(wave, steps, L, S):
+    """Textbook 1-D Yee line in SI units with the same dx, dt (Courant S):
+    E at integer points u, H at u + 1/2, hard source E[0]^n = wave[n];
+    eps0 dE/dt = -dH/du, mu0 dH/dt = -dE/du, so a wave moving to +u has
+    H = E / eta0.  Returns E^n[u] and H^{n+1/2}[u] for n = 0..steps."""
+    eta0 = math.sqrt(MU0 / EPS0)
+    E = np.zeros(L + 1)
+    H = np.zeros(L)
+    E[0] = wave[0]
+    Es, Hs = [E.copy()], []
+    for n in range(steps):
+        H -= (S / eta0) * (E[1:] - E[:-1])
+        E[1:-1] -= (S * eta0) * (H[1:] - H[:-1])
+        E[0] = wave[n + 1] if n + 1 < len(wave) else 0.0
+        Hs.append(H.copy())
+        Es.append(E.copy())
+    return np.array(Es), np.array(Hs)
+
+
+@pytest.mark.parametrize("prop,sign,pol", [(2, 1, 0), (0, -1, 1), (1, 1, 2), (2, -1, 1)])
+def test_tfsf_total_field_equals_incident_wave(prop, sign, pol):
+    """In an empty grid the total field inside the TF/SF box is the incident
+    plane wave alone.  Its amplitude, sign and timing are fixed by the
+    source's definition -- wave[n] is E_pol at the launch point two cells
+    before the box (along the direction of travel) at t = n dt -- and by
+    Maxwell's equations: E_pol(x_d) is the 1-D Yee line's E at distance
+    sign*(x_d - x_launch) and H_t = sign * levi(pol, t, prop) * H_line (the
+    Poynting vector points along sign * prop).  The line here is this test's
+    own.  A scaled, sign-flipped, shifted or mis-polarised incident wave
+    fails; the leakage pin (P11) alone would not see those."""
+    n3 = (26, 22, 28)
+    lo, hi = (5, 6, 5), (19, 15, 21)
+    sim = _sim(n=n3)
+    steps = 110
+    t = np.arange(steps + 1) * sim.dt
+    wave = I.gaussian_sine(t, 300e-9, 0.5e-15, 1.2e-15)
+    sim.set_planewave(prop, sign, pol, lo, hi, wave)
+    tr = 3 - prop - pol
+    lev = 1 if (pol, tr, prop) in ((0, 1, 2), (1, 2, 0), (2, 0, 1)) else -1
+    launch = lo[prop] - 2 if sign > 0 else hi[prop] + 2
+    Es, Hs = _line_1d(wave, steps, 80, 0.5)
+    c0 = [(lo[a] + hi[a]) // 2 for a in range(3)]
+    peakE = np.max(np.abs(Es))
+    peakH = np.max(np.abs(Hs))
+    seen = 0.0
+    for n in (40, 70, steps):
+        sim.reset()
+        sim.run(n)
+        Ef = sim.field(pol)
+        Hf = sim.field(3 + tr)
+        for q in range(lo[prop] + 1, hi[prop]):
+            cell = list(c0)
+            cell[prop] = q
+            z, y, x = cell[2], cell[1], cell[0]
+            # E_pol (pol != prop) sits at the integer coordinate q along prop;
+            # H_t at q + 1/2
+            uE = sign * (q - launch)
+            assert abs(Ef[z, y, x] - Es[n, uE]) <= 1e-12 * peakE, (n, q, Ef[z, y, x], Es[n, uE])
+            seen = max(seen, abs(Es[n, uE]))
+            uH = q - launch if sign > 0 else launch - q - 1   # H_line[u] sits at u + 1/2
+            h_ref = sign * lev * Hs[n - 1, uH]
+            assert abs(Hf[z, y, x] - h_ref) <= 1e-12 * peakH, (n, q, Hf[z, y, x], h_ref)
+    assert seen > 0.5 * peakE   # the pulse crossed the compared points
+
+
+# ---------------------------------------------- P14 with a stretched CPML
+def test_p14_cpml_reflection_with_kappa_grading():
+    """Bound only, with a non-default grading that exercises every CPML term:
+    kappa_max = 5 (the 1/kappa scaling of the differences), alpha_max = 0.1,
+    polynomial order 4 and a 1.2x conductivity: still below -40 dB against a
+    grid large enough that nothing returns in time.  A kappa used as
+    kappa instead of 1/kappa, or applied to the wrong axis, reflects far
+    more."""
+    steps = 140
+    t = (np.arange(steps) + 0.5) * 5e-9 * 0.5 / C0
+    wave = I.gaussian_sine(t, 200e-9, 0.3e-15, 0.45e-15, amp=1e9)
+
+    def probe(n, npml):
+        sim = OracleSim(n, n, n, 5e-9, 0.5, npml, 4.0, 5.0, 0.1, 1.2)
+        c = n // 2
+        sim.set_dipole((c, c, c), 2, wave)
+        out = []
+        for _ in range(steps):
+            sim.run(1)
+            out.append(np.array([sim.field(2)[c, c, c + 10], sim.field(2)[c + 9, c - 9, c]]))
+        return np.array(out)
+
+    small = probe(36, 8)
+    big = probe(96, 8)
+    refl = np.max(np.abs(small - big)) / np.max(np.abs(big))
+    print("cpml (kappa 5, alpha 0.1, m 4) reflection", 20 * math.log10(refl), "dB")
+    assert refl < 1e-2

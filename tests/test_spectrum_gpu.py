@@ -34,4 +34,4 @@ def test_gap_spectrum_matches_oracle_and_objective():
     ne = h.shape[1]
     say("spectrum rel L2", rel_l2(spec, spec_o), "at omega0", spec[-1] * ne, F)
     assert rel_l2(spec, spec_o) <= 1e-5
-    assert spec[-1] * ne == pytest.approx(F, rel=1e-9)
+    assert spec[-1] * ne == pytest.approx(F, rel=1e-9, abs=0)
