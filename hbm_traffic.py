@@ -1,4 +1,6 @@
-"""HBM traffic of the grid kernel (ccpr_step_kernel) from rocprofv3 counters.
+"""HBM traffic of the step kernels from rocprofv3 counters: the grid pass
+(ccpr_step_kernel, both tile variants), the design-voxel kernel
+(ccpr_aux_kernel) and the x-CPML post/pre kernel (ccpr_post_fused_kernel).
 
 The counters are calibrated against a plain device copy of known size, run in
 the same process: the factor (bytes moved) / (counter reading) of the copy
@@ -7,10 +9,10 @@ scales the grid kernel's readings.
 Steps (from the repository root; each 'run' under its own counter pass):
 
   rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o fetch -- \\
-      python3 paper_2305_00234_amd/hbm_traffic.py run
+      python3 hbm_traffic.py run
   rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o write -- \\
-      python3 paper_2305_00234_amd/hbm_traffic.py run
-  python3 paper_2305_00234_amd/hbm_traffic.py summarize OUT/fetch OUT/write \\
+      python3 hbm_traffic.py run
+  python3 hbm_traffic.py summarize OUT/fetch OUT/write \\
       profiles/step_kernel_hbm_traffic_gold_gap_320.json
 
 'run' copies a 1 GiB device buffer four times (hipMemcpy device to device),
@@ -28,9 +30,11 @@ import json
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 GRID_KERNEL = "ccpr_step_kernel"
+# other step kernels reported per dispatch (one dispatch per step each)
+OTHER_KERNELS = ("ccpr_aux_kernel", "ccpr_post_fused_kernel")
 
 
 def run(steps: int = 10) -> None:
@@ -104,6 +108,18 @@ def summarize(fetch_dir: str, write_dir: str, out_json: str) -> dict:
     gw = [per_w[n] for n in names]
     fetch_b = sum(gf) * 1024.0 * f_fac
     write_b = sum(gw) * 1024.0 * w_fac
+    others = {}
+    for k in OTHER_KERNELS:
+        kn = sorted(n for n in fetch if k in n)
+        if not kn:
+            continue
+        fv = [v for n in kn for _, v in fetch[n]]
+        wv = [v for n in kn for _, v in write.get(n, [])]
+        others[k] = {
+            "dispatches": len(fv),
+            "hbm_fetch_bytes_per_dispatch": sum(fv) / len(fv) * 1024.0 * f_fac,
+            "hbm_write_bytes_per_dispatch": (sum(wv) / len(wv) * 1024.0 * w_fac) if wv else None,
+        }
     src = os.path.join(ROOT, "paper_2305_00234_amd", "csrc", "ccpr_kernels.hip")
     d = {
         "kernel": name,
@@ -118,6 +134,7 @@ def summarize(fetch_dir: str, write_dir: str, out_json: str) -> dict:
         "hbm_fetch_bytes_per_launch": fetch_b,
         "hbm_write_bytes_per_launch": write_b,
         "hbm_bytes_per_launch": fetch_b + write_b,  # per grid pass (all variants)
+        "other_kernels": others,
         "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
     }
     with open(out_json, "w") as f:

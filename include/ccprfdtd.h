@@ -220,15 +220,41 @@ ccpr_status ccpr_bind_workspace(ccpr_solver* s, void* dev_ptr, uint64_t bytes, v
 /* Forward run of nsteps from zero fields, recording the gap monitor and the
  * gradient history (DFT gradient mode: its transform), then the objective
  * (synchronises the stream to return *objective_out, which may be NULL).
- * CCPR_EDIVERGED when the objective is not finite (fields that overflowed:
- * a non-passive material); the solve is then not usable for ccpr_adjoint. */
+ * CCPR_EDIVERGED when the divergence watchdog (ccpr_set_watchdog) tripped
+ * -- every step after it is skipped on the device, and ccpr_step_count then
+ * returns the steps done when it tripped -- or when the objective is not
+ * finite (a non-passive material); the solve is then not usable for
+ * ccpr_adjoint. */
 ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out);
 
 /* Adjoint run (same update, zero initial fields, time-reversed source
  * (1/dt) dF/dE at the gap edges, no incident wave) with the gradient
- * correlation; recomputes checkpointed segments as needed.  Stream-ordered.
- * CCPR_ESTATE before a successful ccpr_forward. */
+ * correlation; recomputes checkpointed segments as needed.  Stream-ordered
+ * (with the watchdog on it synchronises at the end to read it:
+ * CCPR_EDIVERGED if it tripped).  CCPR_ESTATE before a successful
+ * ccpr_forward, and for a second adjoint of the same forward run when this
+ * one recomputed segments (their history overwrote the first resident
+ * segment's; ccpr_forward_serial then returns -1). */
 ccpr_status ccpr_adjoint(ccpr_solver* s);
+
+/* Serial number of the forward run whose state the next ccpr_adjoint would
+ * use (it counts the successful forward runs of this solver), or -1 when no
+ * such state exists: no forward run yet, a configuration change since, or an
+ * adjoint run that recomputed segments over its history.  Callers that hold
+ * on to a forward result (a differentiable objective's backward) compare it
+ * with the serial they saw and run the forward again on a mismatch. */
+long long ccpr_forward_serial(const ccpr_solver* s);
+
+/* Divergence watchdog (failure detection): after every 'every'-th step of
+ * the forward and adjoint runs (including the serving engine's), one small
+ * launch checks the E edges of the gap box; if one is not finite or larger
+ * than 'limit' in units of the run's source amplitude (the incident wave's
+ * peak, or the peak current of the dipole / adjoint source per step: a
+ * passive medium stays orders of magnitude below the default 1e15), every
+ * later step kernel of the run returns at once and the run reports
+ * CCPR_EDIVERGED.  every = 0 turns it off (default: every 128 steps).
+ * CCPR_EINVAL for every < 0 or limit outside (0, 3e38]. */
+ccpr_status ccpr_set_watchdog(ccpr_solver* s, int every, double limit);
 
 /* Spectrum of the gap field recorded by the last ccpr_forward (the monitor of
  * Eq. Objective_analyitically_enhancement read in the frequency domain, as
@@ -385,7 +411,8 @@ ccpr_status ccpr_nondiscreteness(const float* rho_projected, long long n, double
  * max_active: solves on the device at once (1..64); chunk_steps: leapfrog
  * steps enqueued per solve per turn.  The engine creates its HIP streams (two
  * per slot, default priority) here.  CCPR_EINVAL on bad arguments,
- * CCPR_EDEVICE if the streams cannot be created. */
+ * CCPR_EDEVICE if the streams or the slots' pinned result buffers cannot be
+ * created. */
 ccpr_status ccpr_engine_create(void* arena, uint64_t arena_bytes, int max_active, int chunk_steps,
                                ccpr_engine** out);
 

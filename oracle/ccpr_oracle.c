@@ -91,6 +91,9 @@ struct or_sim {
     int bs_on, bs_lo[3], bs_dim[3], bs_ncell, bs_nsteps;
     double* bs_table;
     int step;
+    /* copy of the six fields at the end of the last forward run of
+     * or_gradient / or_gradient_dft / or_objective (NULL until kept) */
+    double* fwd_end[6];
 };
 
 static size_t idx3(const or_sim* s, int i, int j, int k)
@@ -178,6 +181,7 @@ void or_destroy(or_sim* s)
         for (int d = 0; d < 3; ++d) { free(s->psiE[c][d]); free(s->psiH[c][d]); }
     free(s->rho); free(s->J); free(s->dip_wave);
     free(s->pw_wave); free(s->pw_E); free(s->pw_H); free(s->bs_table);
+    for (int c = 0; c < 6; ++c) free(s->fwd_end[c]);
     free(s);
 }
 
@@ -334,6 +338,13 @@ void or_reset(or_sim* s)
 }
 
 int or_step_count(const or_sim* s) { return s->step; }
+
+int or_get_forward_end_field(const or_sim* s, int comp, double* out)
+{
+    if (comp < 0 || comp > 5 || !s->fwd_end[comp]) return -1;
+    memcpy(out, s->fwd_end[comp], ncells(s) * sizeof(double));
+    return 0;
+}
 
 void or_get_field(const or_sim* s, int comp, double* out)
 {
@@ -640,6 +651,10 @@ static int forward_and_objective(or_sim* s, int M, int kind, const int* glo, con
         }
     }
     free(T_step);
+    for (int c = 0; c < 6; ++c) {
+        if (!s->fwd_end[c]) s->fwd_end[c] = malloc(ncells(s) * sizeof(double));
+        memcpy(s->fwd_end[c], s->F[c], ncells(s) * sizeof(double));
+    }
     double dt = s->dt, F = 0.0;
     size_t ne_tot = (size_t)(M + 1) * ncell * 3;
     memset(dFdE, 0, ne_tot * sizeof(double));

@@ -88,6 +88,10 @@ void or_run(or_sim* s, int nsteps); /* advance nsteps full leapfrog steps      *
 int  or_step_count(const or_sim* s);
 /* comp 0..5 = Ex,Ey,Ez,Hx,Hy,Hz; out holds nz*ny*nx doubles. */
 void or_get_field(const or_sim* s, int comp, double* out);
+/* comp 0..5 of the state at the end of the forward run inside the last
+ * or_gradient / or_gradient_dft / or_objective call (the call itself leaves
+ * the adjoint fields, or the forward ones); -1 before any such call. */
+int or_get_forward_end_field(const or_sim* s, int comp, double* out);
 /* overwrite a field component (tests: eigenmode initial states) */
 void or_set_field(or_sim* s, int comp, const double* in);
 

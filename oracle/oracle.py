@@ -52,6 +52,8 @@ def _lib():
         lib.or_step_count.argtypes = [_p]
         lib.or_get_field.argtypes = [_p, _i, _dp]
         lib.or_set_field.argtypes = [_p, _i, _dp]
+        lib.or_get_forward_end_field.restype = _i
+        lib.or_get_forward_end_field.argtypes = [_p, _i, _dp]
         lib.or_gradient.argtypes = [_p, _i, _i, _ip, _ip, _d, _i, _i, _dp, _dp, _dp]
         lib.or_objective.argtypes = [_p, _i, _i, _ip, _ip, _d, _i, _i, _dp]
         lib.or_gradient_dft.argtypes = [_p, _i, _ip, _ip, _d, _dp, _dp]
@@ -201,6 +203,16 @@ class OracleSim:
 
     def fields(self):
         return [self.field(c) for c in range(6)]
+
+    def forward_end_fields(self):
+        """The six fields at the end of the forward run inside the last
+        gradient / gradient_dft / objective call."""
+        out = []
+        for c in range(6):
+            a = np.empty(self.shape, dtype=np.float64)
+            self._chk(_lib().or_get_forward_end_field(self._h, c, a.ctypes.data_as(_dp)), "forward end field")
+            out.append(a)
+        return out
 
     def set_field(self, comp, arr):
         a, ap = _dv(np.broadcast_to(arr, self.shape))

@@ -40,11 +40,24 @@ class CCPRObjective(torch.autograd.Function):
         ctx.solver = solver
         ctx.rho_dtype = rho.dtype
         ctx.shape = rho.shape
+        ctx.args = (int(nsteps), tuple(design_lo), float(gamma))
+        ctx.serial = solver.forward_serial
+        ctx.save_for_backward(r32)
         return torch.tensor(F, dtype=torch.float64, device=rho.device)
 
     @staticmethod
     def backward(ctx, grad_out):
         s: Solver = ctx.solver
+        if s.forward_serial != ctx.serial:
+            # the solver's forward state is no longer this node's: another
+            # objective ran on the same solver since, or an earlier backward's
+            # segment recompute overwrote the history (retain_graph): run this
+            # node's forward again
+            (r32,) = ctx.saved_tensors
+            nsteps, lo, gamma = ctx.args
+            s.set_design(lo, r32, gamma)
+            s.forward(nsteps)
+            ctx.serial = s.forward_serial
         s.adjoint()
         g = torch.empty(ctx.shape, dtype=torch.float64, device=grad_out.device)
         s.gradient(out=g)

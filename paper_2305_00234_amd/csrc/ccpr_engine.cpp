@@ -6,8 +6,12 @@
 // each to its own slice of the arena and its own HIP stream, and then keeps
 // every admitted solve fed with chunks of leapfrog steps, round robin, so the
 // small kernels of different solves overlap on the device.  A finished solve's
-// objective and gradient are copied to pinned host memory, its slice and
-// stream are released, and the next queued solve is admitted.  Every solve
+// objective and gradient are copied to its slot's pinned host buffers, its
+// slice and streams are released, and the next queued solve is admitted.
+// Pinned buffers belong to the slots and are allocated once at creation
+// (grown by doubling when a larger design arrives; outgrown buffers are kept
+// until the engine is destroyed), so no pinned free -- which would
+// synchronise the device -- happens while solves run.  Every solve
 // runs the same kernels in the same order as a solve on its own, so its
 // results do not depend on what else is running.
 #include <hip/hip_runtime.h>
@@ -44,8 +48,9 @@ struct Job {
     std::deque<hipEvent_t> inflight;  // one event per enqueued chunk
     bool enqueued_all = false;
     hipEvent_t done_ev = nullptr;
-    double* scal_host = nullptr;  // pinned [8]
-    double* grad_host = nullptr;  // pinned [nd]
+    int slot = -1;                // result buffers of this slot
+    double* scal_host = nullptr;  // pinned [8] (the slot's)
+    double* grad_host = nullptr;  // pinned [nd] (the slot's)
     long long nd = 0;
     double F = 0;
     std::vector<double> grad;
@@ -55,6 +60,13 @@ struct Job {
 
 struct Block {
     uint64_t off, len;
+};
+
+struct Slot {
+    bool busy = false;
+    double* scal = nullptr;   // pinned [8]
+    double* grad = nullptr;   // pinned [cap]
+    long long cap = 0;
 };
 
 }  // namespace
@@ -73,6 +85,8 @@ struct ccpr_engine {
     std::map<uint64_t, Job*> jobs;
     uint64_t next_ticket = 1;
     std::vector<hipStream_t> streams;  // pool: two per slot, created once
+    std::vector<Slot> slots;           // max_active result-buffer slots
+    std::vector<double*> retired;      // outgrown pinned buffers (freed at destroy)
     double t0 = 0;                     // creation time (job times are relative to it)
     std::thread worker;
     std::string err;
@@ -125,8 +139,8 @@ void release_device(ccpr_engine* e, Job* j)
     if (j->stream) e->streams.push_back(j->stream);
     if (j->stream2) e->streams.push_back(j->stream2);
     j->stream = j->stream2 = nullptr;
-    if (j->scal_host) (void)hipHostFree(j->scal_host);
-    if (j->grad_host) (void)hipHostFree(j->grad_host);
+    if (j->slot >= 0) e->slots[j->slot].busy = false;
+    j->slot = -1;
     j->scal_host = j->grad_host = nullptr;
     ccpr_pipe_unbind(j->s);
     arena_free(e, j->off, j->bytes);
@@ -134,7 +148,10 @@ void release_device(ccpr_engine* e, Job* j)
 
 void fail_job(ccpr_engine* e, Job* j, const std::string& why)
 {
+    // the solve's work may still run on either of its streams (a split grid
+    // pass leaves its second launch on the other one)
     if (j->stream) (void)hipStreamSynchronize(j->stream);
+    if (j->stream2) (void)hipStreamSynchronize(j->stream2);
     j->err = why;
     release_device(e, j);
     j->t_done = now_s();
@@ -159,10 +176,35 @@ bool admit(ccpr_engine* e, Job* j)
         e->streams.pop_back();
     }
     j->nd = ccpr_pipe_design_voxels(j->s);
-    if (why.empty() && (hipHostMalloc((void**)&j->scal_host, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-                        hipHostMalloc((void**)&j->grad_host, std::max(j->nd, 1LL) * sizeof(double),
-                                      hipHostMallocDefault) != hipSuccess))
-        why = "hipHostMalloc failed";
+    if (why.empty()) {
+        for (size_t q = 0; q < e->slots.size(); ++q)
+            if (!e->slots[q].busy) {
+                j->slot = (int)q;
+                break;
+            }
+        if (j->slot < 0) {
+            why = "no free result slot";
+        } else {
+            Slot& sl = e->slots[j->slot];
+            if (sl.cap < std::max(j->nd, 1LL)) {
+                long long cap = std::max(sl.cap, 1LL << 16);
+                while (cap < j->nd) cap *= 2;
+                double* g = nullptr;
+                if (hipHostMalloc((void**)&g, cap * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+                    why = "hipHostMalloc failed";
+                } else {
+                    if (sl.grad) e->retired.push_back(sl.grad);
+                    sl.grad = g;
+                    sl.cap = cap;
+                }
+            }
+            if (why.empty()) {
+                sl.busy = true;
+                j->scal_host = sl.scal;
+                j->grad_host = sl.grad;
+            }
+        }
+    }
     if (why.empty() && ccpr_pipe_set_stream2(j->s, j->stream2) != CCPR_OK)
         why = std::string("stream: ") + ccpr_last_error(j->s);
     if (why.empty() && ccpr_bind_workspace(j->s, e->arena + off, j->bytes, j->stream) != CCPR_OK)
@@ -280,14 +322,27 @@ ccpr_status ccpr_engine_create(void* arena, uint64_t arena_bytes, int max_active
     e->max_active = max_active;
     e->chunk = chunk_steps;
     e->free_list.push_back(Block{0, e->arena_bytes});
-    for (int q = 0; q < 2 * max_active; ++q) {
+    bool ok = true;
+    for (int q = 0; q < 2 * max_active && ok; ++q) {
         hipStream_t st;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            for (hipStream_t x : e->streams) (void)hipStreamDestroy(x);
-            delete e;
-            return CCPR_EDEVICE;
+        ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (ok) e->streams.push_back(st);
+    }
+    e->slots.resize(max_active);
+    for (Slot& sl : e->slots) {
+        if (!ok) break;
+        sl.cap = 1 << 16;
+        ok = hipHostMalloc((void**)&sl.scal, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&sl.grad, sl.cap * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    }
+    if (!ok) {
+        for (hipStream_t x : e->streams) (void)hipStreamDestroy(x);
+        for (Slot& sl : e->slots) {
+            if (sl.scal) (void)hipHostFree(sl.scal);
+            if (sl.grad) (void)hipHostFree(sl.grad);
         }
-        e->streams.push_back(st);
+        delete e;
+        return CCPR_EDEVICE;
     }
     e->t0 = now_s();
     e->worker = std::thread(worker_loop, e);
@@ -395,6 +450,11 @@ void ccpr_engine_destroy(ccpr_engine* e)
     e->worker.join();
     for (auto& kv : e->jobs) delete kv.second;
     for (hipStream_t st : e->streams) (void)hipStreamDestroy(st);
+    for (Slot& sl : e->slots) {
+        if (sl.scal) (void)hipHostFree(sl.scal);
+        if (sl.grad) (void)hipHostFree(sl.grad);
+    }
+    for (double* p : e->retired) (void)hipHostFree(p);
     delete e;
 }
 

@@ -160,6 +160,8 @@ struct StepArgs {
     float phc, phs;             // DFT modes: cos, sin of omega dt n (forward step n)
                                 // or of omega dt m (adjoint field m)
     const StepCold* cold;
+    const unsigned* halt;       // nonzero: the divergence watchdog tripped; every
+                                // step kernel returns at once
     const int2* zr;             // plane range [k0, k1) of each logical z-chunk
     const int2* tiles;          // this launch's tiles: (y-strip, logical z-chunk)
     int nys;                    // y strips
@@ -223,3 +225,9 @@ int ccpr_launch_incident_line(const double* wave, int nw, int M, int L, double c
 int ccpr_launch_objective(const float* gap, int M, int ne, int kind, double omega_dt, int nb,
                           int nend, double* scal, double* work, float* adj, void* stream);
 int ccpr_launch_check_rho(const float* rho, long long n, double* flag, void* stream);
+// divergence watchdog after step n of a run: trips when an E edge of the
+// monitor box [lo, lo + dim) of the field state a.Eo is not finite or above
+// limit (scaled units): halt[0] = 1 (the step kernels of every later step
+// return at once) and scal[7] = n + 1 (steps done when it tripped), once
+int ccpr_launch_watch(const StepArgs& a, const int lo[3], const int dim[3], float limit, int n, unsigned* halt,
+                      double* scal, void* stream);

@@ -207,6 +207,7 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
 {
     __shared__ float xe[2][R + 1][16];
     __shared__ float xh[2][R][16];
+    if (*a.halt) return;  // the divergence watchdog stopped the run
     const StepCold& c = *a.cold;
 
     // XCD-aware tile order: hardware hands workgroups to the 8 XCDs round
@@ -496,6 +497,7 @@ __device__ __forceinline__ long long edge_index(const EdgeMap& m, int xi, int yi
 template <int PMAX, bool NT, bool DFT, bool EDGE>
 __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
 {
+    if (*a.halt) return;  // the divergence watchdog stopped the run
     const StepCold& c = *a.cold;
     const unsigned cs = a.cstride;
     const int n = a.n;
@@ -688,6 +690,7 @@ __device__ __forceinline__ void aux_misc(const StepArgs& a, long long e)
 //  - TF/SF H faces (the next tf_nH threads): H += coef*incE[n][m].
 __global__ __launch_bounds__(256) void ccpr_pre_kernel(const StepArgs a, long long nxs)
 {
+    if (*a.halt) return;
     const StepCold& c = *a.cold;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     float* H = const_cast<float*>(a.Hi);
@@ -729,6 +732,7 @@ __global__ __launch_bounds__(256) void ccpr_pre_kernel(const StepArgs a, long lo
 // Tangential E on the walls stays zero.
 __global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long long nxs, long long nmisc)
 {
+    if (*a.halt) return;
     const StepCold& c = *a.cold;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nxs) {
@@ -775,6 +779,7 @@ __global__ __launch_bounds__(256) void ccpr_post_fused_kernel(const StepArgs a, 
                                                               long long nmisc, long long ntfh)
 {
     __shared__ float se[2][256];
+    if (*a.halt) return;
     const StepCold& c = *a.cold;
     const int tid = threadIdx.x;
     if ((long long)blockIdx.x >= nbx) {
@@ -1109,6 +1114,34 @@ __global__ void check_rho_kernel(const float* rho, long long n, double* flag)
     }
 }
 
+// Divergence watchdog (one workgroup): every E edge of the monitor box
+// [lo, lo + dim) in the field state E just written must be finite and at most
+// limit in magnitude (scaled units: the source's peak is 1).  On the first
+// violation halt[0] = 1 -- the step kernels of every later launch read it and
+// return at once -- and scal[7] = step (the steps done when it tripped).
+__global__ __launch_bounds__(256) void watch_kernel(const float* E, unsigned cstride, int nxp, int nyp, int3 lo,
+                                                    int3 dim, float limit, int step, unsigned* halt, double* scal)
+{
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const int n = dim.x * dim.y * dim.z;
+    int b = 0;
+    for (int t = threadIdx.x; t < 3 * n; t += blockDim.x) {
+        const int c = t / n, q = t - c * n;
+        const int i = lo.x + q % dim.x, j = lo.y + (q / dim.x) % dim.y, k = lo.z + q / (dim.x * dim.y);
+        const float v = ldf(E, (unsigned)c * cstride +
+                                   (((unsigned)(k + 1) * nyp + (unsigned)(j + 1)) * nxp + (unsigned)i) * 4u);
+        if (!(fabsf(v) <= limit)) b = 1;  // not finite, or too large
+    }
+    if (b) atomicOr(&bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0 && bad && halt[0] == 0u) {
+        halt[0] = 1u;
+        scal[7] = (double)step;
+    }
+}
+
 int grid_for(long long n) { long long g = (n + 255) / 256; return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096); }
 
 }  // namespace
@@ -1296,6 +1329,15 @@ int ccpr_launch_gap_spectrum(const float* gap, int M, int ne, double dt, const d
     if (nf <= 0 || ne <= 0) return 0;
     hipLaunchKernelGGL(gap_spectrum_kernel, dim3((unsigned)nf), dim3(256), 0, (hipStream_t)stream, gap, M, ne, dt,
                        omega, scale, out);
+    return (int)hipGetLastError();
+}
+
+int ccpr_launch_watch(const StepArgs& a, const int lo[3], const int dim[3], float limit, int n, unsigned* halt,
+                      double* scal, void* stream)
+{
+    hipLaunchKernelGGL(watch_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, (const float*)a.Eo, a.cstride,
+                       a.nxp, a.nyp, make_int3(lo[0], lo[1], lo[2]), make_int3(dim[0], dim[1], dim[2]), limit,
+                       n + 1, halt, scal);
     return (int)hipGetLastError();
 }
 

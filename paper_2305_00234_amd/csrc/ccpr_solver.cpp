@@ -49,6 +49,7 @@ struct Layout {
     size_t tiles;                // tile lists of the step kernel (interior, then CPML)
     size_t drive;                // S curl H' of design and source cells (scratch of one step)
     size_t rho, pmlE, pmlH, scal, gradacc, work;
+    size_t halt;                 // divergence watchdog word (see ccpr_launch_watch)
     size_t fixed_end;
     // variable part
     size_t src_fwd, src_adj, wave, lineE, lineH, incE, incH, tf, gap, T, ckpt, stage;
@@ -113,6 +114,15 @@ struct ccpr_solver {
     int src_table_steps = -1;   // steps covered by the uploaded forward source table
     Layout lay{};
     bool have_forward = false, have_adjoint = false;
+    // an adjoint run that recomputed segments wrote their history over the
+    // first resident segment's: a second adjoint needs a new forward run
+    bool hist_stale = false;
+    long long fwd_serial = 0;   // successful forward runs so far
+    // divergence watchdog: check the gap box every watch_every steps of the
+    // forward and adjoint runs (0: off) against watch_limit (scaled units)
+    int watch_every = 128;
+    double watch_limit = 1e15;
+    bool watch_run = false;     // inside a forward / adjoint loop
     int M = 0;
     double F = 0, adj_alpha = 1.0, grad_scale = 0;
     int current_state = 0;  // 0 forward, 1 adjoint (for get_field)
@@ -278,6 +288,7 @@ Layout make_layout(const ccpr_solver* s, int M, int K_req, int R_req = 1)
     L.scal = take(16 * 8);
     L.gradacc = take((size_t)std::max(n_rho(s), 1LL) * 8);
     L.work = take((size_t)std::max(s->gncell * 3, 1) * 16);
+    L.halt = take(16);
     L.fixed_end = o;
     // forward source tables cover the solve (or the waveform when stepping)
     const int nw = (int)s->wave.size();
@@ -815,6 +826,7 @@ StepArgs hot_args(ccpr_solver* s, int st)
     A.mode = 0;
     A.phc = A.phs = 0.f;
     A.cold = wsp<StepCold>(s, L.cold[st]);
+    A.halt = wsp<unsigned>(s, L.halt);
     A.zr = wsp<int2>(s, L.zr);
     A.tiles = wsp<int2>(s, L.tiles);
     A.nys = (s->g.ny + s->rows - 1) / s->rows;
@@ -897,9 +909,28 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
     if (e == 0)
         e = fuse ? ccpr_launch_post_fused(A, nmisc, C.pw_on ? C.tf_nH : 0, As)
                  : ccpr_launch_post(A, nxs, nmisc, As);
+    if (e == 0 && s->watch_run && s->watch_every > 0 && s->has_obj && (A.n + 1) % s->watch_every == 0)
+        e = ccpr_launch_watch(A, s->glo, s->gdim, (float)s->watch_limit, A.n, wsp<unsigned>(s, s->lay.halt),
+                              wsp<double>(s, s->lay.scal), As);
     if (e != 0) return fail(s, CCPR_EDEVICE, "step kernel launch: %s", hipGetErrorString((hipError_t)e));
     s->pre_done[st] = fuse;
     s->parity[st] ^= 1;
+    return CCPR_OK;
+}
+
+// Marks a forward / adjoint loop: launch_step runs the divergence watchdog
+// only inside one.
+struct WatchScope {
+    ccpr_solver* s;
+    explicit WatchScope(ccpr_solver* x) : s(x) { s->watch_run = true; }
+    ~WatchScope() { s->watch_run = false; }
+};
+
+// Re-arm the divergence watchdog (halt word and the step it records).
+ccpr_status clear_halt(ccpr_solver* s)
+{
+    HIPCHK(ccpr_launch_fill(wsp<float>(s, s->lay.halt), 2, 0.f, s->stream));
+    HIPCHK(ccpr_launch_fill_d(wsp<double>(s, s->lay.scal) + 7, 1, 0.0, s->stream));
     return CCPR_OK;
 }
 
@@ -1097,6 +1128,8 @@ ccpr_status refresh_fixed(ccpr_solver* s, bool force)
     s->rho_uploaded = false;
     if (!s->rho_on_host && s->has_design) s->has_design = false;  // device densities must be set again
     HIPCHK(ccpr_launch_fill_d(wsp<double>(s, s->lay.scal), 16, 0.0, s->stream));
+    st = clear_halt(s);
+    if (st) return st;
     st = zero_state(s, 0);
     if (st) return st;
     st = zero_state(s, 1);
@@ -1185,6 +1218,12 @@ ccpr_status check_results(ccpr_solver* s, const double* scal)
     s->F = scal[4];
     s->grad_scale = scal[5];
     s->adj_alpha = scal[6];
+    if (scal[7] > 0) {
+        s->step_count = (int)scal[7];
+        return fail(s, CCPR_EDIVERGED,
+                    "the fields diverged: the watchdog found a gap-box field above %g (or not finite) after %d steps",
+                    s->watch_limit, (int)scal[7]);
+    }
     if (!std::isfinite(s->F) || !std::isfinite(scal[1]))
         return fail(s, CCPR_EDIVERGED, "objective is not finite: the fields diverged");
     return CCPR_OK;
@@ -1475,6 +1514,8 @@ ccpr_status ccpr_reset(ccpr_solver* s)
     if (st) return st;
     s->step_count = 0;
     s->current_state = 0;
+    st = clear_halt(s);
+    if (st) return st;
     return zero_state(s, 0);
 }
 
@@ -1498,6 +1539,8 @@ ccpr_status ccpr_step(ccpr_solver* s, int n)
                     s->lay.inc_steps);
     build_mats(s);
     st = upload_cold(s, 0);
+    if (st) return st;
+    st = clear_halt(s);
     if (st) return st;
     s->current_state = 0;
     for (int q = 0; q < n; ++q) {
@@ -1556,6 +1599,9 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
     if (st) return st;
     HIPCHK(ccpr_launch_fill(wsp<float>(s, L.gap), (long long)s->gncell * 3, 0.f, s->stream));
     if (s->grad_dft) HIPCHK(ccpr_launch_fill(wsp<float>(s, L.T), 12 * std::max(s->nd, 1LL), 0.f, s->stream));
+    st = clear_halt(s);
+    if (st) return st;
+    s->have_forward = s->have_adjoint = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s->timing) {
         HIPCHK(hipEventCreate(&e0));
@@ -1563,13 +1609,16 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
         HIPCHK(hipEventRecord(e0, s->stream));
     }
     s->timed_loop = s->timing;
-    for (int n = 0; n < M; ++n) {
-        if (saves_checkpoint(L, n)) {
-            st = checkpoint(s, n / K - 1, true);
+    {
+        WatchScope watch(s);
+        for (int n = 0; n < M; ++n) {
+            if (saves_checkpoint(L, n)) {
+                st = checkpoint(s, n / K - 1, true);
+                if (st) return st;
+            }
+            st = forward_step(s, n, forward_slot(L, n), true, fuse_forward(s, n + 1));
             if (st) return st;
         }
-        st = forward_step(s, n, forward_slot(L, n), true, fuse_forward(s, n + 1));
-        if (st) return st;
     }
     st = join_lead(s);
     if (st) return st;
@@ -1599,6 +1648,8 @@ ccpr_status ccpr_forward(ccpr_solver* s, int nsteps, double* objective_out)
     if (st) return st;
     s->have_forward = true;
     s->have_adjoint = false;
+    s->hist_stale = false;
+    ++s->fwd_serial;
     if (objective_out) *objective_out = s->F;
     return CCPR_OK;
 }
@@ -1607,6 +1658,9 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
 {
     if (!s) return CCPR_EINVAL;
     if (!s->have_forward) return fail(s, CCPR_ESTATE, "adjoint needs a completed forward run");
+    if (s->hist_stale)
+        return fail(s, CCPR_ESTATE, "the last adjoint run recomputed segments over the forward history: "
+                                    "run ccpr_forward again before another adjoint");
     const Layout& L = s->lay;
     const int M = s->M, K = L.K, S = L.S;
     const long long ndm = std::max(s->nd, 1LL);
@@ -1619,6 +1673,10 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms_total = 0;
     s->timed_loop = s->timing;
+    WatchScope watch(s);
+    s->have_adjoint = false;
+    // recomputed segments write their history over the first resident one's
+    s->hist_stale = S > L.R && !s->grad_dft;
     for (int seg = S - 1; seg >= 0; --seg) {
         const int n0 = seg * K, n1 = std::min(M, n0 + K);
         if (seg < S - L.R) {
@@ -1667,6 +1725,15 @@ ccpr_status ccpr_adjoint(ccpr_solver* s)
         if (st) return st;
     }
     s->current_state = 1;
+    if (s->watch_every > 0) {
+        double tripped = 0;
+        HIPCHK(hipMemcpyAsync(&tripped, wsp<double>(s, L.scal) + 7, sizeof tripped, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        if (tripped > 0)
+            return fail(s, CCPR_EDIVERGED,
+                        "the adjoint fields diverged: the watchdog found a gap-box field above %g (or not finite) "
+                        "after %d adjoint steps", s->watch_limit, (int)tripped);
+    }
     s->have_adjoint = true;
     return CCPR_OK;
 }
@@ -1765,6 +1832,22 @@ ccpr_status ccpr_set_tile_planes(ccpr_solver* s, int planes)
     return CCPR_OK;
 }
 
+ccpr_status ccpr_set_watchdog(ccpr_solver* s, int every, double limit)
+{
+    if (!s) return CCPR_EINVAL;
+    if (every < 0 || !(limit > 0) || !std::isfinite(limit) || limit > 3e38)
+        return fail(s, CCPR_EINVAL, "watchdog: every must be >= 0 and 0 < limit <= 3e38");
+    s->watch_every = every;
+    s->watch_limit = limit;
+    return CCPR_OK;
+}
+
+long long ccpr_forward_serial(const ccpr_solver* s)
+{
+    if (!s || !s->have_forward || s->hist_stale) return -1;
+    return s->fwd_serial;
+}
+
 ccpr_status ccpr_set_tile_rows(ccpr_solver* s, int rows)
 {
     if (!s) return CCPR_EINVAL;
@@ -1801,6 +1884,8 @@ ccpr_status ccpr_pipe_begin(ccpr_solver* s, int nsteps)
     HIPCHK(ccpr_launch_fill(wsp<float>(s, s->lay.gap), (long long)s->gncell * 3, 0.f, s->stream));
     if (s->grad_dft)
         HIPCHK(ccpr_launch_fill(wsp<float>(s, s->lay.T), 12 * std::max(s->nd, 1LL), 0.f, s->stream));
+    st = clear_halt(s);
+    if (st) return st;
     s->have_forward = s->have_adjoint = false;
     s->pipe_phase = 0;
     s->pipe_n = 0;
@@ -1813,6 +1898,7 @@ int ccpr_pipe_advance(ccpr_solver* s, int max_steps)
     const int M = s->M, K = L.K, S = L.S;
     int done = 0;
     ccpr_status st = CCPR_OK;
+    WatchScope watch(s);
     while (done < max_steps && s->pipe_phase != 3) {
         if (s->pipe_phase == 0) {  // forward step n
             const int n = s->pipe_n;
@@ -1903,6 +1989,8 @@ ccpr_status ccpr_pipe_check(ccpr_solver* s, const double* scal_host, double* F)
     ccpr_status st = check_results(s, scal_host);
     if (st) return st;
     s->have_forward = s->have_adjoint = true;
+    s->hist_stale = s->lay.S > s->lay.R && !s->grad_dft;
+    ++s->fwd_serial;
     if (F) *F = s->F;
     return CCPR_OK;
 }

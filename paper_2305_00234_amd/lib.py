@@ -7,6 +7,7 @@ library has not been built, ``load()`` raises.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 from typing import Optional, Sequence
@@ -34,7 +35,7 @@ EXPORTS = [
     "ccpr_set_checkpointing", "ccpr_set_gradient_mode", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
     "ccpr_adjoint", "ccpr_gradient", "ccpr_gap_spectrum", "ccpr_reset", "ccpr_step", "ccpr_get_field",
     "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_grid_timing", "ccpr_get_info",
-    "ccpr_set_tile_planes", "ccpr_set_tile_rows",
+    "ccpr_set_tile_planes", "ccpr_set_tile_rows", "ccpr_set_watchdog", "ccpr_forward_serial",
     "ccpr_engine_create", "ccpr_engine_submit", "ccpr_engine_poll", "ccpr_engine_wait",
     "ccpr_engine_result", "ccpr_engine_release", "ccpr_engine_last_error", "ccpr_engine_destroy",
     "ccpr_filter_project", "ccpr_filter_project_grad", "ccpr_nondiscreteness",
@@ -106,6 +107,8 @@ def load():
         "ccpr_get_info": (_i, [_p, _ip, _ip, _ip]),
         "ccpr_set_tile_planes": (_i, [_p, _i]),
         "ccpr_set_tile_rows": (_i, [_p, _i]),
+        "ccpr_set_watchdog": (_i, [_p, _i, _d]),
+        "ccpr_forward_serial": (C.c_longlong, [_p]),
         "ccpr_engine_create": (_i, [_p, C.c_uint64, _i, _i, C.POINTER(_p)]),
         "ccpr_engine_submit": (_i, [_p, _p, _i, C.POINTER(C.c_uint64)]),
         "ccpr_engine_poll": (_i, [_p, C.c_uint64, _ip]),
@@ -257,11 +260,33 @@ class Solver:
         self._keep = []
         self.design_dims = None
         self.per_edge = False
+        self._bound_stream = None   # torch stream the workspace was bound with
 
     # -- plumbing
     def _chk(self, st, what):
         if st != OK:
             raise CcprError(st, what, self._lib.ccpr_last_error(self._h).decode())
+
+    @contextlib.contextmanager
+    def _ordered(self):
+        """The library enqueues on the stream bound with the workspace.  When
+        torch's current stream is another one, order the bound stream after
+        the work already on the current stream (device inputs) and the current
+        stream after the call's work (device outputs)."""
+        bs = self._bound_stream
+        if bs is None:
+            yield
+            return
+        import torch
+        cur = torch.cuda.current_stream(bs.device)
+        other = cur.cuda_stream != bs.cuda_stream
+        if other:
+            bs.wait_stream(cur)
+        try:
+            yield
+        finally:
+            if other:
+                cur.wait_stream(bs)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -293,9 +318,10 @@ class Solver:
             import torch
             assert rho.dtype == torch.float32 and rho.is_contiguous() and rho.dim() == 3
             dims = (rho.shape[2], rho.shape[1], rho.shape[0])
-            self._chk(self._lib.ccpr_set_design(self._h, _i3(lo), _i3(dims), gamma,
-                                                C.c_void_p(rho.data_ptr()), MEM_DEVICE),
-                      "ccpr_set_design")
+            with self._ordered():
+                self._chk(self._lib.ccpr_set_design(self._h, _i3(lo), _i3(dims), gamma,
+                                                    C.c_void_p(rho.data_ptr()), MEM_DEVICE),
+                          "ccpr_set_design")
         else:
             r = np.ascontiguousarray(rho, dtype=np.float32)
             dims = (r.shape[2], r.shape[1], r.shape[0])
@@ -315,9 +341,10 @@ class Solver:
         if hasattr(rho_edges, "data_ptr") and getattr(rho_edges, "is_cuda", False):
             import torch
             assert rho_edges.dtype == torch.float32 and rho_edges.is_contiguous() and rho_edges.numel() == n
-            self._chk(self._lib.ccpr_set_design_edges(self._h, _i3(lo), _i3(dims), gamma,
-                                                      C.c_void_p(rho_edges.data_ptr()), MEM_DEVICE),
-                      "ccpr_set_design_edges")
+            with self._ordered():
+                self._chk(self._lib.ccpr_set_design_edges(self._h, _i3(lo), _i3(dims), gamma,
+                                                          C.c_void_p(rho_edges.data_ptr()), MEM_DEVICE),
+                          "ccpr_set_design_edges")
         else:
             parts = []
             for c in range(3):
@@ -411,19 +438,31 @@ class Solver:
         if nbytes > free - reserve:
             nbytes = max(free - reserve, 1 << 20)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        stream = torch.cuda.current_stream(dev).cuda_stream
-        self.bind_workspace(ws.data_ptr(), nbytes, stream)
+        stream = torch.cuda.current_stream(dev)
+        self.bind_workspace(ws.data_ptr(), nbytes, stream.cuda_stream)
+        self._bound_stream = stream
         self._ws = ws
         return ws
 
     # -- running
     def forward(self, nsteps) -> float:
         F = C.c_double(0.0)
-        self._chk(self._lib.ccpr_forward(self._h, nsteps, C.byref(F)), "ccpr_forward")
+        with self._ordered():
+            self._chk(self._lib.ccpr_forward(self._h, nsteps, C.byref(F)), "ccpr_forward")
         return F.value
 
     def adjoint(self):
-        self._chk(self._lib.ccpr_adjoint(self._h), "ccpr_adjoint")
+        with self._ordered():
+            self._chk(self._lib.ccpr_adjoint(self._h), "ccpr_adjoint")
+
+    @property
+    def forward_serial(self) -> int:
+        """Serial of the forward run the next adjoint would use (-1: none)."""
+        return int(self._lib.ccpr_forward_serial(self._h))
+
+    def set_watchdog(self, every: int = 128, limit: float = 1e15):
+        """Divergence watchdog: check the gap box every 'every' steps (0: off)."""
+        self._chk(self._lib.ccpr_set_watchdog(self._h, int(every), float(limit)), "ccpr_set_watchdog")
 
     def gap_spectrum(self, omegas):
         """Mean |E_hat(omega)|^2 over the gap edges of the last forward run, for
@@ -442,8 +481,9 @@ class Solver:
         if out is not None and getattr(out, "is_cuda", False):
             if out.numel() != self.gradient_size:
                 raise ValueError(f"gradient output holds {out.numel()} values, need {self.gradient_size}")
-            self._chk(self._lib.ccpr_gradient(self._h, C.c_void_p(out.data_ptr()), MEM_DEVICE),
-                      "ccpr_gradient")
+            with self._ordered():
+                self._chk(self._lib.ccpr_gradient(self._h, C.c_void_p(out.data_ptr()), MEM_DEVICE),
+                          "ccpr_gradient")
             return out
         g = np.empty(self.gradient_size, dtype=np.float64)
         self._chk(self._lib.ccpr_gradient(self._h, g.ctypes.data_as(C.c_void_p), MEM_HOST),
@@ -451,15 +491,18 @@ class Solver:
         return self.split_edges(g) if self.per_edge else g.reshape(d[2], d[1], d[0])
 
     def reset(self):
-        self._chk(self._lib.ccpr_reset(self._h), "ccpr_reset")
+        with self._ordered():
+            self._chk(self._lib.ccpr_reset(self._h), "ccpr_reset")
 
     def step(self, n=1):
-        self._chk(self._lib.ccpr_step(self._h, int(n)), "ccpr_step")
+        with self._ordered():
+            self._chk(self._lib.ccpr_step(self._h, int(n)), "ccpr_step")
 
     def field(self, comp, out=None):
         if out is not None and getattr(out, "is_cuda", False):
-            self._chk(self._lib.ccpr_get_field(self._h, comp, C.c_void_p(out.data_ptr()), MEM_DEVICE),
-                      "ccpr_get_field")
+            with self._ordered():
+                self._chk(self._lib.ccpr_get_field(self._h, comp, C.c_void_p(out.data_ptr()), MEM_DEVICE),
+                          "ccpr_get_field")
             return out
         f = np.empty(self.shape, dtype=np.float32)
         self._chk(self._lib.ccpr_get_field(self._h, comp, f.ctypes.data_as(C.c_void_p), MEM_HOST),

@@ -93,13 +93,74 @@ def gpu_gradient(w: Workload, tile_planes=None, checkpoint_every=None, want_adjo
 def oracle_gradient(w: Workload):
     o = oracle_from_workload(w)
     kind = OBJ_DFT if w.objective == "dft" else OBJ_TIME
-    # forward fields at the end of the run (the gradient call leaves the adjoint)
-    o.reset()
-    o.run(w.steps)
-    fwd = o.fields()
     if w.gradient == "dft":
         F, g = o.gradient_dft(w.steps, w.gap_lo, w.gap_dims, w.omega)
     else:
         F, g = o.gradient(w.steps, kind, w.gap_lo, w.gap_dims, w.omega, w.window[0], w.window_end)
-    adj = o.fields()
+    fwd = o.forward_end_fields()    # the state at the end of the forward run
+    adj = o.fields()                # the gradient call leaves the adjoint fields
     return F, g, fwd, adj
+
+
+def _state(fields):
+    """(6, nz, ny, nx) float64 state with H scaled by eta0 (energy norm)."""
+    f = np.stack([np.asarray(x, np.float64) for x in fields])
+    f[3:] *= ETA0
+    return f
+
+
+def region_masks(w: Workload):
+    """Cell masks (nz, ny, nx) of the regions where local errors would be
+    diluted in a whole-grid norm: the design box, the gap, the CPML slabs,
+    the TF/SF shell (cells within one cell of the total-field box's faces),
+    the far faces (the last two cell layers along each axis, where the
+    kernels' tiles end ragged) and the rest of the grid."""
+    nx, ny, nz = w.shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = {}
+    lo, d = w.design_lo, w.design_dims
+    e = 1 if w.rho_edges is not None else 0
+    out["design"] = ((i >= lo[0]) & (i < lo[0] + d[0] + e) & (j >= lo[1]) & (j < lo[1] + d[1] + e) &
+                     (k >= lo[2]) & (k < lo[2] + d[2] + e))
+    g, gd = w.gap_lo, w.gap_dims
+    out["gap"] = ((i >= g[0]) & (i < g[0] + gd[0]) & (j >= g[1]) & (j < g[1] + gd[1]) &
+                  (k >= g[2]) & (k < g[2] + gd[2]))
+    p = w.npml
+    if p > 0:
+        out["cpml"] = ((i < p) | (i >= nx - p) | (j < p) | (j >= ny - p) | (k < p) | (k >= nz - p))
+    if w.source == "planewave":
+        a, b = w.tfsf_lo, w.tfsf_hi
+        near = np.zeros_like(out["gap"])
+        inside = np.ones_like(out["gap"])
+        for ax, q in ((0, i), (1, j), (2, k)):
+            near |= (np.abs(q - a[ax]) <= 1) | (np.abs(q - b[ax]) <= 1)
+            inside &= (q >= a[ax] - 1) & (q <= b[ax] + 1)
+        out["tfsf_shell"] = near & inside
+    out["far_faces"] = (i >= nx - 2) | (j >= ny - 2) | (k >= nz - 2)
+    rest = np.ones_like(out["gap"])
+    for m in out.values():
+        rest &= ~m
+    out["rest"] = rest
+    return out
+
+
+def region_errors(gpu_fields, or_fields, w: Workload):
+    """Relative L2 error of the (E, eta0 H) state inside each region of
+    region_masks, and the largest error of any field word over the state's
+    peak ("max_abs/peak"), with each region's share of the state's norm."""
+    g, o = _state(gpu_fields), _state(or_fields)
+    d = g - o
+    tot = np.linalg.norm(o)
+    res = {"max_abs/peak": float(np.max(np.abs(d)) / np.max(np.abs(o)))}
+    for name, m in region_masks(w).items():
+        if not m.any():
+            continue
+        on = np.linalg.norm(o[:, m])
+        res[name] = (float(np.linalg.norm(d[:, m]) / on) if on > 0 else float(np.linalg.norm(d[:, m])),
+                     float(on / tot))
+    return res
+
+
+def fmt_regions(r):
+    return ", ".join(f"{k} {v:.2e}" if not isinstance(v, tuple) else f"{k} {v[0]:.2e} (norm share {v[1]:.1e})"
+                     for k, v in r.items())

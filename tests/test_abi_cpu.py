@@ -221,3 +221,17 @@ def test_edge_design_validation_and_workspace(built):
     ne, nv = 523, 210
     assert b_edge - b_vox == (a256(4 * ne) - a256(4 * nv)) + (a256(8 * ne) - a256(8 * nv))
     s.close()
+
+
+def test_watchdog_and_forward_serial_on_host(built):
+    """ccpr_set_watchdog validates its arguments; without a forward run there
+    is no forward state to differentiate (serial -1)."""
+    s = L.Solver(24, 24, 24, 10e-9, npml=4)
+    assert s.forward_serial == -1
+    s.set_watchdog(0)                   # off
+    s.set_watchdog(64, 1e20)
+    for every, limit in ((-1, 1e15), (16, 0.0), (16, float("nan")), (16, 1e39)):
+        with pytest.raises(L.CcprError) as e:
+            s.set_watchdog(every, limit)
+        assert e.value.status == L.EINVAL
+    s.close()

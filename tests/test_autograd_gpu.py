@@ -110,3 +110,108 @@ def test_full_size_time_domain_checkpoint_invariance():
     assert F1 == F2 and F1 > 0
     assert np.array_equal(g1, g2)
     assert np.isfinite(g1).all() and np.abs(g1).max() > 0
+
+
+def _recompute_case():
+    """400-step Drude dipole run in 100-step segments, two resident: the
+    adjoint recomputes two segments over the first resident one's history."""
+    w = _small("time")
+    w.steps = 400
+    w.wave = I.drude_dipole_32(steps=400).wave
+    w.window = (60, 380)
+    return w
+
+
+def test_second_adjoint_needs_a_new_forward_run():
+    """After an adjoint that recomputed segments the history of the first
+    resident segment is gone: a second adjoint is refused (CCPR_ESTATE) and
+    the forward serial reads -1; a new forward run restores it, and the
+    gradient is then bitwise the first one."""
+    require_gpu()
+    from paper_2305_00234_amd import lib as L
+    from paper_2305_00234_amd.solver import configure
+    w = _recompute_case()
+    s = configure(w)
+    s.set_checkpointing(100)
+    s.set_resident_segments(2)
+    s.bind_torch(w.steps)
+    s.forward(w.steps)
+    serial = s.forward_serial
+    assert serial >= 1 and s.info()["segments"] == 4 and s.info()["resident_segments"] == 2
+    s.adjoint()
+    g1 = s.gradient()
+    assert s.forward_serial == -1
+    with pytest.raises(L.CcprError) as e:
+        s.adjoint()
+    assert e.value.status == L.ESTATE
+    s.forward(w.steps)
+    assert s.forward_serial == serial + 1
+    s.adjoint()
+    g2 = s.gradient()
+    s.close()
+    assert np.array_equal(g1, g2)
+
+
+def test_autograd_retain_graph_and_shared_solver():
+    """backward(retain_graph=True) twice on a recomputing layout gives the
+    same gradient bitwise (the second backward runs its forward again), and
+    two objectives evaluated on one solver before a joint backward each get
+    their own gradient (the earlier node re-runs its forward)."""
+    torch = require_gpu()
+    from paper_2305_00234_amd.autograd import objective
+    from paper_2305_00234_amd.solver import configure
+    w = _recompute_case()
+    s = configure(w)
+    s.set_checkpointing(100)
+    s.set_resident_segments(2)
+    s.bind_torch(w.steps)
+    rho = torch.tensor(w.rho, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = objective(rho, s, w.steps, w.design_lo, w.gamma)
+    F.backward(retain_graph=True)
+    g1 = rho.grad.detach().clone()
+    rho.grad = None
+    F.backward()
+    g2 = rho.grad.detach().clone()
+    assert torch.equal(g1, g2)
+    # two densities through one solver, one backward
+    rho_b = (0.5 * rho.detach()).clone().requires_grad_(True)
+    ra = rho.detach().clone().requires_grad_(True)
+    Fa = objective(ra, s, w.steps, w.design_lo, w.gamma)
+    Fb = objective(rho_b, s, w.steps, w.design_lo, w.gamma)
+    (Fa + Fb).backward()
+    Fb_alone = objective(rho_b.detach().clone().requires_grad_(True), s, w.steps, w.design_lo, w.gamma)
+    s.close()
+    assert torch.equal(ra.grad, g1)
+    assert float(Fb_alone.detach()) == float(Fb.detach())
+    assert float(Fa.detach()) == float(F.detach())
+    say("shared solver: grad a == single backward; F_b", float(Fb.detach()))
+
+
+def test_objective_on_another_torch_stream():
+    """The workspace is bound with torch's default stream; the density is
+    produced and the objective differentiated under another torch stream.
+    The binding orders the library's stream after the caller's and the
+    caller's after the library's: F and the gradient equal those of the
+    default-stream run bitwise."""
+    torch = require_gpu()
+    from paper_2305_00234_amd.autograd import objective
+    from paper_2305_00234_amd.solver import configure
+    w = _small("dft")
+    s = configure(w)
+    s.bind_torch(w.steps)
+    base = torch.tensor(w.rho, dtype=torch.float64, device="cuda")
+    r0 = base.clone().requires_grad_(True)
+    F0 = objective(r0, s, w.steps, w.design_lo, w.gamma)
+    F0.backward()
+    g0 = r0.grad.detach().clone()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        # a density computed on the side stream just before the call
+        r1 = (base * 2.0 - base).requires_grad_(True)
+        F1 = objective(r1, s, w.steps, w.design_lo, w.gamma)
+        F1.backward()
+        g1 = (r1.grad * 1.0)      # consumed on the side stream
+    torch.cuda.synchronize()
+    s.close()
+    assert float(F1.detach()) == float(F0.detach())
+    assert torch.equal(g1, g0)

@@ -1,8 +1,9 @@
 """Failure detection forced from the host, with every kernel exiting
 normally: a non-passive material (negative static susceptibility) makes the
-fields grow until they overflow; ccpr_forward reports CCPR_EDIVERGED, the
-adjoint refuses to run on that solve, and the solver runs again once the
-material is passive."""
+fields grow; the divergence watchdog (a check of the gap box every 64
+steps) stops the run long before its end and ccpr_forward reports
+CCPR_EDIVERGED, the adjoint refuses to run on that solve, and the solver
+runs again once the material is passive."""
 import math
 
 import numpy as np
@@ -29,10 +30,14 @@ def test_active_medium_reports_divergence_and_recovers():
     w.mat2 = (active,) * 3
     s = configure(w)
     s.bind_torch(w.steps)
+    s.set_watchdog(64)
     with pytest.raises(L.CcprError) as e:
         s.forward(w.steps)
-    say("active medium:", e.value)
+    say("active medium:", e.value, "steps done when it tripped:", s.step_count)
     assert e.value.status == L.EDIVERGED
+    # the watchdog stopped the run well before its end (the steps after it
+    # are skipped on the device)
+    assert 0 < s.step_count < w.steps and s.step_count % 64 == 0
     with pytest.raises(L.CcprError) as e:
         s.adjoint()
     assert e.value.status == L.ESTATE

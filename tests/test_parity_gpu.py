@@ -393,3 +393,32 @@ def test_most_pole_pairs_per_axis_gradient(pairs):
     assert st <= FIELD_TOL
     assert abs(Fg - Fo) <= FIELD_TOL * abs(Fo)
     assert rel_l2(gg, go) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("source", ["dipole", "planewave"])
+def test_kappa_graded_cpml_fields_and_gradient(source):
+    """A CPML grading with every term active: kappa_max = 5 (the 1/kappa
+    scaling of the differences in the y/z-layer tiles of the grid kernel and
+    in the x-layer pre/post corrections), alpha_max = 0.1, polynomial order 4
+    and 1.2x the default conductivity.  Fields (whole grid and per region,
+    CPML slabs included), objective and gradient against the oracle."""
+    from tests.gpu_util import fmt_regions, region_errors
+    if source == "dipole":
+        w = _dipole_box(n=(70, 38, 33), npml=6, steps=220,
+                        mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
+    else:
+        w = I.gold_gap(n=(66, 41, 45), design=(20, 13, 11), gap=2, npml=6, steps=220, seed=7,
+                       name="tfsf_kappa")
+        _short_pulse(w)
+    w.pml_m, w.pml_kappa_max, w.pml_alpha_max, w.pml_sigma_scale = 4.0, 5.0, 0.1, 1.2
+    Fg, gg, fg, _, _ = gpu_gradient(w, tile_planes=6)
+    Fo, go, fo, _ = oracle_gradient(w)
+    st, eE, eH = field_errors(fg, fo)
+    reg = region_errors(fg, fo, w)
+    msg = (f"kappa CPML {source}: state {st:.2e} (E {eE:.2e}, H {eH:.2e}); F rel {abs(Fg - Fo) / abs(Fo):.2e}; "
+           f"grad {rel_l2(gg, go):.2e}; regions {fmt_regions(reg)}")
+    say(msg)
+    assert st <= FIELD_TOL, msg
+    assert reg["cpml"][0] <= FIELD_TOL, msg
+    assert abs(Fg - Fo) <= FIELD_TOL * abs(Fo), msg
+    assert rel_l2(gg, go) <= GRAD_TOL, msg
