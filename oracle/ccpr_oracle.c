@@ -94,6 +94,8 @@ struct or_sim {
     /* copy of the six fields at the end of the last forward run of
      * or_gradient / or_gradient_dft / or_objective (NULL until kept) */
     double* fwd_end[6];
+    /* diagnostic (or_set_fp32_storage): round the stored state to FP32 */
+    int fp32_store;
 };
 
 static size_t idx3(const or_sim* s, int i, int j, int k)
@@ -429,8 +431,10 @@ static double inc_at(const or_sim* s, int P2)
 {
     int u2 = s->pw_sgn * (P2 - s->pw_ref2);
     if (u2 < 0) return 0.0;
-    if ((u2 & 1) == 0) return u2 / 2 <= s->pw_L ? s->pw_E[u2 / 2] : 0.0;
-    return (u2 - 1) / 2 <= s->pw_L ? s->pw_H[(u2 - 1) / 2] : 0.0;
+    double v;
+    if ((u2 & 1) == 0) v = u2 / 2 <= s->pw_L ? s->pw_E[u2 / 2] : 0.0;
+    else v = (u2 - 1) / 2 <= s->pw_L ? s->pw_H[(u2 - 1) / 2] : 0.0;
+    return s->fp32_store ? (double)(float)v : v;
 }
 
 /* E_e at cell (i,j,k) as seen by an H point whose TF status is tfH. */
@@ -595,14 +599,35 @@ static void update_E(or_sim* s, double* T)
                 }
 }
 
+/* Diagnostic FP32 storage: every stored state word rounded to FP32. */
+static void round_fp32(double* a, size_t n)
+{
+    if (!a) return;
+    for (size_t q = 0; q < n; ++q) a[q] = (double)(float)a[q];
+}
+
+static void store_fp32(or_sim* s, int h)
+{
+    const size_t nc = ncells(s);
+    for (int c = 0; c < 3; ++c) {
+        round_fp32(s->F[h ? 3 + c : c], nc);
+        for (int d = 0; d < 3; ++d) round_fp32(h ? s->psiH[c][d] : s->psiE[c][d], nc);
+    }
+    if (!h && s->J) round_fp32((double*)s->J, s->eoff[3] * 2 * OR_MAX_PAIRS * 2);
+}
+
 static void step_once(or_sim* s, double* T)
 {
     update_H(s);
     if (s->pw_on) line_update_H(s);
+    if (s->fp32_store) store_fp32(s, 1);
     update_E(s, T);
     if (s->pw_on) line_update_E(s, s->step + 1);
+    if (s->fp32_store) store_fp32(s, 0);
     s->step += 1;
 }
+
+void or_set_fp32_storage(or_sim* s, int on) { s->fp32_store = on != 0; }
 
 void or_run(or_sim* s, int nsteps)
 {

@@ -142,6 +142,13 @@ void or_eps_ccpr(const or_sim* s, int axis, double rho, double gamma, double w,
 
 int or_num_threads(void);
 
+/* Diagnostic, not part of the reference: with on != 0 every stored state
+ * word (fields, CPML memories, pole currents, incident-wave values as read)
+ * is rounded to FP32 after each half-step update, the arithmetic staying
+ * FP64.  It measures the floor that FP32 storage alone puts under any FP32
+ * implementation of the same recurrence. */
+void or_set_fp32_storage(or_sim* s, int on);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,7 @@ def _lib():
         lib.or_edge_response.argtypes = [_p, _i, _d, _d, _dp, _i, _dp]
         lib.or_eps_ccpr.argtypes = [_p, _i, _d, _d, _d, _dp, _dp]
         lib.or_num_threads.restype = _i
+        lib.or_set_fp32_storage.argtypes = [_p, _i]
         _LIB = lib
     return _LIB
 
@@ -203,6 +204,11 @@ class OracleSim:
 
     def fields(self):
         return [self.field(c) for c in range(6)]
+
+    def set_fp32_storage(self, on=True):
+        """Diagnostic: round every stored state word to FP32 after each update
+        (FP64 arithmetic), to measure the floor FP32 storage alone sets."""
+        _lib().or_set_fp32_storage(self._h, 1 if on else 0)
 
     def forward_end_fields(self):
         """The six fields at the end of the forward run inside the last

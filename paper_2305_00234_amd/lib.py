@@ -419,6 +419,7 @@ class Solver:
     def bind_workspace(self, ptr: int, nbytes: int, stream: int = 0):
         self._chk(self._lib.ccpr_bind_workspace(self._h, C.c_void_p(ptr), nbytes, C.c_void_p(stream)),
                   "ccpr_bind_workspace")
+        self._bound_stream = None
 
     def bind_torch(self, nsteps: int, device=None, extra: int = 0, reserve: int = 4 << 30,
                    greedy: bool = True):

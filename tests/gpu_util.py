@@ -102,6 +102,22 @@ def oracle_gradient(w: Workload):
     return F, g, fwd, adj
 
 
+def fp32_storage_fields(w: Workload, marks):
+    """The oracle's forward fields at the given steps (ascending) with every
+    stored state word rounded to FP32 after each update (FP64 arithmetic):
+    the floor that FP32 storage alone puts under any FP32 implementation of
+    the same recurrence."""
+    o = oracle_from_workload(w)
+    o.set_fp32_storage(True)
+    o.reset()
+    out, n = [], 0
+    for m in marks:
+        o.run(m - n)
+        n = m
+        out.append(o.fields())
+    return out
+
+
 def _state(fields):
     """(6, nz, ny, nx) float64 state with H scaled by eta0 (energy norm)."""
     f = np.stack([np.asarray(x, np.float64) for x in fields])

@@ -402,7 +402,7 @@ def test_kappa_graded_cpml_fields_and_gradient(source):
     in the x-layer pre/post corrections), alpha_max = 0.1, polynomial order 4
     and 1.2x the default conductivity.  Fields (whole grid and per region,
     CPML slabs included), objective and gradient against the oracle."""
-    from tests.gpu_util import fmt_regions, region_errors
+    from tests.gpu_util import fmt_regions, fp32_storage_fields, region_errors
     if source == "dipole":
         w = _dipole_box(n=(70, 38, 33), npml=6, steps=220,
                         mats=((I.VACUUM,) * 3, (I.GOLD_TABLE1,) * 3))
@@ -415,10 +415,15 @@ def test_kappa_graded_cpml_fields_and_gradient(source):
     Fo, go, fo, _ = oracle_gradient(w)
     st, eE, eH = field_errors(fg, fo)
     reg = region_errors(fg, fo, w)
+    # the CPML slabs hold attenuated fields: compare their error with the
+    # floor FP32 storage alone leaves there (the oracle with its state
+    # rounded to FP32), as the long-horizon tests do
+    (f32,) = fp32_storage_fields(w, (w.steps,))
+    floor = region_errors(f32, fo, w)["cpml"][0]
     msg = (f"kappa CPML {source}: state {st:.2e} (E {eE:.2e}, H {eH:.2e}); F rel {abs(Fg - Fo) / abs(Fo):.2e}; "
-           f"grad {rel_l2(gg, go):.2e}; regions {fmt_regions(reg)}")
+           f"grad {rel_l2(gg, go):.2e}; regions {fmt_regions(reg)}; FP32-storage floor in the CPML {floor:.2e}")
     say(msg)
     assert st <= FIELD_TOL, msg
-    assert reg["cpml"][0] <= FIELD_TOL, msg
+    assert reg["cpml"][0] <= max(FIELD_TOL, 2.0 * floor), msg
     assert abs(Fg - Fo) <= FIELD_TOL * abs(Fo), msg
     assert rel_l2(gg, go) <= GRAD_TOL, msg
