@@ -61,6 +61,7 @@ enum { CCPR_EX = 0, CCPR_EY, CCPR_EZ, CCPR_HX, CCPR_HY, CCPR_HZ };
 
 #define CCPR_MAX_PAIRS_PER_AXIS 8 /* pole pairs over both materials, per axis */
 #define CCPR_MAX_NX 1024          /* x extent handled by one workgroup row    */
+#define CCPR_STATIC_WORKSPACE_BYTES (64ull << 20) /* ccpr_bind_static_workspace */
 
 typedef struct ccpr_solver ccpr_solver;
 
@@ -216,6 +217,24 @@ ccpr_status ccpr_workspace_size_max(const ccpr_solver* s, int nsteps, uint64_t* 
  * HIP stream (hipStream_t, may be NULL for the null stream).  The library
  * never allocates device memory itself.  Rebinding resets the solver. */
 ccpr_status ccpr_bind_workspace(ccpr_solver* s, void* dev_ptr, uint64_t bytes, void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bind the
+ * library's own static workspace of the current device instead of a caller
+ * buffer -- a file-scope device array of CCPR_STATIC_WORKSPACE_BYTES (64 MiB)
+ * that each device holds from its first such bind until the process ends.
+ * Same semantics as ccpr_bind_workspace with that buffer; neither this call
+ * nor the solves run on it allocate (no hipMalloc / hipFree, no stream or
+ * event creation: the grid pass runs as one launch on hip_stream).
+ * Limits: a solve whose workspace (ccpr_workspace_size) exceeds the array
+ * fails with CCPR_ENOMEM at bind time (fixed part) or at ccpr_forward (with
+ * its history), with a message naming both sizes.  One solver per device at
+ * a time: binding another solver to the same device's array unbinds the
+ * previous one (its later calls report CCPR_ESTATE, no workspace bound),
+ * and the array keeps the last solve's contents (every run clears what must
+ * start at zero).  Work of two solvers on one device's array must not
+ * overlap in time: calls that overlap race. */
+ccpr_status ccpr_bind_static_workspace(ccpr_solver* s, void* hip_stream);
 
 /* Forward run of nsteps from zero fields, recording the gap monitor and the
  * gradient history (DFT gradient mode: its transform), then the objective

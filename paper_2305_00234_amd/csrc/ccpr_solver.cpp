@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -100,6 +101,7 @@ struct ccpr_solver {
     // workspace
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
+    int static_dev = -1;        // device whose static workspace is bound (-1: none)
     hipStream_t stream = nullptr;
     int maxpairs = 0, npairs_total = 0;
     int tz = 5;                 // nominal planes per z-chunk of the step kernel
@@ -749,7 +751,9 @@ ccpr_status upload_cold(ccpr_solver* s, int st)
                           hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(s->ws + s->lay.tiles, s->tiles_host.data(), s->tiles_host.size() * sizeof(int2),
                           hipMemcpyHostToDevice, s->stream));
-    if (s->ntiles_pml > 0 && s->ntiles_int > 0 && !s->stream2) {
+    // (no second stream on the static workspace: creating one is a resource
+    // allocation its callers cannot make)
+    if (s->ntiles_pml > 0 && s->ntiles_int > 0 && !s->stream2 && s->static_dev < 0) {
         HIPCHK(hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking));
         s->own_stream2 = true;
     }
@@ -1293,7 +1297,28 @@ ccpr_status set_design_common(ccpr_solver* s, const int lo[3], const int dims[3]
     return CCPR_OK;
 }
 
+// ---- static workspace (ccpr_bind_static_workspace)
+// The library's own device memory for callers that cannot allocate: a
+// file-scope array that each device holds from the first bind on it until
+// the process ends.  In host code its name is only a stand-in; the device
+// address comes from hipGetSymbolAddress, once per device with that device
+// current, and is the only handle host code uses.  One solver at a time is
+// bound to a device's array (a new bind unbinds the previous solver).
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices];
+ccpr_solver* g_static_owner[kMaxStaticDevices];
+
+// Forget the static workspace of s's device if s holds it (lock held).
+void release_static_locked(ccpr_solver* s)
+{
+    if (s->static_dev >= 0 && g_static_owner[s->static_dev] == s) g_static_owner[s->static_dev] = nullptr;
+    s->static_dev = -1;
+}
+
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[CCPR_STATIC_WORKSPACE_BYTES];
 
 // ======================================================================= ABI
 extern "C" {
@@ -1334,6 +1359,10 @@ void ccpr_destroy(ccpr_solver* s)
 {
     if (!s) return;
     if (s->ws) (void)hipStreamSynchronize(s->stream);
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        release_static_locked(s);
+    }
     for (hipEvent_t ev : s->tev) (void)hipEventDestroy(ev);
     if (s->stream2) (void)hipStreamSynchronize(s->stream2);
     if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
@@ -1500,8 +1529,57 @@ ccpr_status ccpr_bind_workspace(ccpr_solver* s, void* dev_ptr, uint64_t bytes, v
     if (L.fixed_end > bytes) return fail(s, CCPR_ENOMEM, "workspace of %llu bytes, need at least %llu",
                                          (unsigned long long)bytes, (unsigned long long)L.total);
     if (s->ws) (void)hipStreamSynchronize(s->stream);
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        release_static_locked(s);
+    }
     s->ws = (char*)dev_ptr;
     s->ws_bytes = bytes;
+    s->stream = (hipStream_t)hip_stream;
+    s->lay = L;
+    return refresh_fixed(s, true);
+}
+
+ccpr_status ccpr_bind_static_workspace(ccpr_solver* s, void* hip_stream)
+{
+    if (!s) return CCPR_EINVAL;
+    Layout L = make_layout(s, 0, 0);
+    if (L.fixed_end > CCPR_STATIC_WORKSPACE_BYTES)
+        return fail(s, CCPR_ENOMEM, "the fixed part of this solve's workspace is %llu bytes: above the %llu-byte "
+                                    "static workspace", (unsigned long long)L.fixed_end,
+                    (unsigned long long)CCPR_STATIC_WORKSPACE_BYTES);
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxStaticDevices) return fail(s, CCPR_ENOTSUP, "device %d: no static workspace", dev);
+    if (s->ws) (void)hipStreamSynchronize(s->stream);
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (!g_static_ptr[dev]) {
+            // once per device, with that device current
+            hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(s, CCPR_EDEVICE, "hipGetSymbolAddress(static workspace): %s", hipGetErrorString(e));
+            g_static_ptr[dev] = ptr;
+        }
+        ptr = g_static_ptr[dev];
+        ccpr_solver* prev = g_static_owner[dev];
+        if (prev && prev != s) {
+            // the previous solver loses the array: its calls now report that
+            // no workspace is bound
+            if (prev->ws) (void)hipStreamSynchronize(prev->stream);
+            prev->ws = nullptr;
+            prev->ws_bytes = 0;
+            prev->have_forward = prev->have_adjoint = false;
+            prev->static_dev = -1;
+            std::memset(prev->fixed_key, 0xff, sizeof prev->fixed_key);
+        }
+        release_static_locked(s);
+        g_static_owner[dev] = s;
+        s->static_dev = dev;
+    }
+    s->ws = (char*)ptr;
+    s->ws_bytes = CCPR_STATIC_WORKSPACE_BYTES;
     s->stream = (hipStream_t)hip_stream;
     s->lay = L;
     return refresh_fixed(s, true);

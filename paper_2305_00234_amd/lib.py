@@ -32,7 +32,8 @@ EXPORTS = [
     "ccpr_set_design_edges", "ccpr_workspace_size_max", "ccpr_set_resident_segments",
     "ccpr_get_resident_segments",
     "ccpr_set_source_dipole", "ccpr_set_source_planewave", "ccpr_set_objective",
-    "ccpr_set_checkpointing", "ccpr_set_gradient_mode", "ccpr_workspace_size", "ccpr_bind_workspace", "ccpr_forward",
+    "ccpr_set_checkpointing", "ccpr_set_gradient_mode", "ccpr_workspace_size", "ccpr_bind_workspace",
+    "ccpr_bind_static_workspace", "ccpr_forward",
     "ccpr_adjoint", "ccpr_gradient", "ccpr_gap_spectrum", "ccpr_reset", "ccpr_step", "ccpr_get_field",
     "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_grid_timing", "ccpr_get_info",
     "ccpr_set_tile_planes", "ccpr_set_tile_rows", "ccpr_set_watchdog", "ccpr_forward_serial",
@@ -93,6 +94,7 @@ def load():
         "ccpr_set_resident_segments": (_i, [_p, _i]),
         "ccpr_get_resident_segments": (_i, [_p, _ip]),
         "ccpr_bind_workspace": (_i, [_p, _p, C.c_uint64, _p]),
+        "ccpr_bind_static_workspace": (_i, [_p, _p]),
         "ccpr_forward": (_i, [_p, _i, _dp]),
         "ccpr_adjoint": (_i, [_p]),
         "ccpr_gradient": (_i, [_p, _p, _i]),
@@ -420,6 +422,15 @@ class Solver:
         self._chk(self._lib.ccpr_bind_workspace(self._h, C.c_void_p(ptr), nbytes, C.c_void_p(stream)),
                   "ccpr_bind_workspace")
         self._bound_stream = None
+
+    def bind_static_workspace(self, stream: int = 0):
+        """ccpr_bind_static_workspace: the library's static 64 MiB device array
+        of the current device as workspace (no allocation), with a raw HIP
+        stream handle (0: the null stream)."""
+        self._chk(self._lib.ccpr_bind_static_workspace(self._h, C.c_void_p(stream)),
+                  "ccpr_bind_static_workspace")
+        self._bound_stream = None
+        self._ws = None
 
     def bind_torch(self, nsteps: int, device=None, extra: int = 0, reserve: int = 4 << 30,
                    greedy: bool = True):
