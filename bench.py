@@ -6,15 +6,21 @@ DFT |E|^2 over a 4^3 gap, time-exact gradient), inputs resident in HBM.
 
 Prints one JSON line.  value = cell-updates of the forward and adjoint runs
 (cells x 2 x 6000 per solve) per second, in millions.  The roofline object is
-for the grid kernel (ccpr_step_kernel, the one that streams every cell):
-algorithmic bytes per launch (algorithmic_bytes) over its average launch
-duration, timed with HIP events on the library's streams around the grid
-launches inside the timed region (every 10th pass by default, --timing-every);
-"step" gives the same for whole leapfrog steps;
+for the grid pass (ccpr_step_kernel, the kernel that streams every cell; one
+or two concurrent launches): the byte model's bytes per pass (grid_model_bytes)
+over its average duration, timed with HIP events on the library's streams
+around the grid launches inside the timed region (every 10th pass by
+default, --timing-every); "step" gives the same for whole leapfrog steps
+with the model's bytes of a step (step_model_bytes).  The byte model counts
+what the method must move, not what this implementation's kernel split adds
+(the E drive hand-over between kernels, the x-layer re-reads).
 roofline.copy_GBs is the measured rate of a plain 1 GiB device copy (bytes
 read + written per second, the practical HBM ceiling) and frac_of_copy the
-grid kernel's share of it.  The CPU baseline is the FP64 oracle on a bounded
-sample of the same workload (a few forward + adjoint steps on the full grid).
+grid pass's share of it.  "serving" is the continuous-batching engine on a
+Poisson trace of solve requests (--serving-requests, 0 to skip) against the
+same solves one after another.  The CPU baseline is the FP64 oracle on a
+bounded sample of the same workload (a few forward + adjoint steps on the
+full grid).
 """
 from __future__ import annotations
 
@@ -46,22 +52,18 @@ def workload_by_name(name, solve_steps=None):
     return table[name](solve_steps)
 
 
-def algorithmic_bytes(w):
-    """Algorithmic HBM bytes of one launch of the grid kernel (ccpr_step_kernel,
-    one leapfrog step over all cells): 48 B per cell (E and H, three FP32
-    components each, read once and written once); 32 B per (cell, y or z CPML
-    layer) for the two psi memories of H (read old, write new) and of E (read,
-    write); 12 B per design voxel and per source-box cell for the stored E
-    drive.  The x CPML, the design pole currents, the gradient history and the
-    TF/SF faces are moved by the small pre / aux / post kernels of the step and
-    are counted in step_bytes, not here."""
+def grid_model_bytes(w):
+    """Byte model of one grid pass (one leapfrog step of every cell, with
+    perfect halo reuse): 48 B per cell (E and H, three FP32 components each,
+    read once and written once) and 32 B per (cell, y or z CPML layer) for the
+    two psi memories of H (read old, write new) and of E (read, write).  The
+    x CPML, the design pole currents and the gradient history are moved by the
+    other kernels of the step and are counted in step_model_bytes."""
     nx, ny, nz = w.shape
     n = nx * ny * nz
-    nd = design_box_cells(w)
     p = w.npml
     yz_layer_cells = 2 * p * nx * nz + 2 * p * nx * ny if p else 0
-    src_cells = 1 if w.source == "dipole" else 0
-    return 48 * n + 32 * yz_layer_cells + 12 * (nd + src_cells)
+    return 48 * n + 32 * yz_layer_cells
 
 
 def design_box_cells(w):
@@ -73,31 +75,28 @@ def design_box_cells(w):
     return int(np.prod(d))
 
 
-def step_bytes(w):
-    """Algorithmic HBM bytes of a whole leapfrog step (all kernels), averaged
-    over a forward and an adjoint step: the grid kernel's bytes; per design
-    voxel 16 B per pole pair and component (J read + write), 4 B density, 12 B
-    E^n + 12 B drive read + 12 B E^{n+1} write; 32 B per (cell, x CPML layer)
-    (psi of H and of E, read + write) plus 16 B of E and H for each; the
-    gradient history: 12 B record (forward), 12 B read + 16 B FP64 accumulator
-    read/write (adjoint); DFT-mode gradient instead: 24 B complex transform
-    of T read + write (forward), 24 B projection of the adjoint E read + write
-    over the fit window (about half the adjoint steps).  Per-edge designs:
-    the design box of N + 1 cells, three densities and three accumulators per
-    cell."""
+def step_model_bytes(w):
+    """Byte model of a whole leapfrog step, averaged over a forward and an
+    adjoint step (what the method must move, with perfect reuse inside the
+    step): 48 B per cell; 32 B per (cell, CPML layer) on each of the three
+    axes (psi of H and of E, read + write); per design voxel 16 B per pole pair
+    and component (complex J read + write, FP32) and 4 B of density (12 B per
+    cell for a per-edge design); the gradient record: time-exact 24 B per
+    design voxel written in the forward step and 24 + 8 B read (history and
+    gradient accumulator) in the adjoint step, 28 B on average; DFT-mode
+    gradient 48 B per design voxel (the running transforms, read + write).
+    The history model stores E and the pole term per component; this
+    implementation stores one FP32 factor per component (12 B), below the
+    model."""
     nx, ny, nz = w.shape
     nd = design_box_cells(w)
     per_cell = 3 if w.rho_edges is not None else 1
     pairs = sum(w.mat1[a].npairs + w.mat2[a].npairs for a in range(3))
     p = w.npml
-    x_layer_cells = 2 * p * ny * nz if p else 0
-    design = (16 * pairs + 4 * per_cell + 36) * nd
-    xpml = (32 + 16) * x_layer_cells
-    if w.gradient == "dft":
-        record = (48 * nd + 48 * nd * 0.5) / 2.0
-    else:
-        record = (12 * nd + (12 + 16 * per_cell) * nd) / 2.0
-    return algorithmic_bytes(w) + design + xpml + record
+    layer_cells = 2 * p * (ny * nz + nx * nz + nx * ny) if p else 0
+    design = (16 * pairs + 4 * per_cell) * nd
+    record = 48 * nd if w.gradient == "dft" else 28 * nd
+    return 48 * nx * ny * nz + 32 * layer_cells + design + record
 
 
 def traffic_from_profile(kernel_src_hash, workload):
@@ -154,17 +153,18 @@ def cpu_baseline(w, sample_steps):
                       f"objective and gradient ({dt:.1f} s wall)"}
 
 
-def serving(args):
+def serving(args, n_requests=None, emit=True):
     """Serving trace (Poisson arrivals, uneven grids and pole counts): the
-    engine's continuous batching against the same solves run one after
-    another with the plain path; same results bitwise, solves/s and p50/p99
-    latency (arrival to result) for both."""
+    engine's continuous batching (batched launches per padded x width)
+    against the same engine with every solve on its own streams and against
+    the same solves run one after another with the plain path; same results
+    bitwise, solves/s and p50/p99 latency (arrival to result) for each."""
     import torch
     from paper_2305_00234_amd import inputs as I
     from paper_2305_00234_amd.lib import JOB_DONE, JOB_FAILED, Engine
     from paper_2305_00234_amd.solver import configure
 
-    trace = I.serving_trace(n_requests=args.serving, rate=args.rate, seed=3)
+    trace = I.serving_trace(n_requests=n_requests or args.serving, rate=args.rate, seed=3)
     arrivals = np.array([r.arrival for r in trace]) - trace[0].arrival
 
     def progress(msg):
@@ -194,35 +194,44 @@ def serving(args):
         seq_done.append(t)
     seq_lat = np.array(seq_done) - arrivals
 
-    # continuous batching: submit at the arrival times
-    solvers = [configure(r.workload) for r in trace]
-    eng = Engine(args.arena_gb << 30, max_active=args.max_active, chunk_steps=args.chunk)
-    tickets = []
-    t0 = time.perf_counter()
-    k = 0
-    done_t = {}
-    while len(done_t) < len(trace):
-        now = time.perf_counter() - t0
-        while k < len(trace) and arrivals[k] <= now:
-            tickets.append(eng.submit(solvers[k], trace[k].workload.steps))
-            k += 1
+    def engine_run(batching):
+        # continuous batching: submit at the arrival times
+        solvers = [configure(r.workload) for r in trace]
+        eng = Engine(args.arena_gb << 30, max_active=args.max_active, chunk_steps=args.chunk,
+                     batching=batching)
+        tickets = []
+        t0 = time.perf_counter()
+        k = 0
+        done_t = {}
+        while len(done_t) < len(trace):
+            now = time.perf_counter() - t0
+            while k < len(trace) and arrivals[k] <= now:
+                tickets.append(eng.submit(solvers[k], trace[k].workload.steps))
+                k += 1
+            for q, tk in enumerate(tickets):
+                if q not in done_t:
+                    st = eng.poll(tk)
+                    if st == JOB_FAILED:
+                        raise RuntimeError(f"served solve {q} failed")
+                    if st == JOB_DONE:
+                        done_t[q] = time.perf_counter() - t0
+            time.sleep(0.0005)
+        wall = max(done_t.values())
+        lat = np.array([done_t[q] for q in range(len(trace))]) - arrivals
+        same = True
         for q, tk in enumerate(tickets):
-            if q not in done_t:
-                st = eng.poll(tk)
-                if st == JOB_FAILED:
-                    raise RuntimeError(f"served solve {q} failed")
-                if st == JOB_DONE:
-                    done_t[q] = time.perf_counter() - t0
-        time.sleep(0.0005)
-    wall = max(done_t.values())
-    bat_lat = np.array([done_t[q] for q in range(len(trace))]) - arrivals
-    same = True
-    for q, tk in enumerate(tickets):
-        F, _, _ = eng.result(tk)
-        same &= F == seq_F[q]
-        eng.release(tk)
-    eng.close()
-    progress(f"batched: wall {wall:.2f} s, results identical: {same}")
+            F, _, _ = eng.result(tk)
+            same &= F == seq_F[q]
+            eng.release(tk)
+        eng.close()
+        for s in solvers:
+            s.close()
+        torch.cuda.empty_cache()
+        progress(f"engine (batching {batching}): wall {wall:.2f} s, results identical: {same}")
+        return wall, lat, same
+
+    wall, bat_lat, same = engine_run(True)
+    wall_s, str_lat, same_s = engine_run(False)
     seq_wall = seq_done[-1]
     out = {
         "metric": "served solves/s (continuous batching) vs sequential plain solves; p50/p99 latency",
@@ -234,7 +243,10 @@ def serving(args):
                        "p99": round(float(np.percentile(bat_lat, 99)) * 1e3, 1)},
         "sequential_latency_ms": {"p50": round(float(np.percentile(seq_lat, 50)) * 1e3, 1),
                                   "p99": round(float(np.percentile(seq_lat, 99)) * 1e3, 1)},
-        "results_identical": bool(same),
+        "per_solve_streams_solves_per_s": round(len(trace) / wall_s, 3),
+        "per_solve_streams_latency_ms": {"p50": round(float(np.percentile(str_lat, 50)) * 1e3, 1),
+                                         "p99": round(float(np.percentile(str_lat, 99)) * 1e3, 1)},
+        "results_identical": bool(same and same_s),
         "n_gpus": 1, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serving_trace", "requests": len(trace), "rate_per_s": args.rate,
                    "sides": "U{64..192}", "pole_pairs": "U{1..3}", "steps": "U{1500..4000}",
@@ -242,7 +254,9 @@ def serving(args):
                    "arena_GiB": args.arena_gb,
                    "cell_updates": int(sum(2 * r.workload.cells * r.workload.steps for r in trace))},
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def copy_rate_gbs(nbytes=1 << 30, reps=10):
@@ -288,7 +302,9 @@ def main():
     ap.add_argument("--timing-every", type=int, default=10,
                     help="time every k-th grid pass with HIP events (fewer events in the stream)")
     ap.add_argument("--serving", type=int, default=0,
-                    help="run the serving trace with this many requests instead")
+                    help="run only the serving trace, with this many requests")
+    ap.add_argument("--serving-requests", type=int, default=24,
+                    help="requests of the serving record in the default run (0: skip it)")
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--chunk", type=int, default=32)
@@ -359,9 +375,9 @@ def main():
     value = updates / (total / args.steps) / 1e6
     avg_step_s = step_ms / 1e3 / max(launches, 1)
     avg_launch_s = grid_ms / 1e3 / max(grid_launches, 1)
-    alg = algorithmic_bytes(w)
+    alg = grid_model_bytes(w)
     achieved = alg / avg_launch_s / 1e9
-    sb = step_bytes(w)
+    sb = step_model_bytes(w)
     traffic = traffic_from_profile(kernel_hash(), w.name)
     copy_gbs = copy_rate_gbs()
 
@@ -391,14 +407,25 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "ccpr_step_kernel",
-                     "alg_bytes_per_launch": int(alg),
+                     "grid_model_bytes": int(alg),
                      "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": grid_launches,
                      "copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
                      "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None},
-        "step": {"avg_step_us": round(avg_step_s * 1e6, 2), "alg_bytes_per_step": int(sb),
+        "step": {"avg_step_us": round(avg_step_s * 1e6, 2), "step_model_bytes": int(sb),
                  "achieved_GBs": round(sb / avg_step_s / 1e9, 1),
                  "frac": round(sb / avg_step_s / 1e9 / HBM_PEAK_GBS, 4), "steps": launches},
     }
+    if args.serving_requests > 0:
+        s.close()
+        del s, grad
+        torch.cuda.empty_cache()
+        progress(f"serving trace ({args.serving_requests} requests)")
+        sv = serving(args, n_requests=args.serving_requests, emit=False)
+        out["serving"] = {k: sv[k] for k in ("value", "unit", "sequential_solves_per_s", "speedup",
+                                             "per_solve_streams_solves_per_s", "latency_ms",
+                                             "sequential_latency_ms", "per_solve_streams_latency_ms",
+                                             "results_identical")}
+        out["serving"]["config"] = sv["config"]
     if not args.no_cpu_baseline:
         progress("cpu baseline (FP64 oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)

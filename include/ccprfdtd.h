@@ -366,12 +366,18 @@ ccpr_status ccpr_set_tile_rows(ccpr_solver* s, int rows);
  * gradient: the path of ccpr_forward + ccpr_adjoint + ccpr_gradient) for many
  * solvers of different grids and pole counts.  The engine owns one device
  * arena and a worker thread: it admits submitted solves in arrival order
- * while the arena (first fit) and the slot limit allow, binds each to its own
- * slice of the arena and its own HIP stream (default priority), and keeps all
- * admitted solves fed with chunks of leapfrog steps so their kernels overlap
- * on the device.  A solve's objective and gradient are the same as on its own
- * (the same kernels in the same order).  When a solve finishes, its results
- * are copied to host memory and its slice and stream are released. */
+ * while the arena (first fit) and the slot limit allow and binds each to its
+ * own slice of the arena.  Solves with one density per voxel and the
+ * time-exact gradient are batched: those of one padded x width (nx rounded up
+ * to 64) share a HIP stream, and each batched grid, aux and post launch
+ * advances up to 8 of them by one leapfrog step (a table in the launch maps
+ * workgroups to solves); their other work (checkpoints, objective, results)
+ * is enqueued per solve on the same stream in order.  Other solves get HIP
+ * streams of their own and are fed with chunks of leapfrog steps so their
+ * kernels overlap on the device.  A solve's objective and gradient are the
+ * same bit for bit as on its own (the same arithmetic in the same order).
+ * When a solve finishes, its results are copied to host memory and its slice
+ * (and streams) are released. */
 
 typedef struct ccpr_engine ccpr_engine;
 
@@ -460,6 +466,10 @@ ccpr_status ccpr_engine_result(ccpr_engine* e, uint64_t ticket, double* objectiv
 
 /* Forget a DONE or FAILED job. */
 ccpr_status ccpr_engine_release(ccpr_engine* e, uint64_t ticket);
+
+/* Batch the solves admitted from now on (on = 1, the default) or give every
+ * solve its own streams (on = 0; for comparisons).  CCPR_EINVAL for NULL. */
+ccpr_status ccpr_engine_set_batching(ccpr_engine* e, int on);
 
 const char* ccpr_engine_last_error(const ccpr_engine* e);
 

@@ -2,10 +2,15 @@
 //
 // The caller hands over one device arena (allocated by torch in the binding)
 // and submits configured solvers.  A worker thread admits queued solves in
-// arrival order while the arena (first fit) and the slot limit allow, binds
-// each to its own slice of the arena and its own HIP stream, and then keeps
-// every admitted solve fed with chunks of leapfrog steps, round robin, so the
-// small kernels of different solves overlap on the device.  A finished solve's
+// arrival order while the arena (first fit) and the slot limit allow and
+// binds each to its own slice of the arena.  Solves that the batched launches
+// can advance (ccpr_pipe_batch_class) are grouped by padded x width: the
+// solves of one width share a stream and advance together, one leapfrog step
+// each per batched grid / aux / post launch (up to CCPR_PIPE_BATCH_MAX solves
+// per launch), so a step of many small solves costs three launches instead of
+// three per solve.  Other solves get streams of their own and are fed with
+// chunks of leapfrog steps, round robin, so their kernels overlap on the
+// device.  A finished solve's
 // objective and gradient are copied to its slot's pinned host buffers, its
 // slice and streams are released, and the next queued solve is admitted.
 // Pinned buffers belong to the slots and are allocated once at creation
@@ -44,7 +49,8 @@ struct Job {
     uint64_t bytes = 0;
     int state = CCPR_JOB_QUEUED;
     uint64_t off = 0;             // arena slice
-    hipStream_t stream = nullptr, stream2 = nullptr;  // from the engine's pool
+    hipStream_t stream = nullptr, stream2 = nullptr;  // from the engine's pool (unbatched solves)
+    int cls = -1;                 // batched solves: their class (padded x width)
     std::deque<hipEvent_t> inflight;  // one event per enqueued chunk
     bool enqueued_all = false;
     hipEvent_t done_ev = nullptr;
@@ -60,6 +66,14 @@ struct Job {
 
 struct Block {
     uint64_t off, len;
+};
+
+// Batched solves of one padded x width: one stream (from the pool) and the
+// chunks of batched steps in flight on it.
+struct ClassQ {
+    hipStream_t stream = nullptr;
+    std::vector<Job*> jobs;           // running, in admission order
+    std::deque<hipEvent_t> inflight;  // one event per enqueued chunk
 };
 
 struct Slot {
@@ -86,6 +100,8 @@ struct ccpr_engine {
     uint64_t next_ticket = 1;
     std::vector<hipStream_t> streams;  // pool: two per slot, created once
     std::vector<Slot> slots;           // max_active result-buffer slots
+    std::map<int, ClassQ> classes;     // batched solves by padded x width
+    bool batching = true;              // group batchable solves (ccpr_engine_set_batching)
     std::vector<double*> retired;      // outgrown pinned buffers (freed at destroy)
     double t0 = 0;                     // creation time (job times are relative to it)
     std::thread worker;
@@ -130,8 +146,24 @@ void arena_free(ccpr_engine* e, uint64_t off, uint64_t bytes)
     }
 }
 
+// A class with no solves left gives its stream back once its chunks are done.
+void retire_class_if_idle(ccpr_engine* e, int cls)
+{
+    auto it = e->classes.find(cls);
+    if (it == e->classes.end() || !it->second.jobs.empty()) return;
+    ClassQ& q = it->second;
+    (void)hipStreamSynchronize(q.stream);
+    for (hipEvent_t ev : q.inflight) (void)hipEventDestroy(ev);
+    e->streams.push_back(q.stream);
+    e->classes.erase(it);
+}
+
 void release_device(ccpr_engine* e, Job* j)
 {
+    if (j->cls >= 0) {
+        ClassQ& q = e->classes[j->cls];
+        q.jobs.erase(std::remove(q.jobs.begin(), q.jobs.end(), j), q.jobs.end());
+    }
     for (hipEvent_t ev : j->inflight) (void)hipEventDestroy(ev);
     j->inflight.clear();
     if (j->done_ev) (void)hipEventDestroy(j->done_ev);
@@ -144,14 +176,16 @@ void release_device(ccpr_engine* e, Job* j)
     j->scal_host = j->grad_host = nullptr;
     ccpr_pipe_unbind(j->s);
     arena_free(e, j->off, j->bytes);
+    j->cls = -1;  // (the worker retires classes left without solves)
 }
 
 void fail_job(ccpr_engine* e, Job* j, const std::string& why)
 {
     // the solve's work may still run on either of its streams (a split grid
-    // pass leaves its second launch on the other one)
+    // pass leaves its second launch on the other one), or on its class's
     if (j->stream) (void)hipStreamSynchronize(j->stream);
     if (j->stream2) (void)hipStreamSynchronize(j->stream2);
+    if (j->cls >= 0) (void)hipStreamSynchronize(e->classes[j->cls].stream);
     j->err = why;
     release_device(e, j);
     j->t_done = now_s();
@@ -167,13 +201,25 @@ bool admit(ccpr_engine* e, Job* j)
     if (!arena_alloc(e, j->bytes, &off)) return false;
     j->off = off;
     std::string why;
-    if (e->streams.size() < 2) {
+    hipStream_t bind_stream = nullptr;
+    const int cls = e->batching ? ccpr_pipe_batch_class(j->s) : -1;
+    if (cls > 0 && (e->classes.count(cls) || !e->streams.empty())) {
+        ClassQ& q = e->classes[cls];
+        if (!q.stream) {
+            q.stream = e->streams.back();
+            e->streams.pop_back();
+        }
+        q.jobs.push_back(j);
+        j->cls = cls;
+        bind_stream = q.stream;
+    } else if (e->streams.size() < 2) {
         why = "no free stream";
     } else {
         j->stream = e->streams.back();
         e->streams.pop_back();
         j->stream2 = e->streams.back();
         e->streams.pop_back();
+        bind_stream = j->stream;
     }
     j->nd = ccpr_pipe_design_voxels(j->s);
     if (why.empty()) {
@@ -205,10 +251,12 @@ bool admit(ccpr_engine* e, Job* j)
             }
         }
     }
-    if (why.empty() && ccpr_pipe_set_stream2(j->s, j->stream2) != CCPR_OK)
+    if (why.empty() && j->cls < 0 && ccpr_pipe_set_stream2(j->s, j->stream2) != CCPR_OK)
         why = std::string("stream: ") + ccpr_last_error(j->s);
-    if (why.empty() && ccpr_bind_workspace(j->s, e->arena + off, j->bytes, j->stream) != CCPR_OK)
+    if (why.empty() && ccpr_bind_workspace(j->s, e->arena + off, j->bytes, bind_stream) != CCPR_OK)
         why = std::string("bind: ") + ccpr_last_error(j->s);
+    if (why.empty() && ccpr_pipe_set_batched(j->s, j->cls >= 0) != CCPR_OK)
+        why = std::string("batching: ") + ccpr_last_error(j->s);
     if (why.empty() && ccpr_pipe_begin(j->s, j->nsteps) != CCPR_OK)
         why = std::string("set-up: ") + ccpr_last_error(j->s);
     j->t_admit = now_s();
@@ -223,6 +271,93 @@ bool admit(ccpr_engine* e, Job* j)
 // Feed one running job: retire finished chunks, enqueue up to two chunks in
 // flight, and after the last chunk the result copies.  Returns true if it did
 // any work.
+hipStream_t job_stream(ccpr_engine* e, Job* j) { return j->cls >= 0 ? e->classes[j->cls].stream : j->stream; }
+
+// After the last enqueued work of a solve: its result copies and completion
+// event.  Returns false (and fails the job) on error.
+bool enqueue_results(ccpr_engine* e, Job* j)
+{
+    if (ccpr_pipe_results(j->s, j->scal_host, j->grad_host) != CCPR_OK ||
+        hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(j->done_ev, job_stream(e, j)) != hipSuccess) {
+        fail_job(e, j, std::string("results: ") + ccpr_last_error(j->s));
+        return false;
+    }
+    j->enqueued_all = true;
+    return true;
+}
+
+// A solve whose completion event fired: check and copy its results.
+void finish_job(ccpr_engine* e, Job* j)
+{
+    double F = 0;
+    if (ccpr_pipe_check(j->s, j->scal_host, &F) != CCPR_OK) {
+        fail_job(e, j, std::string("check: ") + ccpr_last_error(j->s));
+        return;
+    }
+    j->F = F;
+    j->grad.assign(j->grad_host, j->grad_host + j->nd);
+    release_device(e, j);
+    j->t_done = now_s();
+    j->state = CCPR_JOB_DONE;
+}
+
+// Feed the batched solves of one class: retire finished chunks and solves,
+// and keep up to two chunks of batched steps in flight.  Each round of a
+// chunk advances every solve of the class by one leapfrog step (after the
+// other work that precedes that step) and launches the recorded steps
+// together.  Returns true if it did any work.
+bool feed_class(ccpr_engine* e, ClassQ& q)
+{
+    bool worked = false;
+    while (!q.inflight.empty() && hipEventQuery(q.inflight.front()) == hipSuccess) {
+        (void)hipEventDestroy(q.inflight.front());
+        q.inflight.pop_front();
+        worked = true;
+    }
+    std::vector<Job*> done;
+    for (Job* j : q.jobs)
+        if (j->enqueued_all && hipEventQuery(j->done_ev) == hipSuccess) done.push_back(j);
+    for (Job* j : done) {
+        finish_job(e, j);
+        worked = true;
+    }
+    if (q.inflight.size() >= 2) return worked;
+    bool any = false;
+    for (int r = 0; r < e->chunk; ++r) {
+        std::vector<ccpr_solver*> rec;
+        std::vector<Job*> failed;
+        const std::vector<Job*> jobs = q.jobs;  // (failures remove jobs from q.jobs)
+        for (Job* j : jobs) {
+            if (j->enqueued_all || j->state != CCPR_JOB_RUNNING) continue;
+            const int n = ccpr_pipe_advance(j->s, 1);
+            if (n < 0) failed.push_back(j);
+            else if (n == 0) enqueue_results(e, j);
+            else rec.push_back(j->s);
+        }
+        for (Job* j : failed) fail_job(e, j, std::string("step: ") + ccpr_last_error(j->s));
+        if (rec.empty()) break;
+        any = true;
+        for (size_t b = 0; b < rec.size(); b += CCPR_PIPE_BATCH_MAX) {
+            const int k = (int)std::min<size_t>(CCPR_PIPE_BATCH_MAX, rec.size() - b);
+            if (ccpr_pipe_flush(rec.data() + b, k, q.stream) != CCPR_OK) {
+                for (Job* j : std::vector<Job*>(q.jobs))
+                    for (int c = 0; c < k; ++c)
+                        if (j->s == rec[b + c]) fail_job(e, j, std::string("batched step: ") + ccpr_last_error(j->s));
+            }
+        }
+    }
+    if (any) {
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+            if (hipEventRecord(ev, q.stream) == hipSuccess) q.inflight.push_back(ev);
+            else (void)hipEventDestroy(ev);
+        }
+        worked = true;
+    }
+    return worked;
+}
+
 bool feed(ccpr_engine* e, Job* j)
 {
     bool worked = false;
@@ -238,13 +373,7 @@ bool feed(ccpr_engine* e, Job* j)
             return true;
         }
         if (n == 0) {
-            if (ccpr_pipe_results(j->s, j->scal_host, j->grad_host) != CCPR_OK ||
-                hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming) != hipSuccess ||
-                hipEventRecord(j->done_ev, j->stream) != hipSuccess) {
-                fail_job(e, j, std::string("results: ") + ccpr_last_error(j->s));
-                return true;
-            }
-            j->enqueued_all = true;
+            enqueue_results(e, j);
             worked = true;
             break;
         }
@@ -257,17 +386,8 @@ bool feed(ccpr_engine* e, Job* j)
         j->inflight.push_back(ev);
         worked = true;
     }
-    if (j->enqueued_all && hipEventQuery(j->done_ev) == hipSuccess) {
-        double F = 0;
-        if (ccpr_pipe_check(j->s, j->scal_host, &F) != CCPR_OK) {
-            fail_job(e, j, std::string("check: ") + ccpr_last_error(j->s));
-            return true;
-        }
-        j->F = F;
-        j->grad.assign(j->grad_host, j->grad_host + j->nd);
-        release_device(e, j);
-        j->t_done = now_s();
-        j->state = CCPR_JOB_DONE;
+    if (j->state == CCPR_JOB_RUNNING && j->enqueued_all && hipEventQuery(j->done_ev) == hipSuccess) {
+        finish_job(e, j);
         worked = true;
     }
     return worked;
@@ -287,9 +407,13 @@ void worker_loop(ccpr_engine* e)
             else e->cv.notify_all();
         }
         bool worked = false;
+        std::vector<int> cls;
+        for (auto& kv : e->classes) cls.push_back(kv.first);
+        for (int c : cls) worked |= feed_class(e, e->classes[c]);
+        for (int c : cls) retire_class_if_idle(e, c);
         for (size_t q = 0; q < e->active.size();) {
             Job* j = e->active[q];
-            worked |= feed(e, j);
+            if (j->cls < 0 && j->state == CCPR_JOB_RUNNING) worked |= feed(e, j);
             if (j->state == CCPR_JOB_DONE || j->state == CCPR_JOB_FAILED) {
                 e->active.erase(e->active.begin() + q);
                 e->cv.notify_all();
@@ -434,6 +558,14 @@ ccpr_status ccpr_engine_release(ccpr_engine* e, uint64_t ticket)
     if (it->second->state != CCPR_JOB_DONE && it->second->state != CCPR_JOB_FAILED) return CCPR_ESTATE;
     delete it->second;
     e->jobs.erase(it);
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_engine_set_batching(ccpr_engine* e, int on)
+{
+    if (!e) return CCPR_EINVAL;
+    std::lock_guard<std::mutex> lk(e->mu);
+    e->batching = on != 0;
     return CCPR_OK;
 }
 

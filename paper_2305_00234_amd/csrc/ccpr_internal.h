@@ -177,6 +177,27 @@ struct StepArgs {
 #define CCPR_MODE_DFT_T 8       // forward, DFT mode: T_hat += T exp(-j phase)
 #define CCPR_MODE_DFT_P 16      // adjoint, DFT mode: P += E^{n+1} exp(-j phase)
 
+// ---- batched steps of several solves (the serving engine): one grid, one
+// aux and one post launch advance up to CCPR_BATCH_MAX solves of the same
+// padded x width by one leapfrog step each.  A solve's recorded step:
+#define CCPR_BATCH_MAX 8
+struct BatchStep {
+    StepArgs a;                 // its StepArgs (tiles = all its tiles, nblk = their count)
+    int maxpairs;               // pole pairs of its widest axis
+    long long nd;               // design-box cells (aux kernel)
+    int fused;                  // 1: post of this step + pre of the next (fused post kernel)
+    long long nxs, nmisc, ntfh; // x-layer cells, misc cells, next step's TF/SF H words
+};
+// Kernel argument of the batched launches: block b of a launch belongs to
+// solve s with start[s] <= b < start[s + 1].
+struct BatchArgs {
+    StepArgs a[CCPR_BATCH_MAX];
+    int n;
+    int gstart[CCPR_BATCH_MAX + 1], astart[CCPR_BATCH_MAX + 1], pstart[CCPR_BATCH_MAX + 1];
+    int fused[CCPR_BATCH_MAX], rpb[CCPR_BATCH_MAX];
+    long long nbx[CCPR_BATCH_MAX], nmisc[CCPR_BATCH_MAX], ntfh[CCPR_BATCH_MAX], nxs[CCPR_BATCH_MAX];
+};
+
 // floats of the psi memory of derivative axis a (both components)
 __host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, int nxp, int npml)
 {
@@ -199,6 +220,9 @@ int ccpr_launch_post(const StepArgs& a, long long nxs, long long nmisc, void* st
 // step n and the pre work of step n+1 (ntfh TF/SF H words) in one launch
 // (2 npml <= 256)
 int ccpr_launch_post_fused(const StepArgs& a, long long nmisc, long long ntfh, void* stream);
+// the recorded steps st[0..k) (1 <= k <= CCPR_BATCH_MAX, same nxp, 2 rows per
+// thread, 2 npml <= 256) as one batched grid, aux and post launch each
+int ccpr_launch_batch(const BatchStep* st, int k, void* stream);
 int ccpr_launch_fill(float* p, long long n, float v, void* stream);
 int ccpr_launch_fill_d(double* p, long long n, double v, void* stream);
 int ccpr_launch_copy(float* dst, const float* src, long long n, void* stream);

@@ -39,6 +39,9 @@
 //    tiles: neighbouring y-strips share their halo rows in the same L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+
 #include "ccpr_internal.h"
 
 namespace {
@@ -202,23 +205,16 @@ __device__ __forceinline__ float cpml(float d, float4 cf, float p, float* pout, 
 // PML = true fetches the tile's CPML memories together with the fields at the
 // top of every plane.  The two variants run concurrently on their own tile
 // lists.  NT: nontemporal stores of the new fields (large states).
+// Tile L of a.tiles (the body of ccpr_step_kernel and of the batched grid
+// kernel); xe, xh: the workgroup's LDS words at the wave seams.
 template <int R, bool PML, bool NT>
-__global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const StepArgs a)
+__device__ __forceinline__ void grid_tile(const StepArgs& a, const int L, float (*xe)[R + 1][16],
+                                          float (*xh)[R][16])
 {
-    __shared__ float xe[2][R + 1][16];
-    __shared__ float xh[2][R][16];
-    if (*a.halt) return;  // the divergence watchdog stopped the run
     const StepCold& c = *a.cold;
-
-    // XCD-aware tile order: hardware hands workgroups to the 8 XCDs round
-    // robin; give each XCD a contiguous range of the tile list (neighbouring
-    // y-strips share halo rows in that XCD's L2).  Logical z-chunk zl covers
-    // planes zr[zl] = [k0, k1): the host sizes chunks to equal work (CPML
-    // planes cost more) and spreads them over the XCDs.
-    const int b = blockIdx.x;
-    const int per = a.nblk >> 3, rem = a.nblk & 7;
-    const int xcd = b & 7, q = b >> 3;
-    const int L = xcd * per + (xcd < rem ? xcd : rem) + q;
+    // Logical z-chunk zl covers planes zr[zl] = [k0, k1): the host sizes
+    // chunks to equal work (CPML planes cost more) and spreads them over the
+    // XCDs.
     const int2 tile = a.tiles[L];  // (y-strip, logical z-chunk)
     const int ys = tile.x;
     const int2 kr = a.zr[tile.y];
@@ -466,6 +462,21 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
     }
 }
 
+template <int R, bool PML, bool NT>
+__global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const StepArgs a)
+{
+    __shared__ float xe[2][R + 1][16];
+    __shared__ float xh[2][R][16];
+    if (*a.halt) return;  // the divergence watchdog stopped the run
+    // XCD-aware tile order: hardware hands workgroups to the 8 XCDs round
+    // robin; give each XCD a contiguous range of the tile list (neighbouring
+    // y-strips share halo rows in that XCD's L2).
+    const int b = blockIdx.x;
+    const int per = a.nblk >> 3, rem = a.nblk & 7;
+    const int xcd = b & 7, q = b >> 3;
+    grid_tile<R, PML, NT>(a, xcd * per + (xcd < rem ? xcd : rem) + q, xe, xh);
+}
+
 // Finish the design voxels the fused step left to it, one thread per voxel:
 // CCPR pole-pair update of the three E edges from E^n and the stored drive
 // (minus a source current if the voxel is also a source cell), the gradient
@@ -494,14 +505,14 @@ __device__ __forceinline__ long long edge_index(const EdgeMap& m, int xi, int yi
     return m.eoff[C] + ((long long)zi * b[1] + yi) * b[0] + xi;
 }
 
+// Design-box cell t (x fastest): the body of ccpr_aux_kernel and of the
+// batched aux kernel.
 template <int PMAX, bool NT, bool DFT, bool EDGE>
-__global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
+__device__ __forceinline__ void aux_cell(const StepArgs& a, const unsigned t)
 {
-    if (*a.halt) return;  // the divergence watchdog stopped the run
     const StepCold& c = *a.cold;
     const unsigned cs = a.cstride;
     const int n = a.n;
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (unsigned)c.nd) return;
     const long long v = t;
     const unsigned dx = c.ddim[0], dy = c.ddim[1];
@@ -625,6 +636,13 @@ __global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
     }
 }
 
+template <int PMAX, bool NT, bool DFT, bool EDGE>
+__global__ __launch_bounds__(256) void ccpr_aux_kernel(const StepArgs a)
+{
+    if (*a.halt) return;  // the divergence watchdog stopped the run
+    aux_cell<PMAX, NT, DFT, EDGE>(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Cells outside the design box: source and gap cells (e in [0, nextra)),
 // then the TF/SF E face words.  Runs in the post kernel's launch.
 __device__ __forceinline__ void aux_misc(const StepArgs& a, long long e)
@@ -730,11 +748,9 @@ __global__ __launch_bounds__(256) void ccpr_pre_kernel(const StepArgs a, long lo
 // nmisc threads).  With d the backward x-difference of H:
 //   Ey -= S((1/kappa - 1) d(Hz) + psi'),  Ez += S((1/kappa - 1) d(Hy) + psi').
 // Tangential E on the walls stays zero.
-__global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long long nxs, long long nmisc)
+__device__ __forceinline__ void post_cell(const StepArgs& a, const long long t, long long nxs, long long nmisc)
 {
-    if (*a.halt) return;
     const StepCold& c = *a.cold;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nxs) {
         if (t - nxs < nmisc) aux_misc(a, t - nxs);
         return;
@@ -761,6 +777,12 @@ __global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long l
     if (j != 0) stf(a.Eo, o + 2 * cs, ldf(a.Eo, o + 2 * cs) + a.S * fmaf(cf.z - 1.f, dHy, p1));
 }
 
+__global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long long nxs, long long nmisc)
+{
+    if (*a.halt) return;
+    post_cell(a, (long long)blockIdx.x * blockDim.x + threadIdx.x, nxs, nmisc);
+}
+
 // After step n when step n+1 follows at once: the work of ccpr_post_kernel
 // for step n and of ccpr_pre_kernel for step n+1 in one launch.  Blocks
 // [0, nbx) hold whole x-layer rows (rpb rows of 2 npml cells each): first the
@@ -774,16 +796,16 @@ __global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long l
 // n+1 (cells disjoint from the x layers and from each other).  NT: the x-layer
 // words are written with nontemporal stores (large states; measured 553 ->
 // 549 us per step at 320^3).
+// Block blk (256 threads) of ccpr_post_fused_kernel and of the batched post
+// kernel; se: the block's LDS exchange.
 template <bool NT>
-__global__ __launch_bounds__(256) void ccpr_post_fused_kernel(const StepArgs a, int rpb, long long nbx,
-                                                              long long nmisc, long long ntfh)
+__device__ __forceinline__ void post_fused_block(const StepArgs& a, int rpb, long long nbx, long long nmisc,
+                                                 long long ntfh, long long blk, float (*se)[256])
 {
-    __shared__ float se[2][256];
-    if (*a.halt) return;
     const StepCold& c = *a.cold;
     const int tid = threadIdx.x;
-    if ((long long)blockIdx.x >= nbx) {
-        const long long t = ((long long)blockIdx.x - nbx) * blockDim.x + tid;
+    if (blk >= nbx) {
+        const long long t = (blk - nbx) * blockDim.x + tid;
         if (t < nmisc) {
             aux_misc(a, t);
             return;
@@ -798,7 +820,7 @@ __global__ __launch_bounds__(256) void ccpr_post_fused_kernel(const StepArgs a, 
     const unsigned cs = a.cstride;
     const int np2 = 2 * a.npml;
     const int rl = tid / np2, xs = tid - rl * np2;
-    const long long u = (long long)blockIdx.x * rpb + rl;  // row k*ny + j
+    const long long u = blk * rpb + rl;  // row k*ny + j
     const bool valid = rl < rpb && u < (long long)a.ny * a.nz;
     const int j = (int)(u % a.ny), k = (int)(u / a.ny);
     const int i = xs < a.npml ? xs : a.nx - np2 + xs;
@@ -859,6 +881,59 @@ __global__ __launch_bounds__(256) void ccpr_post_fused_kernel(const StepArgs a, 
     st_stream<NT>(&pout[sz + x], p1);
     stf_nt<NT>(a.Ho, o + cs, hy + a.S * fmaf(cfh.z - 1.f, dEz, p0));
     stf_nt<NT>(a.Ho, o + 2 * cs, hz - a.S * fmaf(cfh.z - 1.f, dEy, p1));
+}
+
+template <bool NT>
+__global__ __launch_bounds__(256) void ccpr_post_fused_kernel(const StepArgs a, int rpb, long long nbx,
+                                                              long long nmisc, long long ntfh)
+{
+    __shared__ float se[2][256];
+    if (*a.halt) return;
+    post_fused_block<NT>(a, rpb, nbx, nmisc, ntfh, blockIdx.x, se);
+}
+
+// ---- batched steps (serving engine): the same bodies as ccpr_step_kernel
+// (CPML variant on every tile), ccpr_aux_kernel (time-exact, one density per
+// voxel) and ccpr_post_fused_kernel / ccpr_post_kernel, each block taking
+// its solve's StepArgs from the kernel argument.  No XCD tile remap: a
+// solve's tiles are few.
+__device__ __forceinline__ int batch_solve(const int* start, int n, int b)
+{
+    int s = 0;
+    while (s + 1 < n && b >= start[s + 1]) ++s;
+    return s;
+}
+
+template <bool NT>
+__global__ __launch_bounds__(1024) void ccpr_batch_grid_kernel(const BatchArgs B)
+{
+    __shared__ float xe[2][3][16];
+    __shared__ float xh[2][2][16];
+    const int s = batch_solve(B.gstart, B.n, blockIdx.x);
+    const StepArgs& a = B.a[s];
+    if (*a.halt) return;
+    grid_tile<2, true, NT>(a, (int)blockIdx.x - B.gstart[s], xe, xh);
+}
+
+template <int PMAX, bool NT>
+__global__ __launch_bounds__(256) void ccpr_batch_aux_kernel(const BatchArgs B)
+{
+    const int s = batch_solve(B.astart, B.n, blockIdx.x);
+    const StepArgs& a = B.a[s];
+    if (*a.halt) return;
+    aux_cell<PMAX, NT, false, false>(a, ((unsigned)blockIdx.x - (unsigned)B.astart[s]) * 256u + threadIdx.x);
+}
+
+template <bool NT>
+__global__ __launch_bounds__(256) void ccpr_batch_post_kernel(const BatchArgs B)
+{
+    __shared__ float se[2][256];
+    const int s = batch_solve(B.pstart, B.n, blockIdx.x);
+    const StepArgs& a = B.a[s];
+    if (*a.halt) return;
+    const long long blk = (long long)blockIdx.x - B.pstart[s];
+    if (B.fused[s]) post_fused_block<NT>(a, B.rpb[s], B.nbx[s], B.nmisc[s], B.ntfh[s], blk, se);
+    else post_cell(a, blk * 256 + threadIdx.x, B.nxs[s], B.nmisc[s]);
 }
 
 // DFT-mode gradient of each design voxel (see ccpr_set_gradient_mode): the
@@ -1200,6 +1275,65 @@ int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, bool edge, vo
     dim3 ag((unsigned)((nd + 255) / 256)), ab(256);
     if (edge) launch_aux_mode<true>(a, maxpairs, ag, ab, s);
     else launch_aux_mode<false>(a, maxpairs, ag, ab, s);
+    return (int)hipGetLastError();
+}
+
+int ccpr_launch_batch(const BatchStep* st, int k, void* stream)
+{
+    if (k < 1 || k > CCPR_BATCH_MAX) return (int)hipErrorInvalidValue;
+    BatchArgs B;
+    std::memset(&B, 0, sizeof B);
+    B.n = k;
+    int maxp = 0;
+    long long g = 0, x = 0, q = 0;
+    for (int s = 0; s < k; ++s) {
+        const BatchStep& t = st[s];
+        if (t.a.nxp != st[0].a.nxp || t.a.rows != 2 || 2 * t.a.npml > 256) return (int)hipErrorInvalidValue;
+        B.a[s] = t.a;
+        maxp = std::max(maxp, t.maxpairs);
+        const int np2 = 2 * t.a.npml;
+        B.rpb[s] = np2 > 0 ? 256 / np2 : 1;
+        B.nbx[s] = np2 > 0 ? ((long long)t.a.ny * t.a.nz + B.rpb[s] - 1) / B.rpb[s] : 0;
+        B.nmisc[s] = t.nmisc;
+        B.ntfh[s] = t.ntfh;
+        B.nxs[s] = t.nxs;
+        B.fused[s] = t.fused;
+        B.gstart[s] = (int)g;
+        B.astart[s] = (int)x;
+        B.pstart[s] = (int)q;
+        g += t.a.nblk;
+        x += (t.nd + 255) / 256;
+        q += t.fused ? B.nbx[s] + (t.nmisc + t.ntfh + 255) / 256 : (t.nxs + t.nmisc + 255) / 256;
+    }
+    if (g > 0x7fffffff || x > 0x7fffffff || q > 0x7fffffff) return (int)hipErrorInvalidValue;
+    B.gstart[k] = (int)g;
+    B.astart[k] = (int)x;
+    B.pstart[k] = (int)q;
+    hipStream_t hs = (hipStream_t)stream;
+    const bool nt = st[0].a.stream_st != 0;
+    if (g > 0) {
+        if (nt) hipLaunchKernelGGL(ccpr_batch_grid_kernel<true>, dim3((unsigned)g), dim3(st[0].a.nxp), 0, hs, B);
+        else hipLaunchKernelGGL(ccpr_batch_grid_kernel<false>, dim3((unsigned)g), dim3(st[0].a.nxp), 0, hs, B);
+    }
+    if (x > 0) {
+#define CCPR_BAUX(P)                                                                                     \
+    do {                                                                                                 \
+        if (nt) hipLaunchKernelGGL((ccpr_batch_aux_kernel<P, true>), dim3((unsigned)x), dim3(256), 0, hs, B); \
+        else hipLaunchKernelGGL((ccpr_batch_aux_kernel<P, false>), dim3((unsigned)x), dim3(256), 0, hs, B); \
+    } while (0)
+        if (maxp <= 0) CCPR_BAUX(0);
+        else if (maxp <= 1) CCPR_BAUX(1);
+        else if (maxp <= 2) CCPR_BAUX(2);
+        else if (maxp <= 3) CCPR_BAUX(3);
+        else if (maxp <= 4) CCPR_BAUX(4);
+        else if (maxp <= 6) CCPR_BAUX(6);
+        else CCPR_BAUX(8);
+#undef CCPR_BAUX
+    }
+    if (q > 0) {
+        if (nt) hipLaunchKernelGGL(ccpr_batch_post_kernel<true>, dim3((unsigned)q), dim3(256), 0, hs, B);
+        else hipLaunchKernelGGL(ccpr_batch_post_kernel<false>, dim3((unsigned)q), dim3(256), 0, hs, B);
+    }
     return (int)hipGetLastError();
 }
 

@@ -34,3 +34,21 @@ void ccpr_pipe_unbind(ccpr_solver* s);
 // Second stream for the solver's concurrent grid launches (owned by the
 // caller, default priority); must be set before ccpr_pipe_begin.
 ccpr_status ccpr_pipe_set_stream2(ccpr_solver* s, void* stream2);
+
+#define CCPR_PIPE_BATCH_MAX 8  // solves per batched launch
+
+// Batched serving.  ccpr_pipe_batch_class: the padded x width of a solve that
+// the batched launches can advance (solves of one width are batched
+// together), or -1 (per-edge designs, DFT-mode gradients, 4 rows per thread).
+int ccpr_pipe_batch_class(const ccpr_solver* s);
+
+// Switch recording on (before ccpr_pipe_begin, with every solve of a batch
+// bound to one stream): ccpr_pipe_advance(s, 1) then records its leapfrog
+// step (work before it, such as checkpoints, is enqueued at once) instead of
+// launching it.  CCPR_ENOTSUP if ccpr_pipe_batch_class is -1.
+ccpr_status ccpr_pipe_set_batched(ccpr_solver* s, int on);
+
+// Launch the steps recorded by ss[0..k) (at most CCPR_BATCH_MAX of them, of
+// one padded x width) as one batched grid, aux and post launch on stream, then
+// their watchdog checks; the solves' results are the same as unbatched.
+ccpr_status ccpr_pipe_flush(ccpr_solver* const* ss, int k, void* stream);

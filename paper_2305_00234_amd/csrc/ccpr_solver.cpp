@@ -158,6 +158,12 @@ struct ccpr_solver {
     // resumable solve (serving engine): phase 0 forward, 1 objective,
     // 2 adjoint (sub 0: recompute the segment, 1: adjoint steps), 3 all enqueued
     int pipe_phase = 3, pipe_n = 0, pipe_seg = 0, pipe_sub = 0, pipe_k = 0;
+    // batched serving (ccpr_pipe_set_batched): launch_step records the grid /
+    // aux / post work of a step instead of launching it; ccpr_pipe_flush
+    // launches the recorded steps of several solves together
+    bool batched = false;
+    bool rec_pending = false, rec_watch = false;
+    BatchStep rec{};
 };
 
 namespace {
@@ -753,7 +759,7 @@ ccpr_status upload_cold(ccpr_solver* s, int st)
                           hipMemcpyHostToDevice, s->stream));
     // (no second stream on the static workspace: creating one is a resource
     // allocation its callers cannot make)
-    if (s->ntiles_pml > 0 && s->ntiles_int > 0 && !s->stream2 && s->static_dev < 0) {
+    if (s->ntiles_pml > 0 && s->ntiles_int > 0 && !s->stream2 && s->static_dev < 0 && !s->batched) {
         HIPCHK(hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking));
         s->own_stream2 = true;
     }
@@ -855,6 +861,26 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
     hipStream_t Fs = s->lead2 ? s->stream : s->stream2;
     int e = s->pre_done[st] ? 0 : ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, Ls);
     s->pre_done[st] = false;
+    if (s->batched) {
+        // record the grid (every tile, CPML variant), aux and post work of
+        // this step for the next ccpr_pipe_flush
+        if (e != 0) return fail(s, CCPR_EDEVICE, "pre kernel launch: %s", hipGetErrorString((hipError_t)e));
+        if (s->rec_pending) return fail(s, CCPR_ESTATE, "internal: a recorded step was not flushed");
+        fuse = fuse && s->fuse_ok[st];
+        s->rec.a = A;
+        s->rec.a.nblk = s->ntiles_int + s->ntiles_pml;
+        s->rec.maxpairs = s->maxpairs;
+        s->rec.nd = ndes;
+        s->rec.fused = fuse ? 1 : 0;
+        s->rec.nxs = nxs;
+        s->rec.nmisc = nmisc;
+        s->rec.ntfh = C.pw_on ? C.tf_nH : 0;
+        s->rec_watch = s->watch_run && s->watch_every > 0 && s->has_obj && (A.n + 1) % s->watch_every == 0;
+        s->rec_pending = true;
+        s->pre_done[st] = fuse;
+        s->parity[st] ^= 1;
+        return CCPR_OK;
+    }
     const bool tm = s->timing && s->timed_loop && (s->pass_no++ % s->timing_every) == 0;
     if (tm) {
         while (s->tev.size() < s->tev_used + 3) {
@@ -2075,6 +2101,59 @@ ccpr_status ccpr_pipe_check(ccpr_solver* s, const double* scal_host, double* F)
 
 long long ccpr_pipe_design_voxels(const ccpr_solver* s) { return s->has_design ? n_rho(s) : 0; }
 
+static_assert(CCPR_PIPE_BATCH_MAX == CCPR_BATCH_MAX, "batch sizes of the engine and the kernels differ");
+
+int ccpr_pipe_batch_class(const ccpr_solver* s)
+{
+    // batched launches cover one density per voxel, the time-exact gradient,
+    // 2 rows per thread and x layers that fit the fused post kernel's blocks
+    if (s->edge || s->grad_dft || s->rows != 2 || 2 * s->g.npml > 256) return -1;
+    return s->nxp;
+}
+
+ccpr_status ccpr_pipe_set_batched(ccpr_solver* s, int on)
+{
+    {
+        ccpr_status j = join_lead(s);
+        if (j) return j;
+    }
+    if (on && ccpr_pipe_batch_class(s) < 0) return fail(s, CCPR_ENOTSUP, "this solve cannot be batched");
+    s->batched = on != 0;
+    s->rec_pending = false;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_pipe_flush(ccpr_solver* const* ss, int k, void* stream)
+{
+    BatchStep st[CCPR_BATCH_MAX];
+    ccpr_solver* who[CCPR_BATCH_MAX];
+    int m = 0;
+    for (int q = 0; q < k; ++q) {
+        ccpr_solver* s = ss[q];
+        if (!s->rec_pending) continue;
+        if (m == CCPR_BATCH_MAX || (m > 0 && s->rec.a.nxp != st[0].a.nxp)) return CCPR_EINVAL;
+        st[m] = s->rec;
+        who[m++] = s;
+    }
+    if (m == 0) return CCPR_OK;
+    const int e = ccpr_launch_batch(st, m, stream);
+    ccpr_status res = e == 0 ? CCPR_OK : CCPR_EDEVICE;
+    for (int q = 0; q < m; ++q) {
+        ccpr_solver* s = who[q];
+        s->rec_pending = false;
+        if (e != 0) {
+            fail(s, CCPR_EDEVICE, "batched step launch: %s", hipGetErrorString((hipError_t)e));
+            continue;
+        }
+        if (s->rec_watch) {
+            const int w = ccpr_launch_watch(s->rec.a, s->glo, s->gdim, (float)s->watch_limit, s->rec.a.n,
+                                            wsp<unsigned>(s, s->lay.halt), wsp<double>(s, s->lay.scal), stream);
+            if (w != 0) res = fail(s, CCPR_EDEVICE, "watchdog launch: %s", hipGetErrorString((hipError_t)w));
+        }
+    }
+    return res;
+}
+
 ccpr_status ccpr_pipe_set_stream2(ccpr_solver* s, void* stream2)
 {
     {
@@ -2100,5 +2179,7 @@ void ccpr_pipe_unbind(ccpr_solver* s)
     s->rho_uploaded = false;
     s->lead2 = false;  // (the engine unbinds after the solve's work completed)
     s->pre_done[0] = s->pre_done[1] = false;
+    s->batched = false;
+    s->rec_pending = false;
     std::memset(s->fixed_key, 0xff, sizeof s->fixed_key);
 }

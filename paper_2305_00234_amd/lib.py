@@ -39,6 +39,7 @@ EXPORTS = [
     "ccpr_set_tile_planes", "ccpr_set_tile_rows", "ccpr_set_watchdog", "ccpr_forward_serial",
     "ccpr_engine_create", "ccpr_engine_submit", "ccpr_engine_poll", "ccpr_engine_wait",
     "ccpr_engine_result", "ccpr_engine_release", "ccpr_engine_last_error", "ccpr_engine_destroy",
+    "ccpr_engine_set_batching",
     "ccpr_filter_project", "ccpr_filter_project_grad", "ccpr_nondiscreteness",
     "ccpr_filter_project_edges", "ccpr_filter_project_grad_edges",
 ]
@@ -119,6 +120,7 @@ def load():
         "ccpr_engine_release": (_i, [_p, C.c_uint64]),
         "ccpr_engine_last_error": (C.c_char_p, [_p]),
         "ccpr_engine_destroy": (None, [_p]),
+        "ccpr_engine_set_batching": (_i, [_p, _i]),
         "ccpr_filter_project": (_i, [_p, _p, _p, _p, _ip, _d, _d, _d, _p]),
         "ccpr_filter_project_grad": (_i, [_p, _p, _p, _p, _ip, _d, _d, _d, _p]),
         "ccpr_filter_project_edges": (_i, [_p, _p, _p, _p, _ip, _d, _d, _d, _p]),
@@ -566,7 +568,8 @@ class Engine:
     sub-allocates the solves' workspaces from it.  Solvers passed to submit()
     are kept alive here until their job is released."""
 
-    def __init__(self, arena_bytes: int, max_active: int = 4, chunk_steps: int = 32, device=None):
+    def __init__(self, arena_bytes: int, max_active: int = 4, chunk_steps: int = 32, device=None,
+                 batching: bool = True):
         import torch
         self._lib = load()
         self._arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=torch.device(device or "cuda"))
@@ -577,6 +580,8 @@ class Engine:
             raise CcprError(st, "ccpr_engine_create", "bad engine arguments")
         self._h = h
         self._solvers = {}
+        if not batching:
+            self._chk(self._lib.ccpr_engine_set_batching(self._h, 0), "ccpr_engine_set_batching")
 
     def _chk(self, st, what):
         if st != OK:

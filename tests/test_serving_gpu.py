@@ -125,3 +125,64 @@ def test_submit_rejects_oversized_and_duplicate():
     eng.release(t)
     eng.close()
     s.close()
+
+
+def _small_mix():
+    """Twelve solves of two padded x widths (64 and 128 cells), 1-3 pole
+    pairs, 4- or 6-cell CPML, 120-300 steps; two with the time-domain
+    objective in 40-step checkpointed segments (one resident: the adjoint
+    recomputes the others)."""
+    specs = [(24, 1, 160, 4), (28, 2, 200, 4), (32, 3, 240, 6), (36, 1, 120, 4), (40, 2, 300, 6),
+             (44, 3, 180, 4), (48, 1, 220, 6), (52, 2, 140, 4), (66, 3, 160, 6), (72, 1, 200, 4),
+             (80, 2, 180, 6), (100, 3, 120, 4)]
+    ws = []
+    for k, (side, p, steps, npml) in enumerate(specs):
+        w = I.serving_workload(side, p, steps, seed=900 + k, npml=npml)
+        if k in (2, 9):
+            w.objective = "time"
+            w.checkpoint_every = 40
+        ws.append(w)
+    return ws
+
+
+def _serve(ws, batching, max_active=12, chunk=8):
+    from paper_2305_00234_amd.lib import JOB_DONE, JOB_FAILED, Engine
+    from paper_2305_00234_amd.solver import configure
+    solvers = [configure(w) for w in ws]
+    arena = sum(s.workspace_size(w.steps) for s, w in zip(solvers, ws)) + (64 << 20)
+    eng = Engine(arena, max_active=max_active, chunk_steps=chunk, batching=batching)
+    tickets = [eng.submit(s, w.steps) for s, w in zip(solvers, ws)]
+    t0 = time.time()
+    while True:
+        states = [eng.poll(t) for t in tickets]
+        assert JOB_FAILED not in states, states
+        if all(st == JOB_DONE for st in states):
+            break
+        assert time.time() - t0 < 120
+        time.sleep(0.0005)
+    out = []
+    for t in tickets:
+        F, g, _ = eng.result(t)
+        out.append((F, g))
+        eng.release(t)
+    eng.close()
+    for s in solvers:
+        s.close()
+    return out
+
+
+def test_batched_small_solves_two_widths_equal_alone():
+    """Batched launches (one grid, aux and post launch per step for up to 8
+    solves of one padded width; twelve solves need two launches of the
+    64-cell class per step) give every solve bitwise the objective and
+    gradient it has alone, and the same as the engine with batching off."""
+    torch = require_gpu()
+    ws = _small_mix()
+    alone = [_alone(w) for w in ws]
+    torch.cuda.synchronize()
+    batched = _serve(ws, batching=True)
+    plain = _serve(ws, batching=False)
+    for k, ((F, g), (Fb, gb), (Fp, gp)) in enumerate(zip(alone, batched, plain)):
+        say("request", k, ws[k].name, ws[k].objective, "F", F, Fb, Fp)
+        assert Fb == F and Fp == F
+        assert _same(gb, g) and _same(gp, g)
