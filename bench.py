@@ -153,7 +153,7 @@ def cpu_baseline(w, sample_steps):
                       f"objective and gradient ({dt:.1f} s wall)"}
 
 
-def serving(args, n_requests=None, emit=True):
+def serving(args, n_requests=None, emit=True, sides=(64, 192), rate=None):
     """Serving trace (Poisson arrivals, uneven grids and pole counts): the
     engine's continuous batching (batched launches per padded x width)
     against the same engine with every solve on its own streams and against
@@ -164,7 +164,8 @@ def serving(args, n_requests=None, emit=True):
     from paper_2305_00234_amd.lib import JOB_DONE, JOB_FAILED, Engine
     from paper_2305_00234_amd.solver import configure
 
-    trace = I.serving_trace(n_requests=n_requests or args.serving, rate=args.rate, seed=3)
+    rate = rate or args.rate
+    trace = I.serving_trace(n_requests=n_requests or args.serving, rate=rate, seed=3, side_range=sides)
     arrivals = np.array([r.arrival for r in trace]) - trace[0].arrival
 
     def progress(msg):
@@ -248,8 +249,8 @@ def serving(args, n_requests=None, emit=True):
                                          "p99": round(float(np.percentile(str_lat, 99)) * 1e3, 1)},
         "results_identical": bool(same and same_s),
         "n_gpus": 1, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "serving_trace", "requests": len(trace), "rate_per_s": args.rate,
-                   "sides": "U{64..192}", "pole_pairs": "U{1..3}", "steps": "U{1500..4000}",
+        "config": {"workload": "serving_trace", "requests": len(trace), "rate_per_s": rate,
+                   "sides": f"U{{{sides[0]}..{sides[1]}}}", "pole_pairs": "U{1..3}", "steps": "U{1500..4000}",
                    "max_active": args.max_active, "chunk_steps": args.chunk,
                    "arena_GiB": args.arena_gb,
                    "cell_updates": int(sum(2 * r.workload.cells * r.workload.steps for r in trace))},
@@ -305,6 +306,8 @@ def main():
                     help="run only the serving trace, with this many requests")
     ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests of the serving record in the default run (0: skip it)")
+    ap.add_argument("--serving-small-requests", type=int, default=48,
+                    help="requests of the small-grid serving record (sides U{24..64}, 200 requests/s; 0: skip)")
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--chunk", type=int, default=32)
@@ -415,10 +418,11 @@ def main():
                  "achieved_GBs": round(sb / avg_step_s / 1e9, 1),
                  "frac": round(sb / avg_step_s / 1e9 / HBM_PEAK_GBS, 4), "steps": launches},
     }
-    if args.serving_requests > 0:
+    if args.serving_requests > 0 or args.serving_small_requests > 0:
         s.close()
         del s, grad
         torch.cuda.empty_cache()
+    if args.serving_requests > 0:
         progress(f"serving trace ({args.serving_requests} requests)")
         sv = serving(args, n_requests=args.serving_requests, emit=False)
         out["serving"] = {k: sv[k] for k in ("value", "unit", "sequential_solves_per_s", "speedup",
@@ -426,6 +430,13 @@ def main():
                                              "sequential_latency_ms", "per_solve_streams_latency_ms",
                                              "results_identical")}
         out["serving"]["config"] = sv["config"]
+    if args.serving_small_requests > 0:
+        progress(f"small-grid serving trace ({args.serving_small_requests} requests)")
+        sv = serving(args, n_requests=args.serving_small_requests, emit=False, sides=(24, 64), rate=200.0)
+        out["serving_small"] = {k: sv[k] for k in ("value", "sequential_solves_per_s", "speedup",
+                                                   "per_solve_streams_solves_per_s", "latency_ms",
+                                                   "sequential_latency_ms", "results_identical")}
+        out["serving_small"]["config"] = sv["config"]
     if not args.no_cpu_baseline:
         progress("cpu baseline (FP64 oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)

@@ -32,14 +32,15 @@
 // 64, y to nyp = (ny rounded up to CCPR_YPAD) + 2 with one zero row below, z to
 // nzp = nz + 2 with one zero plane below and above.  Cell (i,j,k) of component
 // c lives at c*npad + ((k+1)*nyp + (j+1))*nxp + i; ghost cells are zero and
-// never written.  Kernels address fields with 32-bit byte offsets, so
-// 3*npad*4 must stay below 2^32.
+// never written.  Kernels address a component with 32-bit byte offsets from
+// its own base, so npad*4 must stay below 2^32.
 
-// One TF/SF face correction: field word at byte offset 'off' of E (or H),
-// incident table column m, coefficient coef (sign, side and Courant number
-// folded in); uidx = component * nx*ny*nz + (k*ny + j)*nx + i.
+// One TF/SF face correction: field word at byte offset 'off' of E (or H)
+// (component included, so 64-bit), incident table column m, coefficient coef
+// (sign, side and Courant number folded in);
+// uidx = component * nx*ny*nz + (k*ny + j)*nx + i.
 struct TfEntry {
-    unsigned off;
+    unsigned long long off;
     int m;
     float coef;
     unsigned uidx;

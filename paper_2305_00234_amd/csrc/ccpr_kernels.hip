@@ -184,6 +184,24 @@ __device__ __forceinline__ void stf_nt(float* base, unsigned boff, float v)
     st_stream<NT>(reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff), v);
 }
 
+// Component c of a field buffer (components npad floats = cs bytes apart).
+// The base is formed in 64-bit arithmetic (uniform, scalar registers), so the
+// per-lane byte offsets of ldf / stf stay 32-bit within one component: a
+// component may hold up to 2^30 floats.
+__device__ __forceinline__ const float* fcomp(const float* base, unsigned cs, int c)
+{
+    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (size_t)cs * (size_t)c);
+}
+__device__ __forceinline__ float* fcomp(float* base, unsigned cs, int c)
+{
+    return reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (size_t)cs * (size_t)c);
+}
+// Field word at a 64-bit byte offset (TF/SF face list).
+__device__ __forceinline__ float* fword(const float* base, unsigned long long boff)
+{
+    return reinterpret_cast<float*>(const_cast<char*>(reinterpret_cast<const char*>(base)) + boff);
+}
+
 // CPML memory update on one derivative d with the (prefetched) old memory p:
 // p' = b p + a d (stored by the owner only); returns d/kappa + p'.
 __device__ __forceinline__ float cpml(float d, float4 cf, float p, float* pout, unsigned idx, bool store)
@@ -270,8 +288,8 @@ __device__ __forceinline__ void grid_tile(const StepArgs& a, const int L, float 
     for (int r = 0; r < R + 2; ++r) {
         const unsigned o = poff(k0 - 1, r);
         ex[r] = ldf(a.Ei, o);
-        ey[r] = ldf(a.Ei, o + cs);
-        ez[r] = ldf(a.Ei, o + 2 * cs);
+        ey[r] = ldf(fcomp(a.Ei, cs, 1), o);
+        ez[r] = ldf(fcomp(a.Ei, cs, 2), o);
     }
 #pragma unroll
     for (int r = 0; r <= R; ++r) { hxm[r] = 0.f; hym[r] = 0.f; }
@@ -288,15 +306,15 @@ __device__ __forceinline__ void grid_tile(const StepArgs& a, const int L, float 
         for (int r = 0; r < R + 2; ++r) {
             const unsigned o = poff(kk + 1, r);
             nex[r] = ldf(a.Ei, o);
-            ney[r] = ldf(a.Ei, o + cs);
-            nez[r] = zlast ? 0.f : ldf(a.Ei, o + 2 * cs);
+            ney[r] = ldf(fcomp(a.Ei, cs, 1), o);
+            nez[r] = zlast ? 0.f : ldf(fcomp(a.Ei, cs, 2), o);
         }
 #pragma unroll
         for (int r = 0; r <= R; ++r) {
             const unsigned o = poff(kk, r);
             hxo[r] = ldf(a.Hi, o);
-            hyo[r] = ldf(a.Hi, o + cs);
-            hzo[r] = zhalo ? 0.f : ldf(a.Hi, o + 2 * cs);
+            hyo[r] = ldf(fcomp(a.Hi, cs, 1), o);
+            hzo[r] = zhalo ? 0.f : ldf(fcomp(a.Hi, cs, 2), o);
         }
 
         // ---- row classes of this plane.  Row r is H row j0-1+r; E rows are r = 1..R.
@@ -382,8 +400,8 @@ __device__ __forceinline__ void grid_tile(const StepArgs& a, const int L, float 
             if (own && xin) {
                 const unsigned o = poff(kk, r);
                 stf_nt<NT>(a.Ho, o, hx[r]);
-                stf_nt<NT>(a.Ho, o + cs, hy[r]);
-                stf_nt<NT>(a.Ho, o + 2 * cs, hz[r]);
+                stf_nt<NT>(fcomp(a.Ho, cs, 1), o, hy[r]);
+                stf_nt<NT>(fcomp(a.Ho, cs, 2), o, hz[r]);
             }
         }
 
@@ -436,8 +454,8 @@ __device__ __forceinline__ void grid_tile(const StepArgs& a, const int L, float 
                 if (xin) {
                     const unsigned o = poff(kk, r);
                     stf_nt<NT>(a.Eo, o, nxv);
-                    stf_nt<NT>(a.Eo, o + cs, nyv);
-                    stf_nt<NT>(a.Eo, o + 2 * cs, nzv);
+                    stf_nt<NT>(fcomp(a.Eo, cs, 1), o, nyv);
+                    stf_nt<NT>(fcomp(a.Eo, cs, 2), o, nzv);
                 }
                 // design / source cells: hand the drive to the aux kernel
                 if ((rf[r] & CCPR_ROW_DES) && (lf & CCPR_LANE_DES)) {
@@ -538,7 +556,7 @@ __device__ __forceinline__ void aux_cell(const StepArgs& a, const unsigned t)
     j_load<0, PMAX>(c, v, jrx, jix, onx);
     j_load<1, PMAX>(c, v, jry, jiy, ony);
     j_load<2, PMAX>(c, v, jrz, jiz, onz);
-    const float e0x = ldf(a.Ei, o), e0y = ldf(a.Ei, o + cs), e0z = ldf(a.Ei, o + 2 * cs);
+    const float e0x = ldf(a.Ei, o), e0y = ldf(fcomp(a.Ei, cs, 1), o), e0z = ldf(fcomp(a.Ei, cs, 2), o);
     float dx_ = a.drive[v], dy_ = a.drive[c.nd + v], dz_ = a.drive[2 * c.nd + v];
     float rhox, rhoy, rhoz;
     if constexpr (EDGE) {
@@ -601,8 +619,8 @@ __device__ __forceinline__ void aux_cell(const StepArgs& a, const unsigned t)
     if (!EDGE || ony) j_store<1, PMAX, NT>(c, v, jry, jiy);
     if (!EDGE || onz) j_store<2, PMAX, NT>(c, v, jrz, jiz);
     stf_nt<NT>(a.Eo, o, nxv);
-    stf_nt<NT>(a.Eo, o + cs, nyv);
-    stf_nt<NT>(a.Eo, o + 2 * cs, nzv);
+    stf_nt<NT>(fcomp(a.Eo, cs, 1), o, nyv);
+    stf_nt<NT>(fcomp(a.Eo, cs, 2), o, nzv);
     if (a.mode & CCPR_MODE_RECORD) {
         st_stream<NT>(&Tslot[v], Tx);
         st_stream<NT>(&Tslot[c.nd + v], Ty);
@@ -655,7 +673,10 @@ __device__ __forceinline__ void aux_misc(const StepArgs& a, long long e)
         const long long f = e - a.nextra;
         if (f < c.tf_nE) {
             const TfEntry q = c.tf[f];
-            if (n < c.tf_rows) stf(a.Eo, q.off, ldf(a.Eo, q.off) + q.coef * c.incH[(long long)n * c.pw_spanH + q.m]);
+            if (n < c.tf_rows) {
+                float* w = fword(a.Eo, q.off);
+                *w = *w + q.coef * c.incH[(long long)n * c.pw_spanH + q.m];
+            }
         }
         return;
     }
@@ -685,12 +706,12 @@ __device__ __forceinline__ void aux_misc(const StepArgs& a, long long e)
         if (i == 0 || kk == 0) nyv = 0.f;
         if (i == 0 || j == 0) nzv = 0.f;
         stf(a.Eo, o, nxv);
-        stf(a.Eo, o + cs, nyv);
-        stf(a.Eo, o + 2 * cs, nzv);
+        stf(fcomp(a.Eo, cs, 1), o, nyv);
+        stf(fcomp(a.Eo, cs, 2), o, nzv);
     } else {
         nxv = ldf(a.Eo, o);
-        nyv = ldf(a.Eo, o + cs);
-        nzv = ldf(a.Eo, o + 2 * cs);
+        nyv = ldf(fcomp(a.Eo, cs, 1), o);
+        nzv = ldf(fcomp(a.Eo, cs, 2), o);
     }
     if ((a.mode & CCPR_MODE_GAP) && in_box(i, j, kk, c.glo, c.gdim)) {
         float* g = c.gap + ((long long)(n + 1) * c.gncell + box_index(i, j, kk, c.glo, c.gdim)) * 3;
@@ -721,8 +742,8 @@ __global__ __launch_bounds__(256) void ccpr_pre_kernel(const StepArgs a, long lo
         const int i = xs < a.npml ? xs : a.nx - np2 + xs;
         const unsigned o = (((unsigned)(k + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
         const bool right = i + 1 < a.nx;
-        const float dEz = (right ? ldf(a.Ei, o + 4 + 2 * cs) : 0.f) - ldf(a.Ei, o + 2 * cs);
-        const float dEy = (right ? ldf(a.Ei, o + 4 + cs) : 0.f) - ldf(a.Ei, o + cs);
+        const float dEz = (right ? ldf(fcomp(a.Ei, cs, 2), o + 4) : 0.f) - ldf(fcomp(a.Ei, cs, 2), o);
+        const float dEy = (right ? ldf(fcomp(a.Ei, cs, 1), o + 4) : 0.f) - ldf(fcomp(a.Ei, cs, 1), o);
         const float4 cf = c.pmlH[0][i];
         const unsigned x = (unsigned)u * np2 + xs;
         const unsigned sz = (unsigned)a.nz * a.ny * np2;
@@ -732,14 +753,15 @@ __global__ __launch_bounds__(256) void ccpr_pre_kernel(const StepArgs a, long lo
         const float p1 = fmaf(cf.x, pin[sz + x], cf.y * dEy);
         pout[x] = p0;
         pout[sz + x] = p1;
-        stf(H, o + cs, ldf(H, o + cs) + a.S * fmaf(cf.z - 1.f, dEz, p0));
-        stf(H, o + 2 * cs, ldf(H, o + 2 * cs) - a.S * fmaf(cf.z - 1.f, dEy, p1));
+        stf(fcomp(H, cs, 1), o, ldf(fcomp(H, cs, 1), o) + a.S * fmaf(cf.z - 1.f, dEz, p0));
+        stf(fcomp(H, cs, 2), o, ldf(fcomp(H, cs, 2), o) - a.S * fmaf(cf.z - 1.f, dEy, p1));
         return;
     }
     const long long f = t - nxs;
     if (c.pw_on && f < c.tf_nH && a.n < c.tf_rows) {
         const TfEntry q = c.tf[c.tf_nE + f];
-        stf(H, q.off, ldf(H, q.off) + q.coef * c.incE[(long long)a.n * c.pw_spanE + q.m]);
+        float* w = fword(H, q.off);
+        *w = *w + q.coef * c.incE[(long long)a.n * c.pw_spanE + q.m];
     }
 }
 
@@ -763,8 +785,8 @@ __device__ __forceinline__ void post_cell(const StepArgs& a, const long long t, 
     const int i = xs < a.npml ? xs : a.nx - np2 + xs;
     if (i == 0) return;
     const unsigned o = (((unsigned)(k + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
-    const float dHz = ldf(a.Ho, o + 2 * cs) - ldf(a.Ho, o - 4 + 2 * cs);
-    const float dHy = ldf(a.Ho, o + cs) - ldf(a.Ho, o - 4 + cs);
+    const float dHz = ldf(fcomp(a.Ho, cs, 2), o) - ldf(fcomp(a.Ho, cs, 2), o - 4);
+    const float dHy = ldf(fcomp(a.Ho, cs, 1), o) - ldf(fcomp(a.Ho, cs, 1), o - 4);
     const float4 cf = c.pmlE[0][i];
     const unsigned x = (unsigned)u * np2 + xs;
     const unsigned sz = (unsigned)a.nz * a.ny * np2;
@@ -773,8 +795,8 @@ __device__ __forceinline__ void post_cell(const StepArgs& a, const long long t, 
     const float p1 = fmaf(cf.x, ps[sz + x], cf.y * dHy);
     ps[x] = p0;
     ps[sz + x] = p1;
-    if (k != 0) stf(a.Eo, o + cs, ldf(a.Eo, o + cs) - a.S * fmaf(cf.z - 1.f, dHz, p0));
-    if (j != 0) stf(a.Eo, o + 2 * cs, ldf(a.Eo, o + 2 * cs) + a.S * fmaf(cf.z - 1.f, dHy, p1));
+    if (k != 0) stf(fcomp(a.Eo, cs, 1), o, ldf(fcomp(a.Eo, cs, 1), o) - a.S * fmaf(cf.z - 1.f, dHz, p0));
+    if (j != 0) stf(fcomp(a.Eo, cs, 2), o, ldf(fcomp(a.Eo, cs, 2), o) + a.S * fmaf(cf.z - 1.f, dHy, p1));
 }
 
 __global__ __launch_bounds__(256) void ccpr_post_kernel(const StepArgs a, long long nxs, long long nmisc)
@@ -813,7 +835,8 @@ __device__ __forceinline__ void post_fused_block(const StepArgs& a, int rpb, lon
         const long long f = t - nmisc;
         if (f < ntfh && a.n + 1 < c.tf_rows) {
             const TfEntry q = c.tf[c.tf_nE + f];
-            stf(a.Ho, q.off, ldf(a.Ho, q.off) + q.coef * c.incE[(long long)(a.n + 1) * c.pw_spanE + q.m]);
+            float* w = fword(a.Ho, q.off);
+            *w = *w + q.coef * c.incE[(long long)(a.n + 1) * c.pw_spanE + q.m];
         }
         return;
     }
@@ -839,16 +862,16 @@ __device__ __forceinline__ void post_fused_block(const StepArgs& a, int rpb, lon
         ph0 = pin[x];
         ph1 = pin[sz + x];
         if (xs == a.npml - 1) {
-            eyr = ldf(a.Eo, o + 4 + cs);
-            ezr = ldf(a.Eo, o + 4 + 2 * cs);
+            eyr = ldf(fcomp(a.Eo, cs, 1), o + 4);
+            ezr = ldf(fcomp(a.Eo, cs, 2), o + 4);
         }
-        hy = ldf(a.Ho, o + cs);
-        hz = ldf(a.Ho, o + 2 * cs);
-        ey = ldf(a.Eo, o + cs);
-        ez = ldf(a.Eo, o + 2 * cs);
+        hy = ldf(fcomp(a.Ho, cs, 1), o);
+        hz = ldf(fcomp(a.Ho, cs, 2), o);
+        ey = ldf(fcomp(a.Eo, cs, 1), o);
+        ez = ldf(fcomp(a.Eo, cs, 2), o);
         if (i > 0) {
-            const float dHz = hz - ldf(a.Ho, o - 4 + 2 * cs);
-            const float dHy = hy - ldf(a.Ho, o - 4 + cs);
+            const float dHz = hz - ldf(fcomp(a.Ho, cs, 2), o - 4);
+            const float dHy = hy - ldf(fcomp(a.Ho, cs, 1), o - 4);
             const float4 cf = c.pmlE[0][i];
             float* ps = c.psiE[0];
             const float p0 = fmaf(cf.x, ps[x], cf.y * dHz);
@@ -857,11 +880,11 @@ __device__ __forceinline__ void post_fused_block(const StepArgs& a, int rpb, lon
             st_stream<NT>(&ps[sz + x], p1);
             if (k != 0) {
                 ey = ey - a.S * fmaf(cf.z - 1.f, dHz, p0);
-                stf_nt<NT>(a.Eo, o + cs, ey);
+                stf_nt<NT>(fcomp(a.Eo, cs, 1), o, ey);
             }
             if (j != 0) {
                 ez = ez + a.S * fmaf(cf.z - 1.f, dHy, p1);
-                stf_nt<NT>(a.Eo, o + 2 * cs, ez);
+                stf_nt<NT>(fcomp(a.Eo, cs, 2), o, ez);
             }
         }
         se[0][tid] = ey;
@@ -879,8 +902,8 @@ __device__ __forceinline__ void post_fused_block(const StepArgs& a, int rpb, lon
     const float p1 = fmaf(cfh.x, ph1, cfh.y * dEy);
     st_stream<NT>(&pout[x], p0);
     st_stream<NT>(&pout[sz + x], p1);
-    stf_nt<NT>(a.Ho, o + cs, hy + a.S * fmaf(cfh.z - 1.f, dEz, p0));
-    stf_nt<NT>(a.Ho, o + 2 * cs, hz - a.S * fmaf(cfh.z - 1.f, dEy, p1));
+    stf_nt<NT>(fcomp(a.Ho, cs, 1), o, hy + a.S * fmaf(cfh.z - 1.f, dEz, p0));
+    stf_nt<NT>(fcomp(a.Ho, cs, 2), o, hz - a.S * fmaf(cfh.z - 1.f, dEy, p1));
 }
 
 template <bool NT>
@@ -1205,8 +1228,7 @@ __global__ __launch_bounds__(256) void watch_kernel(const float* E, unsigned cst
     for (int t = threadIdx.x; t < 3 * n; t += blockDim.x) {
         const int c = t / n, q = t - c * n;
         const int i = lo.x + q % dim.x, j = lo.y + (q / dim.x) % dim.y, k = lo.z + q / (dim.x * dim.y);
-        const float v = ldf(E, (unsigned)c * cstride +
-                                   (((unsigned)(k + 1) * nyp + (unsigned)(j + 1)) * nxp + (unsigned)i) * 4u);
+        const float v = ldf(fcomp(E, cstride, c), (((unsigned)(k + 1) * nyp + (unsigned)(j + 1)) * nxp + (unsigned)i) * 4u);
         if (!(fabsf(v) <= limit)) b = 1;  // not finite, or too large
     }
     if (b) atomicOr(&bad, 1);

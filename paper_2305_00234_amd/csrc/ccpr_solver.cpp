@@ -526,7 +526,7 @@ ccpr_status build_tf(ccpr_solver* s, const StepCold& C)
         x[t] = ct;
         TfEntry e;
         const long long cell = ((long long)(x[2] + 1) * s->nyp + (x[1] + 1)) * s->nxp + x[0];
-        e.off = (unsigned)((comp * s->npad + cell) * 4);
+        e.off = (unsigned long long)((comp * s->npad + cell) * 4);
         e.m = m;
         e.coef = (float)coef;
         e.uidx = (unsigned)(comp * s->ncell + ((long long)x[2] * ny + x[1]) * nx + x[0]);
@@ -1373,9 +1373,9 @@ ccpr_status ccpr_create(const ccpr_grid* g, ccpr_solver** out)
     s->nyp = (g->ny + CCPR_YPAD - 1) / CCPR_YPAD * CCPR_YPAD + 2;
     s->nzp = g->nz + 2;
     s->npad = (long long)s->nxp * s->nyp * s->nzp;
-    if (s->npad * 12 >= 0xffffffffLL) {
+    if (s->npad * 4 >= 0xffffffffLL) {
         delete s;
-        return fail(nullptr, CCPR_ENOTSUP, "grid too large for 32-bit offsets");
+        return fail(nullptr, CCPR_ENOTSUP, "grid too large: a padded field component exceeds 2^30 floats");
     }
     *out = s;
     return CCPR_OK;

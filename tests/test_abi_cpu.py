@@ -235,3 +235,15 @@ def test_watchdog_and_forward_serial_on_host(built):
             s.set_watchdog(every, limit)
         assert e.value.status == L.EINVAL
     s.close()
+
+
+def test_grid_size_limit_is_per_component(built):
+    """A field component is addressed with 32-bit byte offsets from its own
+    base: a grid whose padded component holds fewer than 2^30 floats is
+    accepted (1024 x 608 x 600 = 373 M cells, above the former limit of
+    three components under one 32-bit offset), a larger one is refused."""
+    s = L.Solver(1024, 608, 600, 10e-9)
+    s.close()
+    with pytest.raises(L.CcprError) as e:
+        L.Solver(1024, 1024, 1100, 10e-9)
+    assert e.value.status == L.ENOTSUP
