@@ -451,14 +451,17 @@ __device__ __forceinline__ void grid_tile(const StepArgs& a, const int L, float 
                 if (kk == 0) nyv = 0.f;
                 if (j == 0) nzv = 0.f;
                 if (i == 0) { nyv = 0.f; nzv = 0.f; }
-                if (xin) {
+                // design-box cells get their E^{n+1} from the aux kernel (which
+                // reads E^n and the drive): no store here
+                const bool des = (rf[r] & CCPR_ROW_DES) && (lf & CCPR_LANE_DES);
+                if (xin && !des) {
                     const unsigned o = poff(kk, r);
                     stf_nt<NT>(a.Eo, o, nxv);
                     stf_nt<NT>(fcomp(a.Eo, cs, 1), o, nyv);
                     stf_nt<NT>(fcomp(a.Eo, cs, 2), o, nzv);
                 }
                 // design / source cells: hand the drive to the aux kernel
-                if ((rf[r] & CCPR_ROW_DES) && (lf & CCPR_LANE_DES)) {
+                if (des) {
                     const long long v = box_index(i, j, kk, c.dlo, c.ddim);
                     a.drive[v] = dx_;
                     a.drive[c.nd + v] = dy_;
