@@ -260,6 +260,43 @@ def serving(args, n_requests=None, emit=True, sides=(64, 192), rate=None):
     return out
 
 
+def other_workload(name):
+    """One whole solve (forward + adjoint + gradient, setup included) of another
+    configuration, timed by the wall clock, with the step and grid-pass
+    durations from HIP events: Mcell-updates/s (the forward and adjoint runs'
+    cell updates; recomputed segments count as overhead) and the byte-model
+    fractions."""
+    import torch
+    from paper_2305_00234_amd.solver import solver_for
+    w = workload_by_name(name)
+    s = solver_for(w)
+    grad = torch.empty(s.gradient_size, dtype=torch.float64, device="cuda")
+    s.set_timing(True, every=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.forward(w.steps)
+    s.adjoint()
+    s.gradient(out=grad)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms, steps = s.timing()
+    grid_ms, passes = s.grid_timing()
+    info = s.info()
+    s.close()
+    del s, grad
+    torch.cuda.empty_cache()
+    step_s = step_ms / 1e3 / max(steps, 1)
+    pass_s = grid_ms / 1e3 / max(passes, 1)
+    return {"workload": w.name, "grid": list(w.shape), "leapfrog_steps_per_solve": w.steps,
+            "objective": w.objective, "solve_s": round(wall, 3),
+            "value": round(w.cells * 2 * w.steps / wall / 1e6, 1), "unit": "Mcell-updates/s",
+            "segments": info["segments"], "resident_segments": info["resident_segments"],
+            "avg_step_us": round(step_s * 1e6, 2),
+            "step_frac": round(step_model_bytes(w) / step_s / 1e9 / HBM_PEAK_GBS, 4),
+            "grid_pass_us": round(pass_s * 1e6, 2),
+            "grid_frac": round(grid_model_bytes(w) / pass_s / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def copy_rate_gbs(nbytes=1 << 30, reps=10):
     """Measured HBM ceiling: bytes read + written per second by a plain
     device-to-device copy of 1 GiB on torch's current stream (HIP events on
@@ -306,6 +343,9 @@ def main():
                     help="run only the serving trace, with this many requests")
     ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests of the serving record in the default run (0: skip it)")
+    ap.add_argument("--other-workloads",
+                    default="gold_gap_td_512x512x256,aniso_two_material_384,paper_broadband_gold",
+                    help="comma-separated configurations solved once each after the timed region ('' to skip)")
     ap.add_argument("--serving-small-requests", type=int, default=48,
                     help="requests of the small-grid serving record (sides U{24..64}, 200 requests/s; 0: skip)")
     ap.add_argument("--rate", type=float, default=20.0)
@@ -418,10 +458,15 @@ def main():
                  "achieved_GBs": round(sb / avg_step_s / 1e9, 1),
                  "frac": round(sb / avg_step_s / 1e9 / HBM_PEAK_GBS, 4), "steps": launches},
     }
-    if args.serving_requests > 0 or args.serving_small_requests > 0:
+    if args.serving_requests > 0 or args.serving_small_requests > 0 or args.other_workloads:
         s.close()
         del s, grad
         torch.cuda.empty_cache()
+    if args.other_workloads:
+        out["other_workloads"] = []
+        for name in args.other_workloads.split(","):
+            progress(f"one solve of {name}")
+            out["other_workloads"].append(other_workload(name))
     if args.serving_requests > 0:
         progress(f"serving trace ({args.serving_requests} requests)")
         sv = serving(args, n_requests=args.serving_requests, emit=False)
