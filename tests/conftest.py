@@ -19,3 +19,19 @@ def oracle_lib():
     if not os.path.exists(build.LIB):
         build.build()
     return build.LIB
+
+
+def pytest_terminal_summary(terminalreporter):
+    """List the errors the GPU tests measured (their say() lines), one per
+    line under the test that measured them."""
+    mod = sys.modules.get("tests.gpu_util")
+    rows = getattr(mod, "MEASURED", None) if mod else None
+    if not rows:
+        return
+    terminalreporter.section("measured errors (GPU vs oracle)")
+    last = None
+    for test, msg in rows:
+        if test != last:
+            terminalreporter.write_line(test or "(outside a test)")
+            last = test
+        terminalreporter.write_line("    " + msg)

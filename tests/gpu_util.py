@@ -2,6 +2,7 @@
 library (FP32, gfx950) and through the FP64 oracle, and compare."""
 from __future__ import annotations
 
+import os
 import sys
 
 import numpy as np
@@ -11,8 +12,17 @@ from paper_2305_00234_amd.inputs import Workload
 from tests.oracle_setup import oracle_from_workload
 
 
+# Every measurement a GPU test prints, with the test that printed it; the
+# session's terminal summary lists them (tests/conftest.py), so the errors
+# behind a pass are visible in a quiet run too.
+MEASURED: list[tuple[str, str]] = []
+
+
 def say(*a):
-    print(*a, flush=True)
+    msg = " ".join(str(x) for x in a)
+    test = os.environ.get("PYTEST_CURRENT_TEST", "").split(" ")[0]
+    MEASURED.append((test, msg))
+    print(msg, flush=True)
     sys.stdout.flush()
 
 
