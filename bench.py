@@ -66,6 +66,20 @@ def grid_model_bytes(w):
     return 48 * n + 32 * yz_layer_cells
 
 
+def design_update_bytes(w):
+    """Bytes of the design cells' CCPR update per step, averaged over a
+    forward and an adjoint step: per design voxel 16 B per pole pair and
+    component (complex J, read + write) and 4 B of density (12 B per cell for
+    a per-edge design), and the gradient record's 28 B (time-exact) or 48 B
+    (DFT mode).  Part of step_model_bytes; counted in the grid pass when the
+    grid pass runs the design update itself."""
+    nd = design_box_cells(w)
+    per_cell = 3 if w.rho_edges is not None else 1
+    pairs = sum(w.mat1[a].npairs + w.mat2[a].npairs for a in range(3))
+    record = 48 if w.gradient == "dft" else 28
+    return (16 * pairs + 4 * per_cell + record) * nd
+
+
 def design_box_cells(w):
     """Cells the design kernels run over: the design voxels, or for a per-edge
     design the box of N + 1 cells per axis that holds every design edge."""
@@ -89,14 +103,9 @@ def step_model_bytes(w):
     implementation stores one FP32 factor per component (12 B), below the
     model."""
     nx, ny, nz = w.shape
-    nd = design_box_cells(w)
-    per_cell = 3 if w.rho_edges is not None else 1
-    pairs = sum(w.mat1[a].npairs + w.mat2[a].npairs for a in range(3))
     p = w.npml
     layer_cells = 2 * p * (ny * nz + nx * nz + nx * ny) if p else 0
-    design = (16 * pairs + 4 * per_cell) * nd
-    record = 48 * nd if w.gradient == "dft" else 28 * nd
-    return 48 * nx * ny * nz + 32 * layer_cells + design + record
+    return 48 * nx * ny * nz + 32 * layer_cells + design_update_bytes(w)
 
 
 def traffic_from_profile(kernel_src_hash, workload):
@@ -294,7 +303,9 @@ def other_workload(name):
             "avg_step_us": round(step_s * 1e6, 2),
             "step_frac": round(step_model_bytes(w) / step_s / 1e9 / HBM_PEAK_GBS, 4),
             "grid_pass_us": round(pass_s * 1e6, 2),
-            "grid_frac": round(grid_model_bytes(w) / pass_s / 1e9 / HBM_PEAK_GBS, 4)}
+            "design_update_in_grid_pass": bool(info.get("design_fused")),
+            "grid_frac": round((grid_model_bytes(w) + (design_update_bytes(w) if info.get("design_fused") else 0))
+                               / pass_s / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def copy_rate_gbs(nbytes=1 << 30, reps=10):
@@ -337,6 +348,9 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=10,
                     help="forward + adjoint steps of the oracle sample (about 10 s on 16 cores at 320^3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--design-fusion", action="store_true",
+                    help="run the design cells' update inside the grid pass where the "
+                         "library can (default: the separate design pass)")
     ap.add_argument("--timing-every", type=int, default=10,
                     help="time every k-th grid pass with HIP events (fewer events in the stream)")
     ap.add_argument("--serving", type=int, default=0,
@@ -378,6 +392,8 @@ def main():
     s = solver_for(w)
     if args.tile_planes:
         s.set_tile_planes(args.tile_planes)
+    if args.design_fusion:
+        s.set_design_fusion(True)
     grad = torch.empty(s.gradient_size, dtype=torch.float64, device="cuda")
 
     def one_solve():
@@ -418,7 +434,9 @@ def main():
     value = updates / (total / args.steps) / 1e6
     avg_step_s = step_ms / 1e3 / max(launches, 1)
     avg_launch_s = grid_ms / 1e3 / max(grid_launches, 1)
-    alg = grid_model_bytes(w)
+    # with the design update inside the grid pass its bytes belong to the pass
+    fused = bool(info.get("design_fused"))
+    alg = grid_model_bytes(w) + (design_update_bytes(w) if fused else 0)
     achieved = alg / avg_launch_s / 1e9
     sb = step_model_bytes(w)
     traffic = traffic_from_profile(kernel_hash(), w.name)
@@ -449,7 +467,9 @@ def main():
         "objective": F,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "ccpr_step_kernel",
+                     "traffic": traffic,
+                     "kernel": "ccpr_step_kernel + ccpr_step_des_kernel" if fused else "ccpr_step_kernel",
+                     "design_update_in_grid_pass": fused,
                      "grid_model_bytes": int(alg),
                      "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": grid_launches,
                      "copy_GBs": round(copy_gbs, 1) if copy_gbs else None,

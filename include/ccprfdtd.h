@@ -361,6 +361,26 @@ ccpr_status ccpr_set_tile_planes(ccpr_solver* s, int planes);
  * it. */
 ccpr_status ccpr_set_tile_rows(ccpr_solver* s, int rows);
 
+/* Launch shape: on = 1 lets the grid pass finish the design cells itself --
+ * the CCPR pole-pair update, pole currents, gradient record or correlation
+ * and gap monitor of supplement Eqs. Maxwells2 a, b and Eq. Gradient_FDTD,
+ * computed from E^n and curl H still in registers -- in a launch of the
+ * tiles that own design cells after the CPML tiles; on = 0 (default) leaves
+ * them to the separate design pass, which is faster on the configurations
+ * measured (the fused launch runs its design cells plane by plane inside the
+ * z-march, at a quarter of the occupancy).  The grid pass does it only for
+ * one density per voxel with the time-exact gradient, nx <= 512, at most 8
+ * pole pairs per axis, no design cell in a tile that touches the y or z
+ * CPML, and grids large enough for the split grid pass; otherwise the
+ * separate pass runs whatever the setting.  Results do not depend on it
+ * (the arithmetic is the same).  Takes effect at the next forward or
+ * adjoint run.  CCPR_EINVAL unless on is 0 or 1. */
+ccpr_status ccpr_set_design_fusion(ccpr_solver* s, int on);
+
+/* *fused = 1 if the last planned run finished the design cells in the grid
+ * pass (see ccpr_set_design_fusion), else 0.  CCPR_EINVAL for NULL. */
+ccpr_status ccpr_get_design_fusion(const ccpr_solver* s, int* fused);
+
 /* ---- serving engine ----------------------------------------------------- */
 /* Continuous batching of whole solves (forward run, objective, adjoint run,
  * gradient: the path of ccpr_forward + ccpr_adjoint + ccpr_gradient) for many

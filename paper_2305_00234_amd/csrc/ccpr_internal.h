@@ -209,6 +209,9 @@ __host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, in
 // Launchers (ccpr_kernels.hip)
 // fused grid step over the tiles of a.tiles (pml: the CPML variant)
 int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream);
+// interior tiles that own design cells, with the design update fused in
+// (per-voxel design, time-exact gradient; rows 2, nxp <= 512, maxpairs <= 8)
+int ccpr_launch_grid_des(const StepArgs& a, int maxpairs, void* stream);
 // aux kernel over the nd cells of the design box (edge: per-edge design)
 int ccpr_launch_aux(const StepArgs& a, int maxpairs, long long nd, bool edge, void* stream);
 // before a step: x-CPML and TF/SF corrections of H^{n-1/2} (nxs x-layer cells,

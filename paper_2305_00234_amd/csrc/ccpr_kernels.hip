@@ -211,9 +211,18 @@ __device__ __forceinline__ float cpml(float d, float4 cf, float p, float* pout, 
     return fmaf(d, cf.z, q);
 }
 
+template <int PMAX, bool NT, bool DFT, bool EDGE, bool REG>
+__device__ __forceinline__ void design_cell(const StepArgs& a, const long long v, const int i, const int j,
+                                            const int kk, const unsigned o, const float* e_in,
+                                            const float* d_in);
+
 // Fused leapfrog step over the whole grid: vacuum update of H and E with the
 // y and z CPML.  For design and source cells the E drive S (curl H) is also
 // stored; ccpr_aux_kernel then finishes those cells and the TF/SF E faces.
+// DP >= 0 (interior tiles that own design cells, per-voxel designs, the
+// time-exact gradient): the design cells' CCPR update runs here instead, on
+// E^n and the drive still in registers (design_cell with at most DP pole
+// pairs per axis), and no drive is stored for them.
 // The x CPML and the TF/SF H faces are applied to H^{n-1/2} beforehand by
 // ccpr_pre_kernel, the x CPML of E^{n+1} afterwards by ccpr_post_kernel: the
 // x layers then cost no extra work inside the x-spanning workgroup.
@@ -225,7 +234,7 @@ __device__ __forceinline__ float cpml(float d, float4 cf, float p, float* pout, 
 // lists.  NT: nontemporal stores of the new fields (large states).
 // Tile L of a.tiles (the body of ccpr_step_kernel and of the batched grid
 // kernel); xe, xh: the workgroup's LDS words at the wave seams.
-template <int R, bool PML, bool NT>
+template <int R, bool PML, bool NT, int DP = -1>
 __device__ __forceinline__ void grid_tile(const StepArgs& a, const int L, float (*xe)[R + 1][16],
                                           float (*xh)[R][16])
 {
@@ -461,11 +470,18 @@ __device__ __forceinline__ void grid_tile(const StepArgs& a, const int L, float 
                     stf_nt<NT>(fcomp(a.Eo, cs, 2), o, nzv);
                 }
                 // design / source cells: hand the drive to the aux kernel
+                // (or, DP >= 0, finish the design cell here)
                 if (des) {
                     const long long v = box_index(i, j, kk, c.dlo, c.ddim);
-                    a.drive[v] = dx_;
-                    a.drive[c.nd + v] = dy_;
-                    a.drive[2 * c.nd + v] = dz_;
+                    if constexpr (DP >= 0) {
+                        const float ein[3] = {ex[r], ey[r], ez[r]};
+                        const float din[3] = {dx_, dy_, dz_};
+                        design_cell<DP, NT, false, false, true>(a, v, i, j, kk, poff(kk, r), ein, din);
+                    } else {
+                        a.drive[v] = dx_;
+                        a.drive[c.nd + v] = dy_;
+                        a.drive[2 * c.nd + v] = dz_;
+                    }
                 } else if ((rf[r] & CCPR_ROW_SRC) && (lf & CCPR_LANE_SRC)) {
                     float* d = a.drive + 3 * c.nd + (long long)box_index(i, j, kk, c.slo, c.sdim) * 3;
                     d[0] = dx_;
@@ -498,6 +514,20 @@ __global__ __launch_bounds__(R == 2 ? 1024 : 512) void ccpr_step_kernel(const St
     grid_tile<R, PML, NT>(a, xcd * per + (xcd < rem ? xcd : rem) + q, xe, xh);
 }
 
+// Interior tiles that own design cells, with the design update fused in
+// (R = 2; blockDim = nxp <= 512, which leaves the compiler up to 256 VGPRs).
+template <bool NT, int DP>
+__global__ __launch_bounds__(512) void ccpr_step_des_kernel(const StepArgs a)
+{
+    __shared__ float xe[2][3][16];
+    __shared__ float xh[2][2][16];
+    if (*a.halt) return;  // the divergence watchdog stopped the run
+    const int b = blockIdx.x;
+    const int per = a.nblk >> 3, rem = a.nblk & 7;
+    const int xcd = b & 7, q = b >> 3;
+    grid_tile<2, false, NT, DP>(a, xcd * per + (xcd < rem ? xcd : rem) + q, xe, xh);
+}
+
 // Finish the design voxels the fused step left to it, one thread per voxel:
 // CCPR pole-pair update of the three E edges from E^n and the stored drive
 // (minus a source current if the voxel is also a source cell), the gradient
@@ -526,22 +556,21 @@ __device__ __forceinline__ long long edge_index(const EdgeMap& m, int xi, int yi
     return m.eoff[C] + ((long long)zi * b[1] + yi) * b[0] + xi;
 }
 
-// Design-box cell t (x fastest): the body of ccpr_aux_kernel and of the
-// batched aux kernel.
-template <int PMAX, bool NT, bool DFT, bool EDGE>
-__device__ __forceinline__ void aux_cell(const StepArgs& a, const unsigned t)
+// Design-box cell v = (i, j, kk) (box index, x fastest; o: byte offset of
+// its field words): the CCPR update of its three E edges, the pole currents,
+// the gradient record / correlation or DFT accumulation, the source shadow
+// and the gap monitor.  REG = false: E^n and the drive S (curl H) come from
+// memory (ccpr_aux_kernel, after the grid pass stored the drive); REG = true:
+// from the caller's registers e_in, d_in (the grid pass with the design
+// update fused in).  The arithmetic is the same either way.
+template <int PMAX, bool NT, bool DFT, bool EDGE, bool REG>
+__device__ __forceinline__ void design_cell(const StepArgs& a, const long long v, const int i, const int j,
+                                            const int kk, const unsigned o, const float* e_in,
+                                            const float* d_in)
 {
     const StepCold& c = *a.cold;
     const unsigned cs = a.cstride;
     const int n = a.n;
-    if (t >= (unsigned)c.nd) return;
-    const long long v = t;
-    const unsigned dx = c.ddim[0], dy = c.ddim[1];
-    const unsigned row = t / dx;  // 32-bit: the design box holds < 2^31 voxels
-    const int i = c.dlo[0] + (int)(t - row * dx);
-    const int j = c.dlo[1] + (int)(row % dy);
-    const int kk = c.dlo[2] + (int)(row / dy);
-    const unsigned o = (((unsigned)(kk + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
     // every load first (the current stores alias the later loads otherwise)
     constexpr int PN = PMAX > 0 ? PMAX : 1;
     // design edges of this cell: per voxel all three share the voxel's
@@ -559,8 +588,14 @@ __device__ __forceinline__ void aux_cell(const StepArgs& a, const unsigned t)
     j_load<0, PMAX>(c, v, jrx, jix, onx);
     j_load<1, PMAX>(c, v, jry, jiy, ony);
     j_load<2, PMAX>(c, v, jrz, jiz, onz);
-    const float e0x = ldf(a.Ei, o), e0y = ldf(fcomp(a.Ei, cs, 1), o), e0z = ldf(fcomp(a.Ei, cs, 2), o);
-    float dx_ = a.drive[v], dy_ = a.drive[c.nd + v], dz_ = a.drive[2 * c.nd + v];
+    float e0x, e0y, e0z, dx_, dy_, dz_;
+    if constexpr (REG) {
+        e0x = e_in[0]; e0y = e_in[1]; e0z = e_in[2];
+        dx_ = d_in[0]; dy_ = d_in[1]; dz_ = d_in[2];
+    } else {
+        e0x = ldf(a.Ei, o); e0y = ldf(fcomp(a.Ei, cs, 1), o); e0z = ldf(fcomp(a.Ei, cs, 2), o);
+        dx_ = a.drive[v]; dy_ = a.drive[c.nd + v]; dz_ = a.drive[2 * c.nd + v];
+    }
     float rhox, rhoy, rhoz;
     if constexpr (EDGE) {
         rhox = onx ? c.rho[gx] : 0.f;
@@ -655,6 +690,22 @@ __device__ __forceinline__ void aux_cell(const StepArgs& a, const unsigned t)
         g[1] = nyv;
         g[2] = nzv;
     }
+}
+
+// Design-box cell t (x fastest): the body of ccpr_aux_kernel and of the
+// batched aux kernel.
+template <int PMAX, bool NT, bool DFT, bool EDGE>
+__device__ __forceinline__ void aux_cell(const StepArgs& a, const unsigned t)
+{
+    const StepCold& c = *a.cold;
+    if (t >= (unsigned)c.nd) return;
+    const unsigned dx = c.ddim[0], dy = c.ddim[1];
+    const unsigned row = t / dx;  // 32-bit: the design box holds < 2^31 voxels
+    const int i = c.dlo[0] + (int)(t - row * dx);
+    const int j = c.dlo[1] + (int)(row % dy);
+    const int kk = c.dlo[2] + (int)(row / dy);
+    const unsigned o = (((unsigned)(kk + 1) * a.nyp + (unsigned)(j + 1)) * a.nxp + (unsigned)i) * 4u;
+    design_cell<PMAX, NT, DFT, EDGE, false>(a, (long long)t, i, j, kk, o, nullptr, nullptr);
 }
 
 template <int PMAX, bool NT, bool DFT, bool EDGE>
@@ -1265,6 +1316,27 @@ int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream)
         if (a.stream_st) launch_grid_rows<4, true>(a, pml, grid, block, s);
         else launch_grid_rows<4, false>(a, pml, grid, block, s);
     }
+    return (int)hipGetLastError();
+}
+
+template <bool NT>
+void launch_des_nt(const StepArgs& a, int maxpairs, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (maxpairs <= 1) hipLaunchKernelGGL((ccpr_step_des_kernel<NT, 1>), grid, block, 0, s, a);
+    else if (maxpairs <= 2) hipLaunchKernelGGL((ccpr_step_des_kernel<NT, 2>), grid, block, 0, s, a);
+    else if (maxpairs <= 3) hipLaunchKernelGGL((ccpr_step_des_kernel<NT, 3>), grid, block, 0, s, a);
+    else if (maxpairs <= 4) hipLaunchKernelGGL((ccpr_step_des_kernel<NT, 4>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((ccpr_step_des_kernel<NT, 8>), grid, block, 0, s, a);
+}
+
+int ccpr_launch_grid_des(const StepArgs& a, int maxpairs, void* stream)
+{
+    if (a.nblk <= 0) return 0;
+    if (a.rows != 2 || a.nxp > 512 || maxpairs > 8) return (int)hipErrorInvalidValue;
+    dim3 grid(a.nblk), block(a.nxp);
+    hipStream_t s = (hipStream_t)stream;
+    if (a.stream_st) launch_des_nt<true>(a, maxpairs, grid, block, s);
+    else launch_des_nt<false>(a, maxpairs, grid, block, s);
     return (int)hipGetLastError();
 }
 

@@ -134,8 +134,13 @@ struct ccpr_solver {
     std::vector<int4> extra_host[2];
     std::vector<TfEntry> tf_host;
     std::vector<int2> zr_host;  // plane range of each logical z-chunk
-    std::vector<int2> tiles_host;  // interior tiles, then CPML tiles: (y-strip, logical z-chunk)
-    int ntiles_int = 0, ntiles_pml = 0;
+    // tiles (y-strip, logical z-chunk): interior tiles, then the interior
+    // tiles that own design cells when the grid pass finishes the design
+    // cells itself (des_on), then the CPML tiles
+    std::vector<int2> tiles_host;
+    int ntiles_int = 0, ntiles_des = 0, ntiles_pml = 0;
+    bool des_fuse = false;      // run the design update inside the grid pass where it can
+    bool des_on = false;        // the current plan does it (ntiles_des > 0)
     hipStream_t stream2 = nullptr;  // second stream: CPML tiles run beside the interior ones
     bool own_stream2 = false;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr, pdone_ev = nullptr;
@@ -731,9 +736,12 @@ void plan_chunks(ccpr_solver* s)
     for (int q = 0; q < n; ++q) s->zr_host[q] = phys[CCPR_CHUNK_SPREAD && n % 8 == 0 ? (q % 8) * (n / 8) + q / 8 : q];
     // tiles (y-strip of 'rows' rows, logical z-chunk) in logical order, split
     // by whether any of their H or E rows (halo row and plane included) lies
-    // in a y or z CPML layer
+    // in a y or z CPML layer; interior tiles whose own rows and planes hold
+    // design cells are marked
     const int ny = s->g.ny, R = s->rows, nys = (ny + R - 1) / R;
     std::vector<int2> in, pm;
+    std::vector<char> owns_design;
+    bool design_in_pml = false;
     for (int q = 0; q < n; ++q)
         for (int ys = 0; ys < nys; ++ys) {
             bool pml = false;
@@ -742,11 +750,37 @@ void plan_chunks(ccpr_solver* s)
                 const int k0 = s->zr_host[q].x - 1, k1 = s->zr_host[q].y;  // planes k0..k1-1
                 pml = j0 < np || j1 > ny - np || k0 < np || k1 > nz - np;
             }
-            (pml ? pm : in).push_back(make_int2(ys, q));
+            bool des = false;
+            if (s->has_design) {
+                const int ja = ys * R, jb = std::min(ys * R + R, ny);      // own rows ja..jb-1
+                const int ka = s->zr_host[q].x, kb = s->zr_host[q].y;      // own planes ka..kb-1
+                des = ja < s->dlo[1] + s->ddim[1] && jb > s->dlo[1] && ka < s->dlo[2] + s->ddim[2] &&
+                      kb > s->dlo[2];
+            }
+            if (pml) {
+                pm.push_back(make_int2(ys, q));
+                design_in_pml = design_in_pml || des;
+            } else {
+                in.push_back(make_int2(ys, q));
+                owns_design.push_back(des ? 1 : 0);
+            }
         }
-    s->ntiles_int = (int)in.size();
+    // When enabled (ccpr_set_design_fusion), the design update runs inside
+    // the grid pass (design tiles as a launch of their own after the CPML
+    // tiles) for per-voxel designs with the time-exact gradient when the pass
+    // is split in two launches, nx <= 512 and no CPML tile owns a design
+    // cell; otherwise in the aux pass.
+    const long long nds = std::count(owns_design.begin(), owns_design.end(), (char)1);
+    s->des_on = s->des_fuse && nds > 0 && !s->edge && !s->grad_dft && R == 2 && s->nxp <= 512 &&
+                s->maxpairs <= 8 && !design_in_pml && (long long)in.size() >= 1024 && pm.size() >= 128 &&
+                s->static_dev < 0 && !s->batched;
+    s->tiles_host.clear();
+    std::vector<int2> ds;
+    for (size_t t = 0; t < in.size(); ++t) (s->des_on && owns_design[t] ? ds : s->tiles_host).push_back(in[t]);
+    s->ntiles_int = (int)s->tiles_host.size();
+    s->ntiles_des = (int)ds.size();
     s->ntiles_pml = (int)pm.size();
-    s->tiles_host = in;
+    s->tiles_host.insert(s->tiles_host.end(), ds.begin(), ds.end());
     s->tiles_host.insert(s->tiles_host.end(), pm.begin(), pm.end());
 }
 
@@ -759,7 +793,8 @@ ccpr_status upload_cold(ccpr_solver* s, int st)
                           hipMemcpyHostToDevice, s->stream));
     // (no second stream on the static workspace: creating one is a resource
     // allocation its callers cannot make)
-    if (s->ntiles_pml > 0 && s->ntiles_int > 0 && !s->stream2 && s->static_dev < 0 && !s->batched) {
+    if (s->ntiles_pml > 0 && s->ntiles_int + s->ntiles_des > 0 && !s->stream2 && s->static_dev < 0 &&
+        !s->batched) {
         HIPCHK(hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking));
         s->own_stream2 = true;
     }
@@ -868,7 +903,7 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
         if (s->rec_pending) return fail(s, CCPR_ESTATE, "internal: a recorded step was not flushed");
         fuse = fuse && s->fuse_ok[st];
         s->rec.a = A;
-        s->rec.a.nblk = s->ntiles_int + s->ntiles_pml;
+        s->rec.a.nblk = s->ntiles_int + s->ntiles_des + s->ntiles_pml;
         s->rec.maxpairs = s->maxpairs;
         s->rec.nd = ndes;
         s->rec.fused = fuse ? 1 : 0;
@@ -891,33 +926,46 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
         HIPCHK(hipEventRecord(s->tev[s->tev_used], Ls));
     }
     // grid kernel: CPML tiles and interior tiles as two concurrent launches
-    // (both read step-n state only and write disjoint cells)
+    // (both read step-n state only and write disjoint cells); with the design
+    // update in the grid pass, the design tiles follow the CPML tiles
+    const int nint = s->ntiles_int, ndt = s->ntiles_des, npt = s->ntiles_pml;
     StepArgs Ap = A;
-    Ap.tiles = A.tiles + s->ntiles_int;
-    Ap.nblk = s->ntiles_pml;
+    Ap.tiles = A.tiles + nint + ndt;
+    Ap.nblk = npt;
     // the split pays for its fork only with enough tiles on both sides
-    const bool split = s->stream2 && s->ntiles_int >= 1024 && s->ntiles_pml >= 128;
+    const bool split = s->stream2 && nint + ndt >= 1024 && npt >= 128;
+    const bool fdes = split && ndt > 0;  // design cells finished in the grid pass
+    // interior tiles (with the design tiles unless those run fused)
+    StepArgs Ai = A;
+    Ai.nblk = fdes ? nint : nint + ndt;
     bool two = false;
     hipStream_t As = Ls;  // stream of aux and post
     if (e == 0) {
-        if (s->ntiles_int == 0 || (!split && s->ntiles_pml > 0)) {
+        if (nint + ndt == 0 || (!split && npt > 0)) {
             Ap.tiles = A.tiles;  // one launch over all tiles
-            Ap.nblk = s->ntiles_int + s->ntiles_pml;
+            Ap.nblk = nint + ndt + npt;
             e = ccpr_launch_grid(Ap, true, Ls);
-        } else if (s->ntiles_pml == 0) {
-            e = ccpr_launch_grid(A, false, Ls);
+        } else if (npt == 0) {
+            e = ccpr_launch_grid(Ai, false, Ls);
         } else {
             // the slower CPML tiles go first; the interior tiles fill the
             // device around them; aux waits for the CPML launch too (normally
             // long finished by then)
-            HIPCHK(hipEventRecord(s->fork_ev, Ls));
+            // (on a timed pass the timing events double as the fork and
+            // "CPML done" events, so timing adds one event record, not three)
+            hipEvent_t fork = tm ? s->tev[s->tev_used] : s->fork_ev;
+            hipEvent_t pdone = tm ? s->tev[s->tev_used + 1] : s->pdone_ev;
+            if (!tm) HIPCHK(hipEventRecord(fork, Ls));
+            StepArgs Ad = A;
+            Ad.tiles = A.tiles + nint;
+            Ad.nblk = ndt;
             e = ccpr_launch_grid(Ap, true, Ls);
-            if (tm) HIPCHK(hipEventRecord(s->tev[s->tev_used + 1], Ls));
-            HIPCHK(hipEventRecord(s->pdone_ev, Ls));
-            HIPCHK(hipStreamWaitEvent(Fs, s->fork_ev, 0));
-            if (e == 0) e = ccpr_launch_grid(A, false, Fs);
+            if (e == 0 && fdes) e = ccpr_launch_grid_des(Ad, s->maxpairs, Ls);
+            HIPCHK(hipEventRecord(pdone, Ls));
+            HIPCHK(hipStreamWaitEvent(Fs, fork, 0));
+            if (e == 0) e = ccpr_launch_grid(Ai, false, Fs);
             if (tm) HIPCHK(hipEventRecord(s->tev[s->tev_used + 2], Fs));
-            HIPCHK(hipStreamWaitEvent(Fs, s->pdone_ev, 0));
+            HIPCHK(hipStreamWaitEvent(Fs, pdone, 0));
             As = Fs;
             s->lead2 = !s->lead2;
             two = true;
@@ -934,7 +982,7 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
     }
     // aux and post touch disjoint cells but share the device better in
     // sequence than side by side (measured)
-    if (e == 0) e = ccpr_launch_aux(A, s->maxpairs, ndes, s->edge, As);
+    if (e == 0 && !fdes) e = ccpr_launch_aux(A, s->maxpairs, ndes, s->edge, As);
     fuse = fuse && s->fuse_ok[st];
     if (e == 0)
         e = fuse ? ccpr_launch_post_fused(A, nmisc, C.pw_on ? C.tf_nH : 0, As)
@@ -1950,6 +1998,21 @@ long long ccpr_forward_serial(const ccpr_solver* s)
 {
     if (!s || !s->have_forward || s->hist_stale) return -1;
     return s->fwd_serial;
+}
+
+ccpr_status ccpr_set_design_fusion(ccpr_solver* s, int on)
+{
+    if (!s) return CCPR_EINVAL;
+    if (on != 0 && on != 1) return fail(s, CCPR_EINVAL, "design fusion must be 0 or 1");
+    s->des_fuse = on != 0;
+    return CCPR_OK;
+}
+
+ccpr_status ccpr_get_design_fusion(const ccpr_solver* s, int* fused)
+{
+    if (!s || !fused) return CCPR_EINVAL;
+    *fused = s->des_on && s->ntiles_des > 0 ? 1 : 0;
+    return CCPR_OK;
 }
 
 ccpr_status ccpr_set_tile_rows(ccpr_solver* s, int rows)

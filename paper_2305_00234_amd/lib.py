@@ -36,7 +36,8 @@ EXPORTS = [
     "ccpr_bind_static_workspace", "ccpr_forward",
     "ccpr_adjoint", "ccpr_gradient", "ccpr_gap_spectrum", "ccpr_reset", "ccpr_step", "ccpr_get_field",
     "ccpr_step_count", "ccpr_set_timing", "ccpr_get_timing", "ccpr_get_grid_timing", "ccpr_get_info",
-    "ccpr_set_tile_planes", "ccpr_set_tile_rows", "ccpr_set_watchdog", "ccpr_forward_serial",
+    "ccpr_set_tile_planes", "ccpr_set_tile_rows", "ccpr_set_design_fusion", "ccpr_get_design_fusion",
+    "ccpr_set_watchdog", "ccpr_forward_serial",
     "ccpr_engine_create", "ccpr_engine_submit", "ccpr_engine_poll", "ccpr_engine_wait",
     "ccpr_engine_result", "ccpr_engine_release", "ccpr_engine_last_error", "ccpr_engine_destroy",
     "ccpr_engine_set_batching",
@@ -110,6 +111,8 @@ def load():
         "ccpr_get_info": (_i, [_p, _ip, _ip, _ip]),
         "ccpr_set_tile_planes": (_i, [_p, _i]),
         "ccpr_set_tile_rows": (_i, [_p, _i]),
+        "ccpr_set_design_fusion": (_i, [_p, _i]),
+        "ccpr_get_design_fusion": (_i, [_p, _ip]),
         "ccpr_set_watchdog": (_i, [_p, _i, _d]),
         "ccpr_forward_serial": (C.c_longlong, [_p]),
         "ccpr_engine_create": (_i, [_p, C.c_uint64, _i, _i, C.POINTER(_p)]),
@@ -551,14 +554,21 @@ class Solver:
                   "ccpr_get_info")
         r = C.c_int(0)
         self._chk(self._lib.ccpr_get_resident_segments(self._h, C.byref(r)), "ccpr_get_resident_segments")
+        f = C.c_int(0)
+        self._chk(self._lib.ccpr_get_design_fusion(self._h, C.byref(f)), "ccpr_get_design_fusion")
         return {"segments": a.value, "segment_steps": b.value, "tile_planes": c.value,
-                "resident_segments": r.value}
+                "resident_segments": r.value, "design_fused": f.value}
 
     def set_tile_planes(self, planes):
         self._chk(self._lib.ccpr_set_tile_planes(self._h, planes), "ccpr_set_tile_planes")
 
     def set_tile_rows(self, rows):
         self._chk(self._lib.ccpr_set_tile_rows(self._h, rows), "ccpr_set_tile_rows")
+
+    def set_design_fusion(self, on: bool):
+        """Let the grid pass finish the design cells itself where it can
+        (default), or always leave them to the separate design pass."""
+        self._chk(self._lib.ccpr_set_design_fusion(self._h, 1 if on else 0), "ccpr_set_design_fusion")
 
 
 class Engine:

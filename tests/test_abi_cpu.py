@@ -247,3 +247,16 @@ def test_grid_size_limit_is_per_component(built):
     with pytest.raises(L.CcprError) as e:
         L.Solver(1024, 1024, 1100, 10e-9)
     assert e.value.status == L.ENOTSUP
+
+
+def test_design_fusion_switch_on_host(built):
+    """ccpr_set_design_fusion takes 0 or 1; before a run nothing is planned,
+    so ccpr_get_design_fusion reads 0."""
+    s = L.Solver(24, 24, 24, 10e-9, npml=4)
+    s.set_design_fusion(True)
+    s.set_design_fusion(False)
+    f = L.C.c_int(7)
+    assert s._lib.ccpr_get_design_fusion(s._h, L.C.byref(f)) == 0 and f.value == 0
+    assert s._lib.ccpr_set_design_fusion(s._h, 2) == L.EINVAL
+    assert s._lib.ccpr_get_design_fusion(s._h, None) == L.EINVAL
+    s.close()

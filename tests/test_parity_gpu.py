@@ -18,7 +18,7 @@ import pytest
 from oracle.oracle import OBJ_TIME
 from paper_2305_00234_amd import inputs as I
 from tests.gpu_util import (field_errors, gpu_fields_after_steps, gpu_gradient,
-                            oracle_fields_after_steps, oracle_gradient, rel_l2, say)
+                            oracle_fields_after_steps, oracle_gradient, rel_l2, require_gpu, say)
 from tests.oracle_setup import oracle_from_workload
 
 pytestmark = pytest.mark.gpu
@@ -207,6 +207,52 @@ def test_tile_shape_invariance_bitwise():
     a = gpu_fields_after_steps(w, 80, tile_planes=3)
     b = gpu_fields_after_steps(w, 80, tile_planes=16)
     for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def _solve_with_design_fusion(w, on, checkpoint_every=None, resident=None):
+    from paper_2305_00234_amd.solver import configure
+    torch = require_gpu()
+    s = configure(w)
+    s.set_design_fusion(on)
+    if checkpoint_every:
+        s.set_checkpointing(checkpoint_every)
+    if resident:
+        s.set_resident_segments(resident)
+    s.bind_torch(w.steps)
+    F = s.forward(w.steps)
+    fwd = [s.field(c) for c in range(6)]
+    s.adjoint()
+    g = s.gradient()
+    adj = [s.field(c) for c in range(6)]
+    info = s.info()
+    torch.cuda.synchronize()
+    s.close()
+    return F, g, fwd, adj, info
+
+
+@pytest.mark.parametrize("case", ["dft", "time_checkpointed"])
+def test_design_update_in_grid_pass_bitwise(case):
+    """The design cells' CCPR update inside the grid pass (a launch of the
+    design tiles, E^n and curl H taken from registers) against the separate
+    design pass: objective, gradient and the forward and adjoint end states
+    bit for bit -- a single-frequency objective, and a time-domain one with
+    the adjoint recomputing two of three segments."""
+    if case == "dft":
+        w = I.gold_gap(n=(256, 192, 200), design=(96, 64, 48), steps=150, seed=3, name="fuse_dft")
+        ck = res = None
+    else:
+        w = I.gold_gap(n=(200, 130, 150), design=(61, 37, 29), steps=120, seed=5, objective="time",
+                       name="fuse_time")
+        ck, res = 40, 1
+    a = _solve_with_design_fusion(w, False, ck, res)
+    b = _solve_with_design_fusion(w, True, ck, res)
+    say(case, "design update in the grid pass:", b[4]["design_fused"], "separate:", a[4]["design_fused"],
+        "F", a[0], b[0])
+    assert a[4]["design_fused"] == 0 and b[4]["design_fused"] == 1
+    assert a[0] == b[0]
+    assert np.array_equal(a[1], b[1])
+    for x, y in zip(a[2] + a[3], b[2] + b[3]):
         assert np.array_equal(x, y)
 
 
