@@ -341,6 +341,7 @@ def main():
     ap.add_argument("--solve-steps", type=int, default=None,
                     help="leapfrog steps per solve (default: the workload's)")
     ap.add_argument("--tile-planes", type=int, default=None)
+    ap.add_argument("--tile-rows", type=int, default=None)
     ap.add_argument("--per-edge", action="store_true",
                     help="one density per E edge (seeded uniform) instead of per voxel")
     ap.add_argument("--gradient", choices=["time", "dft"], default="time",
@@ -392,6 +393,8 @@ def main():
     s = solver_for(w)
     if args.tile_planes:
         s.set_tile_planes(args.tile_planes)
+    if args.tile_rows:
+        s.set_tile_rows(args.tile_rows)
     if args.design_fusion:
         s.set_design_fusion(True)
     grad = torch.empty(s.gradient_size, dtype=torch.float64, device="cuda")
