@@ -135,3 +135,31 @@ def test_sampled_grid_pass_timing():
     say("timing: loop ms", ms, "steps", loops, "sampled passes", passes, "all passes", passes1)
     assert loops == 2 * w.steps and passes == 2 * w.steps // 10 and passes1 == w.steps
     assert 0 < gms / passes < float("inf") and 0 < gms1 / passes1 < float("inf")
+
+
+def test_timed_split_passes_give_the_same_results():
+    """With timing on, a timed split grid pass uses its timing events as the
+    fork and join events of its two concurrent launches: every pass timed
+    gives bitwise the objective and gradient of an untimed solve (the launch
+    order constraints are the same)."""
+    require_gpu()
+    from paper_2305_00234_amd.solver import configure
+    w = I.gold_gap(n=(256, 192, 200), design=(96, 64, 48), steps=120, seed=3, name="timed_split")
+
+    def solve(every):
+        s = configure(w)
+        s.bind_torch(w.steps)
+        if every:
+            s.set_timing(True, every=every)
+        F = s.forward(w.steps)
+        s.adjoint()
+        g = s.gradient()
+        passes = s.grid_timing()[1] if every else 0
+        s.close()
+        return F, g, passes
+
+    F0, g0, _ = solve(0)
+    F1, g1, p1 = solve(1)
+    say("timed split passes", p1, "F", F0, F1)
+    assert p1 == 2 * w.steps
+    assert F0 == F1 and np.array_equal(g0, g1)
