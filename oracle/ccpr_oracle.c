@@ -629,6 +629,15 @@ static void step_once(or_sim* s, double* T)
 
 void or_set_fp32_storage(or_sim* s, int on) { s->fp32_store = on != 0; }
 
+int or_get_pml_coef(const or_sim* s, int axis, int half, int q, double* b, double* a, double* kappa)
+{
+    if (!s || axis < 0 || axis > 2 || q < 0 || q >= s->n[axis] || !b || !a || !kappa) return -1;
+    *b = half ? s->bH[axis][q] : s->bE[axis][q];
+    *a = half ? s->aH[axis][q] : s->aE[axis][q];
+    *kappa = half ? s->kH[axis][q] : s->kE[axis][q];
+    return 0;
+}
+
 void or_run(or_sim* s, int nsteps)
 {
     for (int n = 0; n < nsteps; ++n) step_once(s, NULL);

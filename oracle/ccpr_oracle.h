@@ -149,6 +149,12 @@ int or_num_threads(void);
  * implementation of the same recurrence. */
 void or_set_fp32_storage(or_sim* s, int on);
 
+/* CPML recursive-convolution coefficients along axis (0..2) at integer node q
+ * (half = 0) or at q + 1/2 (half = 1), 0 <= q < n[axis]: psi' = b psi + a d,
+ * derivative scaled by 1/kappa.  For the pins only.  Returns 0, or -1 for bad
+ * arguments. */
+int or_get_pml_coef(const or_sim* s, int axis, int half, int q, double* b, double* a, double* kappa);
+
 #ifdef __cplusplus
 }
 #endif

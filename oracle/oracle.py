@@ -63,6 +63,8 @@ def _lib():
         lib.or_eps_ccpr.argtypes = [_p, _i, _d, _d, _d, _dp, _dp]
         lib.or_num_threads.restype = _i
         lib.or_set_fp32_storage.argtypes = [_p, _i]
+        lib.or_get_pml_coef.restype = _i
+        lib.or_get_pml_coef.argtypes = [_p, _i, _i, _i, _dp, _dp, _dp]
         _LIB = lib
     return _LIB
 
@@ -209,6 +211,18 @@ class OracleSim:
         """Diagnostic: round every stored state word to FP32 after each update
         (FP64 arithmetic), to measure the floor FP32 storage alone sets."""
         _lib().or_set_fp32_storage(self._h, 1 if on else 0)
+
+    def pml_coefficients(self, axis, half):
+        """(b, a, kappa) arrays of the CPML recursion along axis at the
+        integer nodes (half = False) or at q + 1/2 (half = True)."""
+        n = self.shape[2 - axis]
+        out = np.empty((3, n))
+        for q in range(n):
+            b, a, k = C.c_double(), C.c_double(), C.c_double()
+            self._chk(_lib().or_get_pml_coef(self._h, axis, 1 if half else 0, q, C.byref(b), C.byref(a),
+                                             C.byref(k)), "pml coefficients")
+            out[:, q] = (b.value, a.value, k.value)
+        return out[0], out[1], out[2]
 
     def forward_end_fields(self):
         """The six fields at the end of the forward run inside the last

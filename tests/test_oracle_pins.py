@@ -188,6 +188,178 @@ def test_p4_energy_invariant_lossless_cavity():
     assert np.max(np.abs(W - W[0])) <= 1e-11 * W[0]
 
 
+def _stretch_lengths(N, npml, m, kmax):
+    """Cell lengths (in units of dx) of the coordinate stretch that a lossless
+    CPML (sigma = 0, alpha = 0) applies along one axis: kappa graded as
+    1 + (kmax - 1) xi^m, xi the depth into a layer of npml cells over npml,
+    at the integer nodes q (dual lengths D) and at q + 1/2 (primal lengths L)."""
+    def kappa(pos):
+        d = np.maximum(npml - pos, pos - (N - npml))
+        xi = np.clip(d, 0.0, npml) / npml
+        return 1.0 + (kmax - 1.0) * xi ** m
+    q = np.arange(N, dtype=np.float64)
+    return kappa(q), kappa(q + 0.5)
+
+
+def test_p4_energy_invariant_kappa_stretched_cpml():
+    """A CPML with sigma = 0 and alpha = 0 leaves only the kappa grading, a
+    real, lossless stretch of the coordinates: the Yee scheme on cells of
+    primal lengths L = kappa(q + 1/2) dx and dual lengths D = kappa(q) dx.
+    That scheme conserves W = eps0/2 sum V_E E.E + mu0/2 sum V_H H+.H- with
+    E_c weighted by L_c D_d1 D_d2 and H_c by D_c L_d1 L_d2 (summation by parts
+    against the PEC walls), so once the source is off W is constant.  A kappa
+    at the wrong staggered position, on the wrong derivative, multiplied
+    instead of divided, or graded differently, breaks the invariant."""
+    n = (14, 13, 12)
+    npml, m, kmax = 4, 3.0, 5.0
+    sim = OracleSim(n[0], n[1], n[2], 5e-9, 0.5, npml, m, kmax, 0.0, 0.0)
+    t = (np.arange(30) + 0.5) * sim.dt
+    sim.set_dipole((7, 6, 6), 2, I.gaussian_sine(t, 400e-9, 0.2e-15, 0.25e-15, amp=1e9))
+    sim.run(40)
+    D, L = zip(*(_stretch_lengths(n[a], npml, m, kmax) for a in range(3)))
+
+    def vol(lengths):  # (x, y, z) length arrays -> (z, y, x) cell volumes
+        return lengths[2][:, None, None] * lengths[1][None, :, None] * lengths[0][None, None, :]
+    VE = [vol([L[0], D[1], D[2]]), vol([D[0], L[1], D[2]]), vol([D[0], D[1], L[2]])]
+    VH = [vol([D[0], L[1], L[2]]), vol([L[0], D[1], L[2]]), vol([L[0], L[1], D[2]])]
+    W = []
+    for _ in range(300):
+        E = [sim.field(c) for c in range(3)]
+        Hm = [sim.field(3 + c) for c in range(3)]
+        sim.run(1)
+        Hp = [sim.field(3 + c) for c in range(3)]
+        W.append(0.5 * EPS0 * sum(np.sum(VE[c] * E[c] ** 2) for c in range(3)) +
+                 0.5 * MU0 * sum(np.sum(VH[c] * Hm[c] * Hp[c]) for c in range(3)))
+    W = np.array(W)
+    assert W[0] > 0
+    assert np.max(np.abs(W - W[0])) <= 1e-11 * W[0]
+    # the uniform-grid weights do not make it an invariant: the stretch is real
+    W1 = []
+    sim2 = OracleSim(n[0], n[1], n[2], 5e-9, 0.5, npml, m, kmax, 0.0, 0.0)
+    sim2.set_dipole((7, 6, 6), 2, I.gaussian_sine(t, 400e-9, 0.2e-15, 0.25e-15, amp=1e9))
+    sim2.run(40)
+    for _ in range(300):
+        E = [sim2.field(c) for c in range(3)]
+        Hm = [sim2.field(3 + c) for c in range(3)]
+        sim2.run(1)
+        Hp = [sim2.field(3 + c) for c in range(3)]
+        W1.append(0.5 * EPS0 * sum(np.sum(E[c] ** 2) for c in range(3)) +
+                  0.5 * MU0 * sum(np.sum(Hm[c] * Hp[c]) for c in range(3)))
+    W1 = np.array(W1)
+    assert np.max(np.abs(W1 - W1[0])) > 1e-6 * W1[0]
+
+
+def test_p14_cpml_static_limit_is_a_stretched_electrostatic_field():
+    """The static limit of the CFS-CPML recursion.  In steady state the
+    memory of a constant derivative d settles at psi = a d / (1 - b), so every
+    derivative along an axis is scaled by 1/kappa + a/(1 - b), which the
+    CFS stretch s(w) = kappa + sigma/(alpha + j w eps0) fixes at w = 0:
+    1/s0 = alpha / (sigma + kappa alpha), at each field's staggered position.
+    A current pulse with a nonzero time integral leaves a static charge pair,
+    so once the radiation has died out E must be the discrete electrostatic
+    field of that pair on the grid stretched by s0: E = -grad phi with
+    eps0 div grad phi = dt div S (S = the summed source on its edge), the
+    gradient along c at half-integer positions, the divergence at the nodes,
+    phi = 0 on the PEC walls.  Checked against a sparse solve of that Poisson
+    problem.  A wrong sigma, kappa or alpha profile, a wrong a or b, or a
+    half-cell shift of the CPML coefficients changes the field."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    N, npml, m, kmax, amax, dx = 16, 4, 3.0, 3.0, 2e4, 5e-9
+    sim = OracleSim(N, N, N, dx, 0.5, npml, m, kmax, amax, 1.0)
+    dt = sim.dt
+    t = (np.arange(60) + 0.5) * dt
+    wave = 1e9 * np.exp(-((t - 30 * dt) / (8 * dt)) ** 2)   # nonzero time integral
+    src = (7, 6, 6)
+    sim.set_dipole(src, 2, wave)
+    sim.run(8000)
+
+    # the static stretch 1/s0 of the CFS profile (sigma_max = 0.8 (m + 1) / (eta0 dx))
+    def inv_s0(pos):
+        xi = np.clip(np.maximum(npml - pos, pos - (N - npml)), 0.0, npml) / npml
+        smax = 0.8 * (m + 1.0) / (math.sqrt(MU0 / EPS0) * dx)
+        sig, kap, al = smax * xi ** m, 1.0 + (kmax - 1.0) * xi ** m, amax * (1.0 - xi)
+        return al / (sig + kap * al)
+    q = np.arange(N + 1, dtype=np.float64)
+    h, g = inv_s0(q), inv_s0(q + 0.5)   # nodes; edges (half-integer)
+    n1 = N - 1                           # unknown nodes 1 .. N-1 per axis
+
+    def nid(p):
+        return ((p[2] - 1) * n1 + (p[1] - 1)) * n1 + (p[0] - 1)
+    rows, cols, vals = [], [], []
+    for p in np.ndindex(n1, n1, n1):
+        p = (p[0] + 1, p[1] + 1, p[2] + 1)
+        r, diag = nid(p), 0.0
+        for c in range(3):
+            for sgn in (1, -1):
+                w = h[p[c]] * g[p[c] if sgn > 0 else p[c] - 1] / dx ** 2
+                diag -= w
+                nb = list(p)
+                nb[c] += sgn
+                if 1 <= nb[c] <= N - 1:
+                    rows.append(r)
+                    cols.append(nid(nb))
+                    vals.append(w)
+        rows.append(r)
+        cols.append(r)
+        vals.append(diag)
+    A = sp.csc_matrix((vals, (rows, cols)), shape=(n1 ** 3, n1 ** 3))
+    b = np.zeros(n1 ** 3)
+    Ssum = dt / EPS0 * wave.sum()
+    b[nid(src)] += Ssum * h[src[2]] / dx
+    b[nid((src[0], src[1], src[2] + 1))] -= Ssum * h[src[2] + 1] / dx
+    phi = np.zeros((N + 1, N + 1, N + 1))   # [i, j, k]; zero on the walls
+    phi[1:N, 1:N, 1:N] = spl.spsolve(A, b).reshape(n1, n1, n1).transpose(2, 1, 0)
+    num = den = 0.0
+    for c in range(3):
+        sl = [slice(0, N)] * 3
+        up = [slice(0, N)] * 3
+        up[c] = slice(1, N + 1)
+        shape = [1, 1, 1]
+        shape[c] = N
+        Ec = -(phi[tuple(up)] - phi[tuple(sl)]) * g[:N].reshape(shape) / dx   # [i, j, k]
+        Ec = Ec.transpose(2, 1, 0)                                           # (z, y, x)
+        num += np.sum((sim.field(c) - Ec) ** 2)
+        den += np.sum(Ec ** 2)
+    err = math.sqrt(num / den)
+    assert den > 0 and err <= 1e-9, err
+
+
+def test_p14_cpml_recursion_integrates_the_cfs_kernel_exactly():
+    """The CFS stretch s(w) = kappa + sigma/(alpha + j w eps0) turns a
+    derivative into d/kappa + zeta * d with the causal kernel
+    zeta(t) = -sigma/(eps0 kappa^2) exp(-(sigma/kappa + alpha) t/eps0).  The
+    recursion psi^n = b psi^{n-1} + a d^n convolves d with the taps a b^m, and
+    for a derivative held over each step these taps must be the kernel's
+    integrals over [m dt, (m+1) dt]: checked for m = 0, 1, 10, 100 at every
+    staggered position of a graded CPML (which also fixes the decay per step
+    b, a quantity the static-limit pin does not see)."""
+    n, npml, m, kmax, amax, dx = 20, 6, 3.0, 4.0, 0.3, 5e-9
+    sim = OracleSim(n, n, n, dx, 0.5, npml, m, kmax, amax, 1.2)
+    dt = sim.dt
+    smax = 1.2 * 0.8 * (m + 1.0) / (math.sqrt(MU0 / EPS0) * dx)
+    checked = 0
+    for axis in range(3):
+        for half in (False, True):
+            b, a, kap = sim.pml_coefficients(axis, half)
+            pos = np.arange(n) + (0.5 if half else 0.0)
+            xi = np.clip(np.maximum(npml - pos, pos - (n - npml)), 0.0, npml) / npml
+            sig, k_ref, al = smax * xi ** m, 1.0 + (kmax - 1.0) * xi ** m, amax * (1.0 - xi)
+            assert np.allclose(kap, k_ref, rtol=1e-14, atol=0)
+            rate = (sig / k_ref + al) / EPS0
+            for q in range(n):
+                if sig[q] == 0.0:
+                    assert a[q] == 0.0
+                    continue
+                for mm in (0, 1, 10, 100):
+                    tap = a[q] * b[q] ** mm
+                    integral = -sig[q] / (EPS0 * k_ref[q] ** 2) * (
+                        math.exp(-rate[q] * mm * dt) - math.exp(-rate[q] * (mm + 1) * dt)) / rate[q]
+                    assert tap == pytest.approx(integral, rel=1e-10, abs=0), (axis, half, q, mm)
+                checked += 1
+    assert checked >= 3 * 2 * 2 * (npml - 1)
+
+
 # --------------------------------------------------------------------- P6
 def test_p6_reciprocity_with_dispersive_inclusion():
     """Reciprocal medium: E_x at B driven by J_x at A equals E_x at A driven by
