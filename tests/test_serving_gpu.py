@@ -186,3 +186,48 @@ def test_batched_small_solves_two_widths_equal_alone():
         say("request", k, ws[k].name, ws[k].objective, "F", F, Fb, Fp)
         assert Fb == F and Fp == F
         assert _same(gb, g) and _same(gp, g)
+
+
+def test_diverging_request_fails_alone():
+    """A request whose material is not passive (static susceptibility < 0)
+    diverges; the watchdog stops its run and the engine reports that job
+    FAILED with the reason, while the requests beside it -- in the same
+    batched launches, or on streams of their own -- finish with bitwise the
+    results they have alone."""
+    import math
+    torch = require_gpu()
+    from paper_2305_00234_amd.lib import EDEVICE, JOB_DONE, JOB_FAILED, CcprError, Engine
+    from paper_2305_00234_amd.solver import configure
+    good = [I.serving_workload(side, p, steps, seed=950 + k, npml=npml)
+            for k, (side, p, steps, npml) in enumerate([(24, 1, 200, 4), (28, 2, 200, 4),
+                                                        (40, 1, 300, 6), (66, 3, 160, 4)])]
+    bad = I.drude_dipole_32(steps=2000, n=24, npml=0, gamma=0.0)
+    bad.design_lo = (8, 8, 8)
+    bad.rho = np.ones((8, 8, 8), np.float32)
+    bad.gap_lo, bad.gap_dims = (11, 11, 11), (2, 2, 2)
+    bad.dipole_cell = (6, 12, 12)
+    bad.mat2 = (I.lorentz(1.0, -3.0, 2 * math.pi * 299792458.0 / 500e-9, 1e13),) * 3
+    alone = [_alone(w) for w in good]
+    torch.cuda.synchronize()
+    for batching in (True, False):
+        solvers = [configure(w) for w in good]
+        sb = configure(bad)
+        sb.set_watchdog(64)
+        arena = sum(s.workspace_size(w.steps) for s, w in zip(solvers, good)) + sb.workspace_size(bad.steps)
+        eng = Engine(arena + (64 << 20), max_active=8, chunk_steps=16, batching=batching)
+        tb = eng.submit(sb, bad.steps)
+        tickets = [eng.submit(s, w.steps) for s, w in zip(solvers, good)]
+        assert eng.wait(tb) == JOB_FAILED
+        with pytest.raises(CcprError) as e:
+            eng.result(tb)
+        assert e.value.status == EDEVICE and "diverged" in str(e.value)
+        for k, t in enumerate(tickets):
+            assert eng.wait(t) == JOB_DONE
+            F, g, _ = eng.result(t)
+            assert F == alone[k][0] and np.array_equal(g, alone[k][1]), (batching, k)
+            eng.release(t)
+        say("batching", batching, "failed request:", e.value)
+        eng.release(tb)
+        eng.close()
+        for s in solvers + [sb]:
+            s.close()
