@@ -20,9 +20,17 @@
 //  - ccpr_post_kernel: the x-CPML correction of E^{n+1}, the source and gap
 //    cells outside the design and the TF/SF E faces; ccpr_post_fused_kernel
 //    does the same and also the next step's pre work when that step follows
-//    at once.
+//    at once;
+//  - watch_kernel (every few steps when the divergence watchdog is on):
+//    checks the gap box and sets a halt word that every step kernel reads
+//    first.
 // Keeping the dispersive work and the x layers out of the grid kernel keeps
 // its loop at the register and instruction budget of a plain Yee update.
+// Options: ccpr_step_des_kernel runs the interior tiles that own design cells
+// with the aux kernel's update fused into their z-march (slower on the
+// workloads measured, off by default); the ccpr_batch_*_kernel launches run
+// the same bodies for up to CCPR_BATCH_MAX solves of one padded x width
+// (serving engine).
 //
 // Grid kernel decomposition (memory-bound stencil, no MFMA):
 //  - a workgroup spans the whole x extent (blockDim = nx rounded up to 64),
