@@ -144,7 +144,7 @@ def test_timed_split_passes_give_the_same_results():
     order constraints are the same)."""
     require_gpu()
     from paper_2305_00234_amd.solver import configure
-    w = I.gold_gap(n=(256, 192, 200), design=(96, 64, 48), steps=120, seed=3, name="timed_split")
+    w = I.gold_gap(n=(256, 192, 200), design=(96, 64, 48), steps=1200, seed=3, name="timed_split")
 
     def solve(every):
         s = configure(w)
@@ -162,4 +162,4 @@ def test_timed_split_passes_give_the_same_results():
     F1, g1, p1 = solve(1)
     say("timed split passes", p1, "F", F0, F1)
     assert p1 == 2 * w.steps
-    assert F0 == F1 and np.array_equal(g0, g1)
+    assert F0 > 0 and F0 == F1 and np.array_equal(g0, g1)
