@@ -208,7 +208,8 @@ __host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, in
 
 // Launchers (ccpr_kernels.hip)
 // fused grid step over the tiles of a.tiles (pml: the CPML variant)
-int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream);
+int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream, void* start_event = nullptr,
+                     void* stop_event = nullptr);
 // interior tiles that own design cells, with the design update fused in
 // (per-voxel design, time-exact gradient; rows 2, nxp <= 512, maxpairs <= 8)
 int ccpr_launch_grid_des(const StepArgs& a, int maxpairs, void* stream);
@@ -223,7 +224,8 @@ int ccpr_launch_post(const StepArgs& a, long long nxs, long long nmisc, void* st
 // after the aux kernel when the next step follows at once: the post work of
 // step n and the pre work of step n+1 (ntfh TF/SF H words) in one launch
 // (2 npml <= 256)
-int ccpr_launch_post_fused(const StepArgs& a, long long nmisc, long long ntfh, void* stream);
+int ccpr_launch_post_fused(const StepArgs& a, long long nmisc, long long ntfh, void* stream,
+                           void* stop_event = nullptr);
 // the recorded steps st[0..k) (1 <= k <= CCPR_BATCH_MAX, same nxp, 2 rows per
 // thread, 2 npml <= 256) as one batched grid, aux and post launch each
 int ccpr_launch_batch(const BatchStep* st, int k, void* stream);

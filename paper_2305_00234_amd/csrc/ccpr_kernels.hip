@@ -45,6 +45,7 @@
 //    owner and are updated in place;
 //  - workgroups are numbered so that each XCD gets a contiguous run of
 //    tiles: neighbouring y-strips share their halo rows in the same L2.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1306,23 +1307,36 @@ int grid_for(long long n) { long long g = (n + 255) / 256; return (int)(g < 4096
 }  // namespace
 
 template <int R, bool NT>
-void launch_grid_rows(const StepArgs& a, bool pml, dim3 grid, dim3 block, hipStream_t s)
+void launch_grid_rows(const StepArgs& a, bool pml, dim3 grid, dim3 block, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1)
 {
-    if (pml) hipLaunchKernelGGL((ccpr_step_kernel<R, true, NT>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((ccpr_step_kernel<R, false, NT>), grid, block, 0, s, a);
+    // with events, they are recorded by the dispatch itself (no separate
+    // marker between this kernel and its neighbours on the stream)
+    if (pml) {
+        if (ev0 || ev1) hipExtLaunchKernelGGL((ccpr_step_kernel<R, true, NT>), grid, block, 0, s, ev0, ev1, 0, a);
+        else hipLaunchKernelGGL((ccpr_step_kernel<R, true, NT>), grid, block, 0, s, a);
+    } else {
+        if (ev0 || ev1) hipExtLaunchKernelGGL((ccpr_step_kernel<R, false, NT>), grid, block, 0, s, ev0, ev1, 0, a);
+        else hipLaunchKernelGGL((ccpr_step_kernel<R, false, NT>), grid, block, 0, s, a);
+    }
 }
 
-int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream)
+int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream, void* start_event, void* stop_event)
 {
-    if (a.nblk <= 0) return 0;
-    dim3 grid(a.nblk), block(a.nxp);
+    hipEvent_t ev0 = (hipEvent_t)start_event, ev1 = (hipEvent_t)stop_event;
     hipStream_t s = (hipStream_t)stream;
+    if (a.nblk <= 0) {
+        if (ev0) (void)hipEventRecord(ev0, s);
+        if (ev1) (void)hipEventRecord(ev1, s);
+        return (int)hipGetLastError();
+    }
+    dim3 grid(a.nblk), block(a.nxp);
     if (a.rows == 2) {
-        if (a.stream_st) launch_grid_rows<2, true>(a, pml, grid, block, s);
-        else launch_grid_rows<2, false>(a, pml, grid, block, s);
+        if (a.stream_st) launch_grid_rows<2, true>(a, pml, grid, block, s, ev0, ev1);
+        else launch_grid_rows<2, false>(a, pml, grid, block, s, ev0, ev1);
     } else {
-        if (a.stream_st) launch_grid_rows<4, true>(a, pml, grid, block, s);
-        else launch_grid_rows<4, false>(a, pml, grid, block, s);
+        if (a.stream_st) launch_grid_rows<4, true>(a, pml, grid, block, s, ev0, ev1);
+        else launch_grid_rows<4, false>(a, pml, grid, block, s, ev0, ev1);
     }
     return (int)hipGetLastError();
 }
@@ -1460,7 +1474,7 @@ int ccpr_launch_post(const StepArgs& a, long long nxs, long long nmisc, void* st
     return (int)hipGetLastError();
 }
 
-int ccpr_launch_post_fused(const StepArgs& a, long long nmisc, long long ntfh, void* stream)
+int ccpr_launch_post_fused(const StepArgs& a, long long nmisc, long long ntfh, void* stream, void* stop_event)
 {
     const int np2 = 2 * a.npml;
     if (np2 > 256) return (int)hipErrorInvalidValue;
@@ -1468,13 +1482,23 @@ int ccpr_launch_post_fused(const StepArgs& a, long long nmisc, long long ntfh, v
     const long long nrows = np2 > 0 ? (long long)a.ny * a.nz : 0;
     const long long nbx = (nrows + rpb - 1) / rpb;
     const long long nb = nbx + (nmisc + ntfh + 255) / 256;
-    if (nb <= 0) return 0;
-    if (a.stream_st)
-        hipLaunchKernelGGL(ccpr_post_fused_kernel<true>, dim3((unsigned)nb), dim3(256), 0, (hipStream_t)stream, a,
-                           rpb, nbx, nmisc, ntfh);
-    else
-        hipLaunchKernelGGL(ccpr_post_fused_kernel<false>, dim3((unsigned)nb), dim3(256), 0, (hipStream_t)stream, a,
-                           rpb, nbx, nmisc, ntfh);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev = (hipEvent_t)stop_event;
+    if (nb <= 0) {
+        if (ev) (void)hipEventRecord(ev, s);
+        return (int)hipGetLastError();
+    }
+    if (a.stream_st) {
+        if (ev) hipExtLaunchKernelGGL(ccpr_post_fused_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, nullptr, ev,
+                                      0, a, rpb, nbx, nmisc, ntfh);
+        else hipLaunchKernelGGL(ccpr_post_fused_kernel<true>, dim3((unsigned)nb), dim3(256), 0, s, a, rpb, nbx,
+                                nmisc, ntfh);
+    } else {
+        if (ev) hipExtLaunchKernelGGL(ccpr_post_fused_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, nullptr, ev,
+                                      0, a, rpb, nbx, nmisc, ntfh);
+        else hipLaunchKernelGGL(ccpr_post_fused_kernel<false>, dim3((unsigned)nb), dim3(256), 0, s, a, rpb, nbx,
+                                nmisc, ntfh);
+    }
     return (int)hipGetLastError();
 }
 

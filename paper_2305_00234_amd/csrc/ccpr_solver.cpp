@@ -12,6 +12,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -144,6 +145,12 @@ struct ccpr_solver {
     hipStream_t stream2 = nullptr;  // second stream: CPML tiles run beside the interior ones
     bool own_stream2 = false;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr, pdone_ev = nullptr;
+    // post_ev is recorded by a step's post dispatch itself (no marker packet);
+    // post_armed: nothing has been launched since, so the next step of state
+    // post_armed_st may fork on it
+    hipEvent_t post_ev = nullptr;
+    bool post_armed = false;
+    int post_armed_st = -1;
     // split passes alternate the two streams' roles: lead2 = the step sequence
     // currently continues on stream2 (join_lead() returns it to 'stream')
     bool lead2 = false;
@@ -438,6 +445,7 @@ ccpr_status upload_rho(ccpr_solver* s)
 // (every launch outside the step loop goes to the solver's stream).
 ccpr_status join_lead(ccpr_solver* s)
 {
+    s->post_armed = false;
     if (!s->lead2) return CCPR_OK;
     HIPCHK(hipEventRecord(s->join_ev, s->stream2));
     HIPCHK(hipStreamWaitEvent(s->stream, s->join_ev, 0));
@@ -802,6 +810,7 @@ ccpr_status upload_cold(ccpr_solver* s, int st)
         HIPCHK(hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&s->pdone_ev, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&s->post_ev, hipEventDisableTiming));
     }
     // source and gap cells outside the design are finished in the same post
     // launch as the x-CPML pass of E, so they must lie outside the x layers
@@ -894,6 +903,10 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
     // satisfied (Fs on the fork event) overlaps the CPML-tile launch.
     hipStream_t Ls = s->lead2 ? s->stream2 : s->stream;
     hipStream_t Fs = s->lead2 ? s->stream : s->stream2;
+    // the last step's post dispatch records post_ev and nothing follows it on
+    // the lead stream (no pre launch either: that post applied it)
+    const bool armed = s->post_armed && s->post_armed_st == st && s->pre_done[st];
+    s->post_armed = false;
     int e = s->pre_done[st] ? 0 : ccpr_launch_pre(A, nxs, C.pw_on ? C.tf_nH : 0, Ls);
     s->pre_done[st] = false;
     if (s->batched) {
@@ -951,17 +964,21 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
             // the slower CPML tiles go first; the interior tiles fill the
             // device around them; aux waits for the CPML launch too (normally
             // long finished by then)
-            // (on a timed pass the timing events double as the fork and
-            // "CPML done" events, so timing adds one event record, not three)
-            hipEvent_t fork = tm ? s->tev[s->tev_used] : s->fork_ev;
+            // the fork is the last post dispatch's own event where it can be,
+            // and the CPML dispatch records "CPML done" itself: an event
+            // record between two kernels costs a marker packet (≈ 1 µs per
+            // step, measured); on a timed pass the timing events double as
+            // the fork and "CPML done" events
+            const bool att = !tm && !fdes;
+            hipEvent_t fork = tm ? s->tev[s->tev_used] : (armed ? s->post_ev : s->fork_ev);
             hipEvent_t pdone = tm ? s->tev[s->tev_used + 1] : s->pdone_ev;
-            if (!tm) HIPCHK(hipEventRecord(fork, Ls));
+            if (!tm && !armed) HIPCHK(hipEventRecord(fork, Ls));
             StepArgs Ad = A;
             Ad.tiles = A.tiles + nint;
             Ad.nblk = ndt;
-            e = ccpr_launch_grid(Ap, true, Ls);
+            e = ccpr_launch_grid(Ap, true, Ls, nullptr, att ? pdone : nullptr);
             if (e == 0 && fdes) e = ccpr_launch_grid_des(Ad, s->maxpairs, Ls);
-            HIPCHK(hipEventRecord(pdone, Ls));
+            if (!att) HIPCHK(hipEventRecord(pdone, Ls));
             HIPCHK(hipStreamWaitEvent(Fs, fork, 0));
             if (e == 0) e = ccpr_launch_grid(Ai, false, Fs);
             if (tm) HIPCHK(hipEventRecord(s->tev[s->tev_used + 2], Fs));
@@ -984,10 +1001,17 @@ ccpr_status launch_step(ccpr_solver* s, StepArgs& A, int st, bool fuse)
     // sequence than side by side (measured)
     if (e == 0 && !fdes) e = ccpr_launch_aux(A, s->maxpairs, ndes, s->edge, As);
     fuse = fuse && s->fuse_ok[st];
+    const bool watch = s->watch_run && s->watch_every > 0 && s->has_obj && (A.n + 1) % s->watch_every == 0;
+    // the next step of this state follows at once: its fork is this dispatch
+    const bool arm = fuse && !watch && s->post_ev;
     if (e == 0)
-        e = fuse ? ccpr_launch_post_fused(A, nmisc, C.pw_on ? C.tf_nH : 0, As)
+        e = fuse ? ccpr_launch_post_fused(A, nmisc, C.pw_on ? C.tf_nH : 0, As, arm ? s->post_ev : nullptr)
                  : ccpr_launch_post(A, nxs, nmisc, As);
-    if (e == 0 && s->watch_run && s->watch_every > 0 && s->has_obj && (A.n + 1) % s->watch_every == 0)
+    if (e == 0 && arm) {
+        s->post_armed = true;
+        s->post_armed_st = st;
+    }
+    if (e == 0 && watch)
         e = ccpr_launch_watch(A, s->glo, s->gdim, (float)s->watch_limit, A.n, wsp<unsigned>(s, s->lay.halt),
                               wsp<double>(s, s->lay.scal), As);
     if (e != 0) return fail(s, CCPR_EDEVICE, "step kernel launch: %s", hipGetErrorString((hipError_t)e));
@@ -1442,6 +1466,7 @@ void ccpr_destroy(ccpr_solver* s)
     if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
     if (s->join_ev) (void)hipEventDestroy(s->join_ev);
     if (s->pdone_ev) (void)hipEventDestroy(s->pdone_ev);
+    if (s->post_ev) (void)hipEventDestroy(s->post_ev);
     if (s->stream2 && s->own_stream2) (void)hipStreamDestroy(s->stream2);
     delete s;
 }
@@ -2241,6 +2266,7 @@ void ccpr_pipe_unbind(ccpr_solver* s)
     s->have_forward = s->have_adjoint = false;
     s->rho_uploaded = false;
     s->lead2 = false;  // (the engine unbinds after the solve's work completed)
+    s->post_armed = false;
     s->pre_done[0] = s->pre_done[1] = false;
     s->batched = false;
     s->rec_pending = false;
