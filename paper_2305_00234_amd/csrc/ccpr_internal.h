@@ -207,7 +207,8 @@ __host__ __device__ inline long long slab_size(int a, int nx, int ny, int nz, in
 }
 
 // Launchers (ccpr_kernels.hip)
-// fused grid step over the tiles of a.tiles (pml: the CPML variant)
+// fused grid step over the tiles of a.tiles (pml: the CPML variant); events
+// given are recorded by the dispatch itself (on the stream when no tiles)
 int ccpr_launch_grid(const StepArgs& a, bool pml, void* stream, void* start_event = nullptr,
                      void* stop_event = nullptr);
 // interior tiles that own design cells, with the design update fused in
@@ -223,7 +224,7 @@ int ccpr_launch_pre(const StepArgs& a, long long nxs, long long ntf, void* strea
 int ccpr_launch_post(const StepArgs& a, long long nxs, long long nmisc, void* stream);
 // after the aux kernel when the next step follows at once: the post work of
 // step n and the pre work of step n+1 (ntfh TF/SF H words) in one launch
-// (2 npml <= 256)
+// (2 npml <= 256); stop_event, if given, is recorded by the dispatch itself
 int ccpr_launch_post_fused(const StepArgs& a, long long nmisc, long long ntfh, void* stream,
                            void* stop_event = nullptr);
 // the recorded steps st[0..k) (1 <= k <= CCPR_BATCH_MAX, same nxp, 2 rows per
